@@ -1,0 +1,180 @@
+/*
+ * xorsat.h -- C ABI of the MI355X quasi-greedy many-clone 3-XORSAT solver.
+ *
+ * Paper: Bernaschi et al., "How we are leading a 3-XORSAT challenge: from the energy landscape
+ * to the algorithm and its efficient implementation on GPUs" (arXiv 2102.09510).
+ *
+ * The library runs the paper's quasi-greedy (QG) single-spin-flip dynamics on many clones of
+ * one instance of H = -sum_t J_t s_a s_b s_c (Eq. (1); the paper has J_t = +1), 64 clones per
+ * 64-bit word, on an AMD gfx950 GPU. All arithmetic is integer and bit-exact: for the same
+ * instance, seed and configuration every result is reproducible to the bit, whatever tiling,
+ * batching or serving mode produced it.
+ *
+ * Conventions
+ *   - Every call returns xs_status; XS_OK is 0. No exception crosses the ABI. On an error
+ *     xs_last_error() returns a message for the calling thread.
+ *   - Spins: s = +1 or -1. Bits: x = 1 <=> s = -1. Clone c lives in bit (c & 63) of 64-bit word
+ *     (c >> 6); the 32 clones c with the same c >> 5 form a "group" that shares every random
+ *     number (Section "Basic information about the GPU implementation": one random number per
+ *     32-clone word).
+ *   - Device pointers are plain HIP device addresses (for example torch's data_ptr()). The
+ *     stream argument is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Structs that may grow carry struct_size; set it to sizeof(the struct).
+ */
+#ifndef XORSAT_H
+#define XORSAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XS_ABI_VERSION 1
+
+typedef int32_t xs_status;
+#define XS_OK 0
+#define XS_EINVAL 1      /* an argument or an instance breaks a stated rule */
+#define XS_ENOMEM 2      /* host or device allocation failed */
+#define XS_EDEVICE 3     /* a HIP call failed (the message names it) */
+#define XS_EAGAIN 4      /* the server cannot admit the request now */
+#define XS_ENOTFOUND 5   /* unknown ticket */
+#define XS_ECANCELED 6   /* the request was cancelled */
+
+/* Largest supported instance: the per-workgroup tables keep LDS byte offsets in 16 bits. */
+#define XS_MAX_N 2048
+/* Clone counts are multiples of this (one random-number block: 8 groups of 32 clones). */
+#define XS_CLONE_QUANTUM 256
+
+/* Run flags (xs_run_config.flags). */
+#define XS_STOP_ON_FIRST 0x1u /* stop after the first chunk in which some clone reached E = -N */
+#define XS_RESUME 0x2u        /* state already holds the start configuration (checkpoint)     */
+
+typedef struct xs_instance xs_instance;
+
+/* ABI version the library was built with (XS_ABI_VERSION). */
+int32_t xs_abi_version(void);
+/* Name of a status code ("XS_EINVAL", ...). Static storage. */
+const char *xs_status_str(xs_status status);
+/* Message of the last failed call on this thread ("" if none). Valid until the next call. */
+const char *xs_last_error(void);
+
+/*
+ * Load an instance (Section "The model and its energy landscape"): n spins, m = n triplets,
+ * tri[3*t .. 3*t+2] the 0-based spins of triplet t, J[t] = +1 or -1 its coupling. Every spin
+ * must appear in exactly three triplets, the three spins of a triplet must differ, and
+ * 4 <= n <= XS_MAX_N; otherwise XS_EINVAL. Repeated triplets are allowed (each is counted).
+ * The spins are partitioned once, on the host, into independent sets of at most colour_cap
+ * spins (Supplementary Material, "Details on the GPU implementation": greedy repeated scans,
+ * sets of 32 were best; 0 selects 32). The partition fixes the update order and therefore the
+ * trajectories, so it is part of the instance. The library copies tri and J; the caller keeps
+ * ownership of its arrays. Device tables are uploaded on first use.
+ */
+xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int8_t *J,
+                             int32_t colour_cap, xs_instance **out);
+void xs_instance_destroy(xs_instance *inst);
+
+typedef struct {
+    int32_t n;          /* spins (= triplets) */
+    int32_t n_classes;  /* independent sets in the partition */
+    int32_t colour_cap; /* largest allowed set */
+    int32_t max_class;  /* largest actual set */
+} xs_instance_info;
+
+xs_status xs_instance_get_info(const xs_instance *inst, xs_instance_info *info);
+/* The update order: perm[n] (spins set by set) and class_off[n_classes + 1] (set k holds
+ * positions class_off[k] .. class_off[k+1]-1). Host arrays owned by the caller. */
+xs_status xs_instance_get_partition(const xs_instance *inst, int32_t *perm, int32_t *class_off);
+
+/*
+ * Run configuration. The dynamics (Section "The quasi-greedy algorithm"): a sweep visits the
+ * spins set by set in partition order; a spin in k unsatisfied triplets flips with
+ * probability w_k, w0 = 0, w2 = w3 = 1, and w1 = accept_thr / 65536 (the paper uses
+ * w1 = 0.055, accept_thr = 3604). The k = 1 test compares a 16-bit draw d with accept_thr.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed low, seed high):
+ *   start bit of spin i, clone c: bit (c & 31) of philox(i, 0xFFFFFFFF, g >> 2, id)[g & 3];
+ *   draw of spin i, sweep t, group g = c >> 5:
+ *       (philox(i, t, g >> 3, id)[(g & 7) >> 1] >> (16 * (g & 1))) & 0xFFFF.
+ */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t instance_id;  /* part of every random counter; keeps instances independent */
+    uint64_t seed;         /* Philox key */
+    uint32_t n_clones;     /* > 0, multiple of XS_CLONE_QUANTUM */
+    uint32_t accept_thr;   /* 0 .. 65536 */
+    uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME */
+    uint32_t max_sweeps;   /* sweep budget of this call (0 = only check the start state) */
+    uint32_t start_sweep;  /* absolute index of the first sweep (for resumed runs) */
+    uint32_t chunk_sweeps; /* sweeps between stop checks, K (0 = 100, as in the paper) */
+    uint32_t tile_blocks;  /* clone blocks of 256 per workgroup; 0 = chosen by the library.
+                              Changes speed only, never results. */
+} xs_run_config;
+
+/*
+ * Caller-owned buffers of one run.
+ *   state      device, uint64 [n][n_clones / 64] (spin-major): bit b of state[i*W + w] is x_i of
+ *              clone 64*w + b. Written with the start configuration unless XS_RESUME; holds the
+ *              configuration at the end sweep on return. Required.
+ *   first_hit  device, int32 [n_clones]: smallest sweep index t in [start_sweep, end_sweep] at
+ *              which the clone's configuration (before sweep t) has E = -N, else -1. Required.
+ *   energy     device, int32 [n_clones] or NULL: E = 2U - N at the end sweep.
+ *   solved     host, int8 [n] or NULL: spins (+1/-1) of the winning clone (unchanged if none).
+ */
+typedef struct {
+    uint64_t *state;
+    int32_t *first_hit;
+    int32_t *energy;
+    int8_t *solved;
+} xs_run_buffers;
+
+typedef struct {
+    int64_t tts_sweeps;          /* min over clones of first_hit (Section "Numerical results":
+                                    a run's TTS is its fastest clone), -1 if none */
+    int32_t winner_clone;        /* lowest clone index attaining tts_sweeps, -1 if none */
+    uint32_t end_sweep;          /* absolute sweep index at which the run stopped */
+    uint32_t sweeps_done;        /* end_sweep - start_sweep */
+    uint32_t tile_blocks;        /* tiling used (result-neutral) */
+    uint64_t clone_spin_updates; /* n_clones * n * sweeps_done */
+    double seconds;              /* wall time of the call */
+} xs_run_result;
+
+/*
+ * Run one instance: draw the start configuration (unless XS_RESUME), then sweep in chunks of
+ * chunk_sweeps until max_sweeps are done or, with XS_STOP_ON_FIRST, until the end of the first
+ * chunk in which some clone reached E = -N. With w0 = 0 a ground state is never left
+ * (Section "The quasi-greedy algorithm", property (iii)), so the exact first sweep of every
+ * clone is known and the chunk length changes only end_sweep, never first hits, TTS, winner
+ * or solved configuration. Work is ordered on `stream`; the call returns after it finished.
+ * XS_EINVAL for bad sizes, XS_EDEVICE for a HIP failure.
+ */
+xs_status xs_run(const xs_instance *inst, const xs_run_config *cfg, const xs_run_buffers *bufs,
+                 void *stream, xs_run_result *result);
+
+/*
+ * Run `count` instances together (uneven sizes allowed): every chunk is one launch over the
+ * workgroup tiles of all unfinished instances. Each instance's results are identical to
+ * xs_run with the same instance, configuration and buffers. Buffers must not overlap.
+ */
+xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
+                       const xs_run_buffers *bufs, void *stream, xs_run_result *results);
+
+/*
+ * Launch timing of the sweep kernel, for measurement tools. When enabled, the library records
+ * a pair of HIP events on the run's stream around every sweep-chunk launch and adds the
+ * elapsed times once the run has synchronised. Counters are process-wide.
+ */
+typedef struct {
+    uint64_t launches;           /* sweep-chunk launches timed */
+    double total_ms;             /* sum of their durations */
+    uint64_t clone_spin_updates; /* updates those launches performed */
+} xs_kernel_stats;
+
+xs_status xs_profile_enable(int32_t on);
+/* Copy the counters; reset them to zero if reset != 0. */
+xs_status xs_profile_read(xs_kernel_stats *out, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XORSAT_H */

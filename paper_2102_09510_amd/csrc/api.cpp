@@ -1,0 +1,474 @@
+// Host runtime of the C ABI declared in include/xorsat.h: instance validation, the greedy
+// independent-set partition, device tables, and the chunked run driver (single and batched).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/xorsat.h"
+#include "xs_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+xs_status fail(xs_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define XS_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(XS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+struct ProfileState {
+    std::mutex mu;
+    bool on = false;
+    xs_kernel_stats stats{};
+};
+ProfileState g_prof;
+
+struct DeviceTables {
+    uint4 *rec = nullptr;
+    int32_t *class_off = nullptr;
+    uint2 *tri = nullptr;
+};
+
+}  // namespace
+
+struct xs_instance {
+    int32_t n = 0;
+    int32_t cap = 32;
+    std::vector<int32_t> tri;        // [n][3]
+    std::vector<int8_t> J;           // [n]
+    std::vector<int32_t> perm;       // update order
+    std::vector<int32_t> class_off;  // [n_classes + 1]
+    std::vector<uint16_t> rec;       // [n][8] in update order
+    std::vector<uint16_t> tri16;     // [n][4]: a, b, c, j
+    int32_t max_class = 0;
+    std::mutex mu;
+    std::map<int, DeviceTables> dev;  // per HIP device
+};
+
+namespace {
+
+// Greedy partition into independent sets of at most `cap` spins: repeated ascending scans; a
+// scan adds an unassigned spin unless the set is full or the spin shares a triplet with a spin
+// the scan already added. The "blocked" stamps mark the neighbours of the current set.
+void partition(xs_instance &I) {
+    const int n = I.n;
+    std::vector<std::vector<int32_t>> nbr(n);
+    for (int t = 0; t < n; ++t)
+        for (int q = 0; q < 3; ++q)
+            for (int r = 0; r < 3; ++r)
+                if (q != r) nbr[I.tri[3 * t + q]].push_back(I.tri[3 * t + r]);
+    std::vector<char> assigned(n, 0);
+    std::vector<int32_t> blocked(n, -1);
+    I.perm.clear();
+    I.class_off.assign(1, 0);
+    I.max_class = 0;
+    int pass = 0;
+    while ((int)I.perm.size() < n) {
+        int size = 0;
+        for (int v = 0; v < n && size < I.cap; ++v) {
+            if (assigned[v] || blocked[v] == pass) continue;
+            assigned[v] = 1;
+            I.perm.push_back(v);
+            ++size;
+            for (int32_t u : nbr[v]) blocked[u] = pass;
+        }
+        I.class_off.push_back((int32_t)I.perm.size());
+        I.max_class = std::max(I.max_class, size);
+        ++pass;
+    }
+}
+
+// Records in update order: spin, then for each of its three triplets (ascending triplet index)
+// the two other spins, then the three coupling bits (bit q: triplet q has J = -1).
+void build_records(xs_instance &I) {
+    const int n = I.n;
+    std::vector<int32_t> inc(3 * n), deg(n, 0);
+    for (int t = 0; t < n; ++t)
+        for (int q = 0; q < 3; ++q) {
+            const int v = I.tri[3 * t + q];
+            inc[3 * v + deg[v]++] = t;
+        }
+    I.rec.assign(8 * (size_t)n, 0);
+    for (int p = 0; p < n; ++p) {
+        const int i = I.perm[p];
+        uint16_t *r = &I.rec[8 * (size_t)p];
+        r[0] = (uint16_t)i;
+        uint16_t jbits = 0;
+        for (int q = 0; q < 3; ++q) {
+            const int t = inc[3 * i + q];
+            int other[2], k = 0;
+            for (int z = 0; z < 3; ++z)
+                if (I.tri[3 * t + z] != i) other[k++] = I.tri[3 * t + z];
+            r[1 + 2 * q] = (uint16_t)other[0];
+            r[2 + 2 * q] = (uint16_t)other[1];
+            if (I.J[t] < 0) jbits |= (uint16_t)(1u << q);
+        }
+        r[7] = jbits;
+    }
+    I.tri16.assign(4 * (size_t)n, 0);
+    for (int t = 0; t < n; ++t) {
+        for (int q = 0; q < 3; ++q) I.tri16[4 * t + q] = (uint16_t)I.tri[3 * t + q];
+        I.tri16[4 * t + 3] = I.J[t] < 0 ? 1 : 0;
+    }
+}
+
+xs_status ensure_tables(xs_instance *I, int device, DeviceTables *out) {
+    std::lock_guard<std::mutex> lock(I->mu);
+    auto it = I->dev.find(device);
+    if (it != I->dev.end()) {
+        *out = it->second;
+        return XS_OK;
+    }
+    DeviceTables t;
+    const size_t n = (size_t)I->n;
+    XS_HIP(hipMalloc(&t.rec, 16 * n));
+    XS_HIP(hipMalloc(&t.class_off, sizeof(int32_t) * I->class_off.size()));
+    XS_HIP(hipMalloc(&t.tri, 8 * n));
+    XS_HIP(hipMemcpy(t.rec, I->rec.data(), 16 * n, hipMemcpyHostToDevice));
+    XS_HIP(hipMemcpy(t.class_off, I->class_off.data(), sizeof(int32_t) * I->class_off.size(),
+                     hipMemcpyHostToDevice));
+    XS_HIP(hipMemcpy(t.tri, I->tri16.data(), 8 * n, hipMemcpyHostToDevice));
+    I->dev[device] = t;
+    *out = t;
+    return XS_OK;
+}
+
+uint32_t ilog2(uint32_t v) {
+    uint32_t r = 0;
+    while ((1u << (r + 1)) <= v) ++r;
+    return r;
+}
+
+// Largest power-of-two tile (in 256-clone blocks) that divides the clone count, keeps LDS byte
+// offsets in 16 bits (n * B <= 2048) and keeps the tile within `max_b`.
+uint32_t auto_tile_blocks(uint32_t n, uint32_t n_blocks, uint32_t max_b) {
+    uint32_t B = 1;
+    while (B * 2 <= max_b && n_blocks % (B * 2) == 0 && n * (B * 2) <= 2048 &&
+           B * 2 <= (uint32_t)xs::kMaxTileBlocks)
+        B *= 2;
+    return B;
+}
+
+xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b) {
+    if (!I || !cfg || !b) return fail(XS_EINVAL, "null argument");
+    if (cfg->struct_size < sizeof(xs_run_config))
+        return fail(XS_EINVAL, "xs_run_config.struct_size %u < %zu", cfg->struct_size,
+                    sizeof(xs_run_config));
+    if (cfg->n_clones == 0 || cfg->n_clones % XS_CLONE_QUANTUM != 0)
+        return fail(XS_EINVAL, "n_clones %u is not a positive multiple of %d", cfg->n_clones,
+                    XS_CLONE_QUANTUM);
+    if (cfg->accept_thr > 65536) return fail(XS_EINVAL, "accept_thr %u > 65536", cfg->accept_thr);
+    if (cfg->flags & ~(XS_STOP_ON_FIRST | XS_RESUME))
+        return fail(XS_EINVAL, "unknown flags 0x%x", cfg->flags);
+    if ((uint64_t)cfg->start_sweep + cfg->max_sweeps >= 0xFFFFFFFFull)
+        return fail(XS_EINVAL, "start_sweep + max_sweeps must stay below 2^32 - 1");
+    if (!b->state || !b->first_hit) return fail(XS_EINVAL, "state and first_hit are required");
+    if (((uintptr_t)b->state & 15) != 0) return fail(XS_EINVAL, "state must be 16-byte aligned");
+    const uint32_t nb = cfg->n_clones / 256;
+    if (cfg->tile_blocks) {
+        const uint32_t B = cfg->tile_blocks;
+        if ((B & (B - 1)) || B > (uint32_t)xs::kMaxTileBlocks || nb % B ||
+            (uint32_t)I->n * B > 2048)
+            return fail(XS_EINVAL,
+                        "tile_blocks %u must be a power of two <= %d dividing n_clones/256 with "
+                        "n * tile_blocks <= 2048",
+                        B, xs::kMaxTileBlocks);
+    }
+    return XS_OK;
+}
+
+xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
+                    const xs_run_buffers *bufs, hipStream_t stream, xs_run_result *results) {
+    const auto wall0 = std::chrono::steady_clock::now();
+    if (count <= 0 || !insts || !cfgs || !bufs || !results)
+        return fail(XS_EINVAL, "empty or null batch");
+    int device = 0;
+    XS_HIP(hipGetDevice(&device));
+
+    std::vector<xs::InstDev> h(count);
+    std::vector<uint2> tiles;
+    size_t lds = 0;
+    for (int k = 0; k < count; ++k) {
+        const xs_instance *I = insts[k];
+        const xs_run_config &c = cfgs[k];
+        xs_status st = validate_run(I, &c, &bufs[k]);
+        if (st != XS_OK) return st;
+        DeviceTables t;
+        st = ensure_tables(const_cast<xs_instance *>(I), device, &t);
+        if (st != XS_OK) return st;
+        const uint32_t nb = c.n_clones / 256;
+        const uint32_t B = c.tile_blocks ? c.tile_blocks : auto_tile_blocks(I->n, nb, 8);
+        xs::InstDev &d = h[k];
+        std::memset(&d, 0, sizeof d);
+        d.rec = t.rec;
+        d.class_off = t.class_off;
+        d.tri = t.tri;
+        d.state = bufs[k].state;
+        d.first_hit = bufs[k].first_hit;
+        d.energy = bufs[k].energy;
+        d.n = (uint32_t)I->n;
+        d.n_words = c.n_clones / 64;
+        d.n_classes = (uint32_t)I->class_off.size() - 1;
+        d.tile_blocks = B;
+        d.log2_tile_blocks = ilog2(B);
+        d.inst_id = c.instance_id;
+        d.thr = c.accept_thr;
+        d.seed_lo = (uint32_t)c.seed;
+        d.seed_hi = (uint32_t)(c.seed >> 32);
+        d.flags = c.flags;
+        d.t_start = c.start_sweep;
+        d.t_stop = c.start_sweep + c.max_sweeps;
+        d.chunk = c.chunk_sweeps ? c.chunk_sweeps : 100;
+        d.t_cur = c.start_sweep;
+        d.done = c.max_sweeps == 0 ? 1u : 0u;
+        d.hit = 0;
+        d.tts = INT32_MAX;
+        d.winner = INT32_MAX;
+        for (uint32_t b0 = 0; b0 < nb; b0 += B) tiles.push_back(make_uint2((uint32_t)k, b0));
+        lds = std::max(lds, xs::chunk_lds_bytes(d.n, B));
+    }
+
+    // Per-call device scratch: descriptors, tiles, the running-instance counter and the
+    // winners' spins.
+    size_t solved_bytes = 0;
+    std::vector<size_t> solved_off(count);
+    for (int k = 0; k < count; ++k) {
+        solved_off[k] = solved_bytes;
+        solved_bytes += (h[k].n + 15) & ~15u;
+    }
+    const size_t off_tiles = (sizeof(xs::InstDev) * count + 255) & ~size_t(255);
+    const size_t off_active = off_tiles + ((sizeof(uint2) * tiles.size() + 255) & ~size_t(255));
+    const size_t off_solved = off_active + 256;
+    const size_t total = off_solved + solved_bytes;
+    uint8_t *scratch = nullptr;
+    XS_HIP(hipMalloc(&scratch, total));
+    struct Free {
+        uint8_t *p;
+        ~Free() { if (p) (void)hipFree(p); }
+    } guard{scratch};
+    for (int k = 0; k < count; ++k)
+        h[k].solved = reinterpret_cast<int8_t *>(scratch + off_solved + solved_off[k]);
+    xs::InstDev *d_inst = reinterpret_cast<xs::InstDev *>(scratch);
+    uint2 *d_tiles = reinterpret_cast<uint2 *>(scratch + off_tiles);
+    uint32_t *d_active = reinterpret_cast<uint32_t *>(scratch + off_active);
+
+    XS_HIP(hipMemcpyAsync(d_inst, h.data(), sizeof(xs::InstDev) * count, hipMemcpyHostToDevice,
+                          stream));
+    XS_HIP(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(uint2) * tiles.size(),
+                          hipMemcpyHostToDevice, stream));
+    for (int k = 0; k < count; ++k) XS_HIP(xs::launch_init(d_inst + k, h[k], stream));
+
+    bool any_running = false;
+    for (int k = 0; k < count; ++k) any_running |= !h[k].done;
+    // Chunk loop: a chunk launch over all tiles, then the device-side decision. The host reads
+    // the count of running instances every `group` chunks (finished instances' tiles exit at
+    // once, so launching ahead changes no result).
+    int group = 1;
+    bool profile;
+    {
+        std::lock_guard<std::mutex> lock(g_prof.mu);
+        profile = g_prof.on;
+    }
+    std::vector<hipEvent_t> ev;
+    struct Events {
+        std::vector<hipEvent_t> *v;
+        ~Events() { for (auto e : *v) (void)hipEventDestroy(e); }
+    } ev_guard{&ev};
+    xs_kernel_stats local{};
+    // Active instances' updates per chunk are accounted from the sweep counters afterwards.
+    while (any_running) {
+        const auto c0 = std::chrono::steady_clock::now();
+        if (profile)
+            while (ev.size() < 2 * (size_t)group) {
+                hipEvent_t e;
+                XS_HIP(hipEventCreate(&e));
+                ev.push_back(e);
+            }
+        for (int g = 0; g < group; ++g) {
+            if (profile) XS_HIP(hipEventRecord(ev[2 * g], stream));
+            XS_HIP(xs::launch_chunk(d_inst, d_tiles, (int)tiles.size(), lds, stream));
+            if (profile) XS_HIP(hipEventRecord(ev[2 * g + 1], stream));
+            XS_HIP(xs::launch_decide(d_inst, count, d_active, stream));
+        }
+        uint32_t active = 0;
+        XS_HIP(hipMemcpyAsync(&active, d_active, sizeof active, hipMemcpyDeviceToHost, stream));
+        XS_HIP(hipStreamSynchronize(stream));
+        any_running = active != 0;
+        if (profile)
+            for (int g = 0; g < group; ++g) {
+                float ms = 0.f;
+                XS_HIP(hipEventElapsedTime(&ms, ev[2 * g], ev[2 * g + 1]));
+                local.total_ms += ms;
+                local.launches += 1;
+            }
+        const double ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0)
+                .count();
+        if (ms < 2.0 * group && group < 64) group *= 2;
+    }
+    for (int k = 0; k < count; ++k) XS_HIP(xs::launch_final(d_inst + k, h[k], stream));
+    std::vector<xs::InstDev> out(count);
+    XS_HIP(hipMemcpyAsync(out.data(), d_inst, sizeof(xs::InstDev) * count, hipMemcpyDeviceToHost,
+                          stream));
+    std::vector<int8_t> solved(solved_bytes);
+    if (solved_bytes)
+        XS_HIP(hipMemcpyAsync(solved.data(), scratch + off_solved, solved_bytes,
+                              hipMemcpyDeviceToHost, stream));
+    XS_HIP(hipStreamSynchronize(stream));
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+    for (int k = 0; k < count; ++k) {
+        const xs::InstDev &d = out[k];
+        xs_run_result &r = results[k];
+        r.tts_sweeps = d.tts == INT32_MAX ? -1 : d.tts;
+        r.winner_clone = d.winner == INT32_MAX ? -1 : d.winner;
+        r.end_sweep = d.t_cur;
+        r.sweeps_done = d.t_cur - d.t_start;
+        r.tile_blocks = d.tile_blocks;
+        r.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * r.sweeps_done;
+        r.seconds = secs;
+        if (bufs[k].solved && d.winner != INT32_MAX)
+            std::memcpy(bufs[k].solved, solved.data() + solved_off[k], d.n);
+        local.clone_spin_updates += r.clone_spin_updates;
+    }
+    if (profile) {
+        std::lock_guard<std::mutex> lock(g_prof.mu);
+        g_prof.stats.launches += local.launches;
+        g_prof.stats.total_ms += local.total_ms;
+        g_prof.stats.clone_spin_updates += local.clone_spin_updates;
+    }
+    return XS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t xs_abi_version(void) { return XS_ABI_VERSION; }
+
+const char *xs_status_str(xs_status s) {
+    switch (s) {
+        case XS_OK: return "XS_OK";
+        case XS_EINVAL: return "XS_EINVAL";
+        case XS_ENOMEM: return "XS_ENOMEM";
+        case XS_EDEVICE: return "XS_EDEVICE";
+        case XS_EAGAIN: return "XS_EAGAIN";
+        case XS_ENOTFOUND: return "XS_ENOTFOUND";
+        case XS_ECANCELED: return "XS_ECANCELED";
+        default: return "XS_UNKNOWN";
+    }
+}
+
+const char *xs_last_error(void) { return g_last_error.c_str(); }
+
+xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int8_t *J,
+                             int32_t colour_cap, xs_instance **out) {
+    if (!out) return fail(XS_EINVAL, "out is null");
+    *out = nullptr;
+    if (!tri || !J) return fail(XS_EINVAL, "tri and J are required");
+    if (n < 4 || n > XS_MAX_N) return fail(XS_EINVAL, "n = %d outside [4, %d]", n, XS_MAX_N);
+    if (m != n) return fail(XS_EINVAL, "m = %d must equal n = %d", m, n);
+    if (colour_cap < 0 || colour_cap > XS_MAX_N)
+        return fail(XS_EINVAL, "colour_cap = %d outside [0, %d]", colour_cap, XS_MAX_N);
+    std::vector<int32_t> deg(n, 0);
+    for (int t = 0; t < m; ++t) {
+        const int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+        if (a < 0 || a >= n || b < 0 || b >= n || c < 0 || c >= n)
+            return fail(XS_EINVAL, "triplet %d has an index outside [0, %d)", t, n);
+        if (a == b || a == c || b == c)
+            return fail(XS_EINVAL, "triplet %d repeats a spin", t);
+        if (J[t] != 1 && J[t] != -1) return fail(XS_EINVAL, "J[%d] = %d is not +1/-1", t, J[t]);
+        ++deg[a];
+        ++deg[b];
+        ++deg[c];
+    }
+    for (int v = 0; v < n; ++v)
+        if (deg[v] != 3) return fail(XS_EINVAL, "spin %d is in %d triplets, not 3", v, deg[v]);
+    xs_instance *I = new (std::nothrow) xs_instance;
+    if (!I) return fail(XS_ENOMEM, "host allocation failed");
+    I->n = n;
+    I->cap = colour_cap ? colour_cap : 32;
+    I->tri.assign(tri, tri + 3 * (size_t)m);
+    I->J.assign(J, J + m);
+    partition(*I);
+    build_records(*I);
+    *out = I;
+    return XS_OK;
+}
+
+void xs_instance_destroy(xs_instance *I) {
+    if (!I) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : I->dev) {
+        (void)hipSetDevice(kv.first);
+        (void)hipFree(kv.second.rec);
+        (void)hipFree(kv.second.class_off);
+        (void)hipFree(kv.second.tri);
+    }
+    if (cur >= 0 && !I->dev.empty()) (void)hipSetDevice(cur);
+    delete I;
+}
+
+xs_status xs_instance_get_info(const xs_instance *I, xs_instance_info *info) {
+    if (!I || !info) return fail(XS_EINVAL, "null argument");
+    info->n = I->n;
+    info->n_classes = (int32_t)I->class_off.size() - 1;
+    info->colour_cap = I->cap;
+    info->max_class = I->max_class;
+    return XS_OK;
+}
+
+xs_status xs_instance_get_partition(const xs_instance *I, int32_t *perm, int32_t *class_off) {
+    if (!I || !perm || !class_off) return fail(XS_EINVAL, "null argument");
+    std::memcpy(perm, I->perm.data(), sizeof(int32_t) * I->perm.size());
+    std::memcpy(class_off, I->class_off.data(), sizeof(int32_t) * I->class_off.size());
+    return XS_OK;
+}
+
+xs_status xs_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    g_prof.on = on != 0;
+    return XS_OK;
+}
+
+xs_status xs_profile_read(xs_kernel_stats *out, int32_t reset) {
+    if (!out) return fail(XS_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    *out = g_prof.stats;
+    if (reset) g_prof.stats = xs_kernel_stats{};
+    return XS_OK;
+}
+
+xs_status xs_run(const xs_instance *inst, const xs_run_config *cfg, const xs_run_buffers *bufs,
+                 void *stream, xs_run_result *result) {
+    return run_batch(1, &inst, cfg, bufs, reinterpret_cast<hipStream_t>(stream), result);
+}
+
+xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
+                       const xs_run_buffers *bufs, void *stream, xs_run_result *results) {
+    return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results);
+}
+
+}  // extern "C"

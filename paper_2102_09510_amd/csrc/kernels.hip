@@ -1,0 +1,395 @@
+// HIP kernels (gfx950) of the quasi-greedy many-clone dynamics.
+//
+// Paper: Bernaschi et al., arXiv 2102.09510. Section "The quasi-greedy algorithm" gives the
+// rule (w0 = 0, w1, w2 = w3 = 1); Section "Basic information about the GPU implementation" the
+// multispin coding (one random number per 32-clone word); the Supplementary Material the
+// independent-set schedule, the LDS-resident state and the many sweeps per launch.
+//
+// Data layout
+//   global state   uint64 [n][W] spin-major, W = n_clones / 64 (bit = clone).
+//   tile           B consecutive 256-clone blocks of one instance (4*B words per spin row),
+//                  owned by one workgroup for a whole chunk of sweeps.
+//   LDS            rec  [n]      16-byte records in update order, u16 fields: byte offsets of
+//                               the spin's own row and of the two other spins of each of its
+//                               three triplets, then meta = i | jbits << 13;
+//                  state [n][32*B] the tile's rows;
+//                  rbits [n][B]  k = 1 acceptance bits of the current sweep, one byte per
+//                               (position, block): bit k belongs to group k of the block;
+//                  acc   [8*B]   per-group OR of "some triplet of the visited spin is
+//                               unsatisfied" over the current sweep.
+//   task           one spin of the current class x 16 bytes of its row (2 words, 4 groups,
+//                  128 clones). Consecutive threads take consecutive 16-byte columns of the
+//                  same row, so a wave reads contiguous LDS runs.
+//
+// Per update, with p_t = x_a ^ x_b ^ j_t the value that satisfies triplet t of spin x:
+//   k = #{t : x != p_t};  m = majority(p1, p2, p3) is the new spin when k != 1 (k = 0 keeps
+//   x = m, k >= 2 flips to m = ~x); k == 1 <=> (x ^ p1 ^ p2 ^ p3) & ~(x ^ m); then the spin
+//   flips iff the group's acceptance bit is set. All of it is bitwise over 32 clones.
+//
+// Ground-state detection (exact first hit): during the sweep that starts from C_t the OR of
+// (k >= 1) over all visited spins is zero iff C_t has E = -N. If C_t has an unsatisfied triplet,
+// the first visited spin of any unsatisfied triplet still sees it (every spin before it had
+// k = 0 and kept its value), so the OR is one; if C_t is a ground state nothing moves.
+#include "xs_internal.h"
+
+#include "../../include/xorsat.h"
+
+namespace xs {
+namespace {
+
+// Three-input logic in one gfx950 instruction: result bit = lut[(a << 2) | (b << 1) | c], so a
+// LUT is the function evaluated on the bit patterns a = 0xF0, b = 0xCC, c = 0xAA.
+constexpr uint32_t kA = 0xF0, kB = 0xCC, kC = 0xAA;
+constexpr uint32_t kXor3 = (kA ^ kB ^ kC) & 0xFF;
+constexpr uint32_t kMaj3 = ((kA & kB) | (kA & kC) | (kB & kC)) & 0xFF;
+constexpr uint32_t kOr3 = (kA | kB | kC) & 0xFF;
+constexpr uint32_t kXorAndNot = ((kA ^ kB) & ~kC) & 0xFF;  // (a ^ b) & ~c
+constexpr uint32_t kXorAnd = (kA ^ (kB & kC)) & 0xFF;      // a ^ (b & c)
+
+template <uint32_t LUT>
+__device__ __forceinline__ uint32_t lop3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, LUT);
+}
+
+// Philox4x32-10 bijection (Salmon, Moraes, Dror, Shaw, SC'11): per round two 32x32->64
+// products; high halves mixed with the other counter words and the round key, low halves
+// passed on; key bumped by the Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4(lop3<kXor3>((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                       lop3<kXor3>((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t below(uint32_t v, uint32_t thr) { return v < thr ? 1u : 0u; }
+
+// One 32-clone word of one spin: nine three-input operations.
+__device__ __forceinline__ uint32_t qg_word(uint32_t x, uint32_t a1, uint32_t b1, uint32_t a2,
+                                            uint32_t b2, uint32_t a3, uint32_t b3, uint32_t j1,
+                                            uint32_t j2, uint32_t j3, uint32_t accept,
+                                            uint32_t &acc) {
+    const uint32_t p1 = lop3<kXor3>(a1, b1, j1);
+    const uint32_t p2 = lop3<kXor3>(a2, b2, j2);
+    const uint32_t p3 = lop3<kXor3>(a3, b3, j3);
+    const uint32_t m = lop3<kMaj3>(p1, p2, p3);     // new spin unless k == 1
+    const uint32_t par = lop3<kXor3>(p1, p2, p3);
+    const uint32_t dmaj = x ^ m;                     // k >= 2
+    const uint32_t k1 = lop3<kXorAndNot>(x, par, dmaj);  // k == 1
+    acc = lop3<kOr3>(acc, k1, dmaj);                 // k >= 1
+    return lop3<kXorAnd>(m, k1, accept);
+}
+
+__device__ __forceinline__ uint4 lds_ld16(const uint8_t *base, uint32_t off) {
+    return *reinterpret_cast<const uint4 *>(base + off);
+}
+
+constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+__host__ __device__ constexpr size_t lds_rec_bytes(uint32_t n) { return size_t(16) * n; }
+
+// ------------------------------------------------------------------------------ init
+
+// Start configuration: the 32 clones of group g of spin i take the bits of
+// philox(i, 0xFFFFFFFF, g >> 2, id)[g & 3]. One thread per (spin, pair of words).
+__global__ __launch_bounds__(256) void qg_init(InstDev *I) {
+    const uint32_t n = I->n, W = I->n_words;
+    const uint32_t pairs = W >> 1;
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t total = (uint64_t)n * (pairs + 1);  // + first_hit clearing share
+    if (q >= total) return;
+    const bool init_state = !(I->flags & XS_RESUME);
+    if (q < (uint64_t)n * pairs) {
+        if (init_state) {
+            const uint32_t i = (uint32_t)(q / pairs), w2 = (uint32_t)(q % pairs);
+            const uint4 o = philox10(make_uint4(i, kInitSweep, w2, I->inst_id), I->seed_lo,
+                                     I->seed_hi);
+            uint64_t *row = I->state + (size_t)i * W + 2 * w2;
+            row[0] = (uint64_t)o.x | ((uint64_t)o.y << 32);
+            row[1] = (uint64_t)o.z | ((uint64_t)o.w << 32);
+        }
+    }
+    // first_hit = -1 for every clone (grid-stride over the clones).
+    const uint64_t n_clones = (uint64_t)W * 64;
+    for (uint64_t c = q; c < n_clones; c += total) I->first_hit[c] = -1;
+}
+
+// ------------------------------------------------------------------------------ chunk
+
+// K sweeps (or fewer at the budget end) of one workgroup tile. The grid holds every tile of
+// every instance of the batch; tiles of finished instances return at once.
+__global__ __launch_bounds__(kThreads) void qg_chunk(const InstDev *__restrict__ insts,
+                                                     const uint2 *__restrict__ tiles) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint2 tile = tiles[blockIdx.x];
+    const InstDev *I = insts + tile.x;
+    if (I->done) return;
+    const uint32_t t0 = I->t_cur;
+    const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
+    if (t0 >= t1) return;
+
+    const uint32_t n = I->n, W = I->n_words;
+    const uint32_t B = I->tile_blocks, lB = I->log2_tile_blocks;
+    const uint32_t rowb = B << 5;      // bytes per spin row of the tile
+    const uint32_t ncol = B << 1;      // 16-byte columns per row
+    const uint32_t lcol = lB + 1;
+    const uint32_t ngrp = B << 3;      // 32-clone groups in the tile
+    const uint32_t blk0 = tile.y;
+    const uint32_t tid = threadIdx.x;
+
+    uint4 *rec_l = reinterpret_cast<uint4 *>(smem);
+    uint8_t *st_l = smem + lds_rec_bytes(n);
+    uint8_t *rb_l = st_l + (size_t)n * rowb;
+    uint32_t *acc_l = reinterpret_cast<uint32_t *>(rb_l + align16((size_t)n * B));
+
+    // Records: spin indices -> byte offsets of the rows in this tile.
+    for (uint32_t p = tid; p < n; p += kThreads) {
+        const uint4 r = I->rec[p];
+        const uint32_t i = r.x & 0xFFFFu;
+        uint4 o;
+        o.x = (i * rowb) | (((r.x >> 16) * rowb) << 16);
+        o.y = ((r.y & 0xFFFFu) * rowb) | (((r.y >> 16) * rowb) << 16);
+        o.z = ((r.z & 0xFFFFu) * rowb) | (((r.z >> 16) * rowb) << 16);
+        o.w = ((r.w & 0xFFFFu) * rowb) | ((i | ((r.w >> 16) << 13)) << 16);
+        rec_l[p] = o;
+    }
+    // State tile: row i holds words [4*blk0, 4*blk0 + 4*B).
+    for (uint32_t q = tid; q < n * ncol; q += kThreads) {
+        const uint32_t i = q >> lcol, k = q & (ncol - 1);
+        const uint4 *src = reinterpret_cast<const uint4 *>(I->state + (size_t)i * W + 4 * blk0);
+        *reinterpret_cast<uint4 *>(st_l + i * rowb + 16 * k) = src[k];
+    }
+    // Groups of the tile already in a ground state keep their recorded first hit.
+    uint32_t hm = 0;
+    if (tid < ngrp) {
+        const int32_t *fh = I->first_hit + ((size_t)(blk0 * 8 + tid) << 5);
+        for (int b = 0; b < 32; ++b) hm |= (fh[b] >= 0 ? 1u : 0u) << b;
+        acc_l[tid] = 0;
+    }
+    __syncthreads();
+
+    const uint32_t thr = I->thr, key0 = I->seed_lo, key1 = I->seed_hi, iid = I->inst_id;
+    const uint32_t ncls = I->n_classes;
+    const int32_t *coff = I->class_off;
+    const uint32_t col = tid & (ncol - 1);  // fixed per thread: kThreads is a multiple of ncol
+    const uint8_t *colbase = st_l + (col << 4);
+    const uint32_t rb_sel = col >> 1, rb_shift = (col & 1) << 2;
+
+    for (uint32_t t = t0; t < t1; ++t) {
+        // Acceptance bits of this sweep: one Philox call per (position, block) gives the eight
+        // 16-bit draws of the block's eight groups.
+        for (uint32_t q = tid; q < n * B; q += kThreads) {
+            const uint32_t p = q >> lB, b = q & (B - 1);
+            const uint32_t i = (rec_l[p].w >> 16) & 0x1FFFu;
+            const uint4 o = philox10(make_uint4(i, t, blk0 + b, iid), key0, key1);
+            uint32_t bits = below(o.x & 0xFFFFu, thr) | below(o.x >> 16, thr) << 1 |
+                            below(o.y & 0xFFFFu, thr) << 2 | below(o.y >> 16, thr) << 3 |
+                            below(o.z & 0xFFFFu, thr) << 4 | below(o.z >> 16, thr) << 5 |
+                            below(o.w & 0xFFFFu, thr) << 6 | below(o.w >> 16, thr) << 7;
+            rb_l[q] = (uint8_t)bits;
+        }
+        __syncthreads();
+
+        uint32_t acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        for (uint32_t c = 0; c < ncls; ++c) {
+            const uint32_t cs = (uint32_t)coff[c];
+            const uint32_t ntask = ((uint32_t)coff[c + 1] - cs) << lcol;
+            for (uint32_t q = tid; q < ntask; q += kThreads) {
+                const uint32_t p = cs + (q >> lcol);
+                const uint4 r = rec_l[p];
+                const uint32_t self = r.x & 0xFFFFu;
+                const uint4 x = lds_ld16(colbase, self);
+                const uint4 a1 = lds_ld16(colbase, r.x >> 16);
+                const uint4 b1 = lds_ld16(colbase, r.y & 0xFFFFu);
+                const uint4 a2 = lds_ld16(colbase, r.y >> 16);
+                const uint4 b2 = lds_ld16(colbase, r.z & 0xFFFFu);
+                const uint4 a3 = lds_ld16(colbase, r.z >> 16);
+                const uint4 b3 = lds_ld16(colbase, r.w & 0xFFFFu);
+                const uint32_t meta = r.w >> 16;
+                const uint32_t j1 = 0u - ((meta >> 13) & 1u);
+                const uint32_t j2 = 0u - ((meta >> 14) & 1u);
+                const uint32_t j3 = 0u - (meta >> 15);
+                const uint32_t nib = (uint32_t)rb_l[(p << lB) + rb_sel] >> rb_shift;
+                uint4 y;
+                y.x = qg_word(x.x, a1.x, b1.x, a2.x, b2.x, a3.x, b3.x, j1, j2, j3,
+                              0u - (nib & 1u), acc0);
+                y.y = qg_word(x.y, a1.y, b1.y, a2.y, b2.y, a3.y, b3.y, j1, j2, j3,
+                              0u - ((nib >> 1) & 1u), acc1);
+                y.z = qg_word(x.z, a1.z, b1.z, a2.z, b2.z, a3.z, b3.z, j1, j2, j3,
+                              0u - ((nib >> 2) & 1u), acc2);
+                y.w = qg_word(x.w, a1.w, b1.w, a2.w, b2.w, a3.w, b3.w, j1, j2, j3,
+                              0u - ((nib >> 3) & 1u), acc3);
+                *reinterpret_cast<uint4 *>(const_cast<uint8_t *>(colbase) + self) = y;
+            }
+            __syncthreads();
+        }
+
+        // OR over the threads that own the same column, then per group.
+        for (uint32_t m = ncol; m < 64; m <<= 1) {
+            acc0 |= __shfl_xor(acc0, (int)m);
+            acc1 |= __shfl_xor(acc1, (int)m);
+            acc2 |= __shfl_xor(acc2, (int)m);
+            acc3 |= __shfl_xor(acc3, (int)m);
+        }
+        if ((tid & 63) < ncol) {
+            atomicOr(&acc_l[4 * col + 0], acc0);
+            atomicOr(&acc_l[4 * col + 1], acc1);
+            atomicOr(&acc_l[4 * col + 2], acc2);
+            atomicOr(&acc_l[4 * col + 3], acc3);
+        }
+        __syncthreads();
+        if (tid < ngrp) {
+            const uint32_t v = acc_l[tid];
+            acc_l[tid] = 0;
+            uint32_t fresh = ~v & ~hm;
+            if (fresh) {
+                int32_t *fh = I->first_hit + ((size_t)(blk0 * 8 + tid) << 5);
+                hm |= fresh;
+                while (fresh) {
+                    const int b = __builtin_ctz(fresh);
+                    fh[b] = (int32_t)t;
+                    fresh &= fresh - 1;
+                }
+                atomicOr(const_cast<uint32_t *>(&I->hit), 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < n * ncol; q += kThreads) {
+        const uint32_t i = q >> lcol, k = q & (ncol - 1);
+        uint4 *dst = reinterpret_cast<uint4 *>(I->state + (size_t)i * W + 4 * blk0);
+        dst[k] = *reinterpret_cast<const uint4 *>(st_l + i * rowb + 16 * k);
+    }
+}
+
+// ------------------------------------------------------------------------------ control
+
+// After a chunk: advance every unfinished instance, end it at the budget or (stop-on-first)
+// once a ground state was seen, and count the ones still running. One workgroup.
+__global__ __launch_bounds__(256) void qg_decide(InstDev *insts, int count, uint32_t *active) {
+    __shared__ uint32_t total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    uint32_t mine = 0;
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        InstDev *I = insts + k;
+        if (I->done) continue;
+        const uint32_t t = min(I->t_cur + I->chunk, I->t_stop);
+        I->t_cur = t;
+        const bool stop = t >= I->t_stop || ((I->flags & XS_STOP_ON_FIRST) && I->hit);
+        if (stop)
+            I->done = 1;
+        else
+            ++mine;
+    }
+    atomicAdd(&total, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) *active = total;
+}
+
+// ------------------------------------------------------------------------------ final pass
+
+// Energies at the end sweep, E = 2U - N, from bit-sliced counters of unsatisfied triplets (one
+// thread per 64-clone word). A clone whose end configuration is a ground state and has no
+// recorded hit gets first_hit = end sweep.
+__global__ __launch_bounds__(256) void qg_energy(InstDev *I) {
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t W = I->n_words, n = I->n;
+    if (w >= W) return;
+    const uint64_t *st = I->state;
+    uint64_t cnt[12];  // U <= n <= 2048 < 2^12
+#pragma unroll
+    for (int k = 0; k < 12; ++k) cnt[k] = 0;
+    for (uint32_t t = 0; t < n; ++t) {
+        const uint2 tr = I->tri[t];
+        uint64_t u = st[(size_t)(tr.x & 0xFFFFu) * W + w] ^ st[(size_t)(tr.x >> 16) * W + w] ^
+                     st[(size_t)(tr.y & 0xFFFFu) * W + w];
+        if (tr.y >> 16) u = ~u;
+        // add u (one bit per clone) to the vertical counter
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const uint64_t carry = cnt[k] & u;
+            cnt[k] ^= u;
+            u = carry;
+        }
+    }
+    const int32_t tend = (int32_t)I->t_cur;
+    for (int b = 0; b < 64; ++b) {
+        uint32_t U = 0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) U |= (uint32_t)((cnt[k] >> b) & 1u) << k;
+        const size_t c = (size_t)w * 64 + b;
+        if (I->energy) I->energy[c] = 2 * (int32_t)U - (int32_t)n;
+        if (U == 0 && I->first_hit[c] < 0) I->first_hit[c] = tend;
+    }
+}
+
+__global__ __launch_bounds__(256) void qg_tts(InstDev *I) {
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (size_t)I->n_words * 64) return;
+    const int32_t f = I->first_hit[c];
+    if (f >= 0) atomicMin(&I->tts, f);
+}
+
+__global__ __launch_bounds__(256) void qg_winner(InstDev *I) {
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (size_t)I->n_words * 64) return;
+    if (I->tts != INT32_MAX && I->first_hit[c] == I->tts) atomicMin(&I->winner, (int32_t)c);
+}
+
+__global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= I->n || I->winner == INT32_MAX) return;
+    const uint32_t c = (uint32_t)I->winner;
+    const uint64_t wv = I->state[(size_t)i * I->n_words + (c >> 6)];
+    I->solved[i] = ((wv >> (c & 63)) & 1u) ? (int8_t)-1 : (int8_t)1;
+}
+
+}  // namespace
+
+size_t chunk_lds_bytes(uint32_t n, uint32_t B) {
+    return lds_rec_bytes(n) + (size_t)n * B * 32 + align16((size_t)n * B) + (size_t)B * 8 * 4;
+}
+
+hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
+    const uint64_t total = (uint64_t)h.n * ((h.n_words >> 1) + 1);
+    const uint32_t blocks = (uint32_t)((total + 255) / 256);
+    hipLaunchKernelGGL(qg_init, dim3(blocks), dim3(256), 0, s, const_cast<InstDev *>(d_inst));
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+                        size_t lds_bytes, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(qg_chunk, dim3(n_tiles), dim3(kThreads), lds_bytes, s, d_insts, d_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s) {
+    hipLaunchKernelGGL(qg_decide, dim3(1), dim3(256), 0, s, d_insts, count, d_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(InstDev *d_inst, const InstDev &h, hipStream_t s) {
+    const uint64_t n_clones = (uint64_t)h.n_words * 64;
+    hipLaunchKernelGGL(qg_energy, dim3((h.n_words + 255) / 256), dim3(256), 0, s, d_inst);
+    hipLaunchKernelGGL(qg_tts, dim3((uint32_t)((n_clones + 255) / 256)), dim3(256), 0, s, d_inst);
+    hipLaunchKernelGGL(qg_winner, dim3((uint32_t)((n_clones + 255) / 256)), dim3(256), 0, s,
+                       d_inst);
+    hipLaunchKernelGGL(qg_gather, dim3((h.n + 255) / 256), dim3(256), 0, s, d_inst);
+    return hipGetLastError();
+}
+
+}  // namespace xs

@@ -1,0 +1,49 @@
+// Device-side descriptors shared by the host runtime (api.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace xs {
+
+constexpr int kThreads = 256;      // threads per sweep workgroup (4 wave64)
+constexpr int kMaxTileBlocks = 32; // 256-clone blocks per workgroup tile (8*B groups <= threads)
+constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
+
+// One instance of a batched run as the kernels see it. Lives in device memory; the host fills
+// the constant part, the kernels update the control part.
+struct InstDev {
+    // tables (device pointers owned by the instance)
+    const uint4 *rec;        // [n] 16-byte records in update order: u16 {i, a1, b1, a2, b2, a3, b3, jbits}
+    const int32_t *class_off; // [n_classes + 1]
+    const uint2 *tri;        // [n] triplets: x = a | b << 16, y = c | j << 16 (j = 1 <=> J = -1)
+    // caller buffers
+    uint64_t *state;         // [n][n_words]
+    int32_t *first_hit;      // [n_clones]
+    int32_t *energy;         // [n_clones] or null
+    int8_t *solved;          // [n] device staging for the winner's spins
+    // constants
+    uint32_t n, n_words, n_classes, tile_blocks, log2_tile_blocks;
+    uint32_t inst_id, thr, seed_lo, seed_hi;
+    uint32_t flags, t_start, t_stop, chunk;
+    // control (mutable)
+    uint32_t t_cur;   // next sweep to run
+    uint32_t done;    // nonzero once the run of this instance ended
+    uint32_t hit;     // nonzero once some clone was seen in a ground state
+    int32_t tts;      // min first_hit (final pass)
+    int32_t winner;   // lowest clone with first_hit == tts (final pass)
+    uint32_t pad[3];
+};
+
+}  // namespace xs
+
+// Launch wrappers implemented in kernels.hip (C++ linkage, internal to the library).
+namespace xs {
+hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
+hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+                        size_t lds_bytes, hipStream_t s);
+hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
+hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
+size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks);
+}  // namespace xs

@@ -1,0 +1,236 @@
+"""Python binding of libxorsat.so (include/xorsat.h): argument marshalling only.
+
+Every step of the dynamics runs in the HIP library. torch supplies device buffers and the
+stream; nothing here computes spins, energies or random numbers. If the library is not built
+this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libxorsat.so")
+
+XS_OK = 0
+XS_STATUS = {0: "XS_OK", 1: "XS_EINVAL", 2: "XS_ENOMEM", 3: "XS_EDEVICE", 4: "XS_EAGAIN",
+             5: "XS_ENOTFOUND", 6: "XS_ECANCELED"}
+XS_STOP_ON_FIRST = 0x1
+XS_RESUME = 0x2
+XS_MAX_N = 2048
+XS_CLONE_QUANTUM = 256
+
+# Every function the header declares, for the export check.
+EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_create",
+           "xs_instance_destroy", "xs_instance_get_info", "xs_instance_get_partition",
+           "xs_run", "xs_run_batch", "xs_profile_enable", "xs_profile_read"]
+
+
+class XsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{XS_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class RunConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("instance_id", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("n_clones", ctypes.c_uint32),
+                ("accept_thr", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("max_sweeps", ctypes.c_uint32), ("start_sweep", ctypes.c_uint32),
+                ("chunk_sweeps", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32)]
+
+
+class RunBuffers(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_void_p), ("first_hit", ctypes.c_void_p),
+                ("energy", ctypes.c_void_p), ("solved", ctypes.c_void_p)]
+
+
+class RunResult(ctypes.Structure):
+    _fields_ = [("tts_sweeps", ctypes.c_int64), ("winner_clone", ctypes.c_int32),
+                ("end_sweep", ctypes.c_uint32), ("sweeps_done", ctypes.c_uint32),
+                ("tile_blocks", ctypes.c_uint32), ("clone_spin_updates", ctypes.c_uint64),
+                ("seconds", ctypes.c_double)]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("clone_spin_updates", ctypes.c_uint64)]
+
+
+class InstanceInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("colour_cap", ctypes.c_int32), ("max_class", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libxorsat.so (built in place by paper_2102_09510_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2102_09510_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    lib.xs_abi_version.restype = i32
+    lib.xs_status_str.argtypes = [i32]
+    lib.xs_status_str.restype = ctypes.c_char_p
+    lib.xs_last_error.restype = ctypes.c_char_p
+    lib.xs_instance_create.argtypes = [i32, i32, P, P, i32, ctypes.POINTER(P)]
+    lib.xs_instance_create.restype = i32
+    lib.xs_instance_destroy.argtypes = [P]
+    lib.xs_instance_destroy.restype = None
+    lib.xs_instance_get_info.argtypes = [P, ctypes.POINTER(InstanceInfo)]
+    lib.xs_instance_get_info.restype = i32
+    lib.xs_instance_get_partition.argtypes = [P, P, P]
+    lib.xs_instance_get_partition.restype = i32
+    lib.xs_run.argtypes = [P, ctypes.POINTER(RunConfig), ctypes.POINTER(RunBuffers), P,
+                           ctypes.POINTER(RunResult)]
+    lib.xs_run.restype = i32
+    lib.xs_run_batch.argtypes = [i32, P, P, P, P, P]
+    lib.xs_run_batch.restype = i32
+    lib.xs_profile_enable.argtypes = [i32]
+    lib.xs_profile_enable.restype = i32
+    lib.xs_profile_read.argtypes = [ctypes.POINTER(KernelStats), i32]
+    lib.xs_profile_read.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != XS_OK:
+        raise XsError(status, load().xs_last_error().decode())
+
+
+class Instance:
+    """An instance loaded into the library (host tables; device tables on first use)."""
+
+    def __init__(self, tri, J, colour_cap: int = 32):
+        lib = load()
+        tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+        J = np.ascontiguousarray(J, dtype=np.int8)
+        h = ctypes.c_void_p()
+        _check(lib.xs_instance_create(tri.shape[0], J.shape[0], tri.ctypes.data,
+                                      J.ctypes.data, colour_cap, ctypes.byref(h)))
+        self._h = h
+        info = InstanceInfo()
+        _check(lib.xs_instance_get_info(h, ctypes.byref(info)))
+        self.n = info.n
+        self.n_classes = info.n_classes
+        self.colour_cap = info.colour_cap
+        self.max_class = info.max_class
+
+    @property
+    def handle(self):
+        return self._h
+
+    def partition(self):
+        perm = np.zeros(self.n, dtype=np.int32)
+        off = np.zeros(self.n_classes + 1, dtype=np.int32)
+        _check(load().xs_instance_get_partition(self._h, perm.ctypes.data, off.ctypes.data))
+        return perm, off
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().xs_instance_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class RunOutput:
+    tts_sweeps: int
+    winner_clone: int
+    end_sweep: int
+    sweeps_done: int
+    tile_blocks: int
+    clone_spin_updates: int
+    seconds: float
+    state: object        # torch int64 [n][n_clones/64] on the device
+    first_hit: object    # torch int32 [n_clones]
+    energy: object       # torch int32 [n_clones] or None
+    solved: np.ndarray | None  # int8 [n] (+1/-1) of the winner, None if no clone hit
+
+
+def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: int = 3604,
+                max_sweeps: int = 100000, stop_on_first: bool = True, resume: bool = False,
+                start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0) -> RunConfig:
+    flags = (XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0)
+    return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
+                     accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks)
+
+
+def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
+    import torch
+    n, nc = inst.n, cfg.n_clones
+    if state is None:
+        state = torch.empty((n, nc // 64), dtype=torch.int64, device=device)
+    else:
+        assert state.dtype == torch.int64 and tuple(state.shape) == (n, nc // 64)
+        assert state.is_contiguous()
+    first_hit = torch.empty(nc, dtype=torch.int32, device=device)
+    energy = torch.empty(nc, dtype=torch.int32, device=device) if want_energy else None
+    solved = np.zeros(n, dtype=np.int8)
+    bufs = RunBuffers(state.data_ptr(), first_hit.data_ptr(),
+                      energy.data_ptr() if energy is not None else None, solved.ctypes.data)
+    return bufs, state, first_hit, energy, solved
+
+
+def _output(res: RunResult, state, first_hit, energy, solved) -> RunOutput:
+    return RunOutput(int(res.tts_sweeps), int(res.winner_clone), int(res.end_sweep),
+                     int(res.sweeps_done), int(res.tile_blocks), int(res.clone_spin_updates),
+                     float(res.seconds), state, first_hit, energy,
+                     solved if res.winner_clone >= 0 else None)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def run(inst: Instance, cfg: RunConfig, *, state=None, want_energy: bool = True,
+        device="cuda") -> RunOutput:
+    """xs_run on torch-owned device buffers (state is drawn unless cfg has XS_RESUME)."""
+    bufs, state, fh, en, solved = _buffers(inst, cfg, state, want_energy, device)
+    res = RunResult()
+    _check(load().xs_run(inst.handle, ctypes.byref(cfg), ctypes.byref(bufs), _stream(),
+                         ctypes.byref(res)))
+    return _output(res, state, fh, en, solved)
+
+
+def run_batch(insts: list[Instance], cfgs: list[RunConfig], *, states=None,
+              want_energy: bool = True, device="cuda") -> list[RunOutput]:
+    """xs_run_batch over several instances (one chunk launch covers all of them)."""
+    count = len(insts)
+    assert count == len(cfgs) and count > 0
+    states = states or [None] * count
+    made = [_buffers(i, c, s, want_energy, device) for i, c, s in zip(insts, cfgs, states)]
+    handles = (ctypes.c_void_p * count)(*[i.handle.value for i in insts])
+    cfg_arr = (RunConfig * count)(*cfgs)
+    buf_arr = (RunBuffers * count)(*[m[0] for m in made])
+    res_arr = (RunResult * count)()
+    _check(load().xs_run_batch(count, handles, cfg_arr, buf_arr, _stream(), res_arr))
+    return [_output(res_arr[k], *made[k][1:]) for k in range(count)]
+
+
+def profile_enable(on: bool = True):
+    """Time every sweep-chunk launch with HIP events on the run's stream."""
+    _check(load().xs_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = False) -> dict:
+    st = KernelStats()
+    _check(load().xs_profile_read(ctypes.byref(st), 1 if reset else 0))
+    return dict(launches=int(st.launches), total_ms=float(st.total_ms),
+                clone_spin_updates=int(st.clone_spin_updates))

@@ -1,0 +1,88 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared function, validates
+instances, and its host-side partition is the same greedy partition the oracle computes."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_09510_amd import xorsat
+from paper_2102_09510_amd.instances import planted_instance
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(xorsat.LIB_PATH):
+        from paper_2102_09510_amd import build
+        build.build()
+    return xorsat.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "xorsat.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xs_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 9
+    assert sorted(xorsat.EXPORTS) == names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.xs_abi_version() == 1
+    assert lib.xs_status_str(1) == b"XS_EINVAL"
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(xorsat.RunConfig) == 48
+    assert ctypes.sizeof(xorsat.RunBuffers) == 32
+    assert ctypes.sizeof(xorsat.RunResult) == 40
+    assert ctypes.sizeof(xorsat.InstanceInfo) == 16
+
+
+@pytest.mark.parametrize("n,cap", [(10, 32), (10, 2), (64, 32), (256, 32), (1024, 32),
+                                   (2048, 32), (200, 7), (100, 64)])
+def test_partition_matches_oracle(lib, n, cap):
+    inst = planted_instance(n, 77 + n) if n != 10 else planted_instance(10, 11)
+    h = xorsat.Instance(inst.tri, inst.J, colour_cap=cap)
+    perm, off = h.partition()
+    operm, ooff = oracle.colour(inst.tri, cap)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(off, ooff)
+    assert h.n_classes == len(ooff) - 1
+    assert h.max_class == int(np.diff(ooff).max())
+    h.close()
+
+
+def test_instance_validation(lib):
+    inst = planted_instance(16, 3)
+    tri, J = inst.tri.copy(), inst.J.copy()
+    bad = []
+    t = tri.copy(); t[0, 1] = t[0, 0]; bad.append((t, J, "repeats"))
+    t = tri.copy(); t[0, 0] = 16; bad.append((t, J, "outside"))
+    t = tri.copy(); t[0, 0] = (t[0, 0] + 1) % 16
+    if len(set(t[0])) == 3:
+        bad.append((t, J, "triplets, not 3"))
+    j = J.copy(); j[3] = 0; bad.append((tri, j, "+1/-1"))
+    for t, j, msg in bad:
+        with pytest.raises(xorsat.XsError) as e:
+            xorsat.Instance(t, j)
+        assert e.value.status == 1 and msg in str(e.value)
+    with pytest.raises(xorsat.XsError):
+        xorsat.Instance(tri[:3], J[:3])
+    big = planted_instance(2049, 1)
+    with pytest.raises(xorsat.XsError):
+        xorsat.Instance(big.tri, big.J)
+
+
+def test_last_error_is_thread_local_message(lib):
+    with pytest.raises(xorsat.XsError):
+        xorsat.Instance(np.zeros((4, 3), dtype=np.int32), np.ones(4, dtype=np.int8))
+    assert lib.xs_last_error().decode()

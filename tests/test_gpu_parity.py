@@ -1,0 +1,232 @@
+"""GPU <-> oracle parity through the C ABI: bit-exact per clone (first hit, energy at the end
+sweep, final spins) and per run (TTS, winner, solved configuration). All integer, so the bar is
+exact equality."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_09510_amd import xorsat
+from paper_2102_09510_amd.instances import THR_PAPER, planted_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def spins_of_clones(state, clones) -> np.ndarray:
+    """[len(clones)][n] spins (+1/-1) from the device state (bit c & 63 of word c >> 6)."""
+    st = state.cpu().numpy().view(np.uint64)
+    clones = np.asarray(clones, dtype=np.int64)
+    bits = (st[:, clones >> 6] >> (clones & 63).astype(np.uint64)) & np.uint64(1)
+    return (1 - 2 * bits.T.astype(np.int16)).astype(np.int8)
+
+
+def oracle_replay(inst, h, cfg, out, clones, init_spins=None):
+    """The oracle run of the given clones from the same start to the GPU's end sweep."""
+    perm, _ = h.partition()
+    operm, _ = oracle.colour(inst.tri, h.colour_cap)
+    assert np.array_equal(perm, operm)
+    res = {"first_hit": [], "energy": [], "final_spins": []}
+    clones = np.asarray(clones)
+    # contiguous runs of clones keep the oracle call count small
+    starts = np.flatnonzero(np.diff(np.r_[-2, clones]) != 1)
+    ends = np.r_[starts[1:], clones.size]
+    for a, b in zip(starts, ends):
+        init = None if init_spins is None else init_spins[a:b]
+        r = oracle.run(inst.tri, inst.J, operm, seed=cfg.seed, instance_id=cfg.instance_id,
+                       thr=cfg.accept_thr, n_sweeps=out.sweeps_done,
+                       start_sweep=cfg.start_sweep, clone_begin=int(clones[a]),
+                       clone_count=int(b - a), init_spins=init, want_final=True)
+        for k in res:
+            res[k].append(r[k])
+    return {k: np.concatenate(v) for k, v in res.items()}
+
+
+def assert_parity(inst, h, cfg, out, clones=None, init_spins=None):
+    n_clones = cfg.n_clones
+    if clones is None:
+        clones = np.arange(n_clones)
+    clones = np.asarray(clones)
+    ref = oracle_replay(inst, h, cfg, out, clones, init_spins)
+    fh = out.first_hit.cpu().numpy()[clones]
+    en = out.energy.cpu().numpy()[clones]
+    sp = spins_of_clones(out.state, clones)
+    bad = np.flatnonzero(fh != ref["first_hit"])
+    assert bad.size == 0, f"first_hit differs at clones {clones[bad[:8]]}"
+    assert np.array_equal(en, ref["energy"])
+    assert np.array_equal(sp, ref["final_spins"])
+    return ref
+
+
+def run_and_check_full(n, seed, n_clones, *, max_sweeps, stop=True, chunk=0, tile_blocks=0,
+                       thr=THR_PAPER, cap=32, iid=3):
+    _torch()
+    inst = planted_instance(n, seed)
+    h = xorsat.Instance(inst.tri, inst.J, colour_cap=cap)
+    cfg = xorsat.make_config(n_clones=n_clones, seed=seed * 7 + 1, instance_id=iid,
+                             accept_thr=thr, max_sweeps=max_sweeps, stop_on_first=stop,
+                             chunk_sweeps=chunk, tile_blocks=tile_blocks)
+    out = xorsat.run(h, cfg)
+    ref = assert_parity(inst, h, cfg, out)
+    tts, winner = oracle.solve_results(ref["first_hit"])
+    assert out.tts_sweeps == tts and out.winner_clone == winner
+    if winner >= 0:
+        assert np.array_equal(out.solved, ref["final_spins"][winner])
+        assert oracle.energy(inst.tri, inst.J, out.solved) == -n
+    return inst, h, cfg, out
+
+
+def test_small_instance_full_parity_to_first_ground_state():
+    """N = 64, 1024 clones, stop at the first ground state (the single-instance workload):
+    every clone, every output, TTS and winner."""
+    inst, h, cfg, out = run_and_check_full(64, 1000001, 1024, max_sweeps=100000)
+    assert out.tts_sweeps >= 0
+    assert out.end_sweep % 100 == 0 or out.end_sweep == 100000
+
+
+@pytest.mark.parametrize("n,clones,B,chunk,sweeps", [
+    (100, 4096, 2, 7, 40),     # ragged classes, 8 tiles, chunk does not divide the budget
+    (37, 2048, 0, 0, 33),      # odd N, auto tiling, single chunk
+    (257, 1024, 1, 5, 23),     # N just above 256, one-block tiles
+    (4, 256, 1, 1, 9),         # smallest instance and clone count
+])
+def test_budget_runs_every_clone(n, clones, B, chunk, sweeps):
+    run_and_check_full(n, 500 + n, clones, max_sweeps=sweeps, stop=False, chunk=chunk,
+                       tile_blocks=B)
+
+
+@pytest.mark.parametrize("thr", [0, 65536])
+def test_deterministic_rules(thr):
+    """w1 = 0 (greedy) and w1 = 1 (every spin with k >= 1 flips)."""
+    run_and_check_full(128, 61, 2048, max_sweeps=30, stop=False, thr=thr)
+
+
+def test_colour_cap_variants():
+    run_and_check_full(96, 62, 1024, max_sweeps=25, stop=False, cap=5)
+    run_and_check_full(96, 62, 1024, max_sweeps=25, stop=False, cap=64)
+
+
+def test_tiling_is_result_neutral():
+    """tile_blocks only moves work between workgroups; every output is identical."""
+    torch = _torch()
+    inst = planted_instance(128, 9)
+    h = xorsat.Instance(inst.tri, inst.J)
+    outs = []
+    for B in (1, 2, 4, 8, 16):
+        cfg = xorsat.make_config(n_clones=8192, seed=99, instance_id=1, max_sweeps=300,
+                                 stop_on_first=False, tile_blocks=B, chunk_sweeps=64)
+        outs.append(xorsat.run(h, cfg))
+    for o in outs[1:]:
+        assert torch.equal(o.state, outs[0].state)
+        assert torch.equal(o.first_hit, outs[0].first_hit)
+        assert torch.equal(o.energy, outs[0].energy)
+        assert o.tts_sweeps == outs[0].tts_sweeps and o.winner_clone == outs[0].winner_clone
+
+
+def test_chunk_length_changes_only_end_sweep():
+    """TTS, winner, solved configuration and each clone's hit up to the TTS do not depend on
+    the chunk length; the end sweep (and so later state) may."""
+    _torch()
+    inst = planted_instance(64, 1000001)
+    h = xorsat.Instance(inst.tri, inst.J)
+    res = []
+    for K in (1, 13, 100, 1000):
+        cfg = xorsat.make_config(n_clones=1024, seed=5, instance_id=0, chunk_sweeps=K,
+                                 max_sweeps=100000)
+        res.append(xorsat.run(h, cfg))
+    for o in res[1:]:
+        assert o.tts_sweeps == res[0].tts_sweeps and o.winner_clone == res[0].winner_clone
+        assert np.array_equal(o.solved, res[0].solved)
+        assert o.end_sweep >= o.tts_sweeps
+    assert res[0].end_sweep == res[0].tts_sweeps + 1 or res[0].end_sweep == res[0].tts_sweeps
+
+
+def test_batch_equals_single_runs():
+    """Uneven instances in one batched run give bit-identical results to one run each."""
+    torch = _torch()
+    sizes = [(48, 512), (64, 1024), (200, 2048), (33, 256), (512, 1024)]
+    insts, hs, cfgs = [], [], []
+    for k, (n, nc) in enumerate(sizes):
+        inst = planted_instance(n, 300 + k)
+        insts.append(inst)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        cfgs.append(xorsat.make_config(n_clones=nc, seed=1000 + k, instance_id=k,
+                                       max_sweeps=400 if n < 100 else 60,
+                                       stop_on_first=n < 100, chunk_sweeps=20))
+    batch = xorsat.run_batch(hs, cfgs)
+    for k in range(len(sizes)):
+        single = xorsat.run(hs[k], cfgs[k])
+        b = batch[k]
+        assert torch.equal(b.state, single.state)
+        assert torch.equal(b.first_hit, single.first_hit)
+        assert torch.equal(b.energy, single.energy)
+        assert (b.tts_sweeps, b.winner_clone, b.end_sweep) == \
+            (single.tts_sweeps, single.winner_clone, single.end_sweep)
+    # and the batch itself against the oracle on the small ones
+    for k in (0, 3):
+        assert_parity(insts[k], hs[k], cfgs[k], batch[k])
+
+
+def test_resume_equals_uninterrupted():
+    torch = _torch()
+    inst = planted_instance(80, 44)
+    h = xorsat.Instance(inst.tri, inst.J)
+    kw = dict(n_clones=2048, seed=77, instance_id=2, stop_on_first=False, chunk_sweeps=16)
+    full = xorsat.run(h, xorsat.make_config(max_sweeps=90, **kw))
+    a = xorsat.run(h, xorsat.make_config(max_sweeps=40, **kw))
+    b = xorsat.run(h, xorsat.make_config(max_sweeps=50, start_sweep=40, resume=True, **kw),
+                   state=a.state.clone())
+    assert torch.equal(full.state, b.state)
+    assert torch.equal(full.energy, b.energy)
+    assert b.end_sweep == 90
+
+
+def test_zero_budget_and_ground_state_start():
+    """max_sweeps = 0 only checks the start; a start in the planted solution is a hit at
+    start_sweep and never moves (w0 = 0)."""
+    torch = _torch()
+    inst = planted_instance(64, 45)
+    h = xorsat.Instance(inst.tri, inst.J)
+    cfg = xorsat.make_config(n_clones=512, seed=3, max_sweeps=0)
+    out = xorsat.run(h, cfg)
+    assert out.sweeps_done == 0 and out.end_sweep == 0
+    assert_parity(inst, h, cfg, out)
+    # all clones start in the planted solution tau
+    bits = (inst.tau < 0).astype(np.uint64)
+    word = np.where(bits[:, None] == 1, np.uint64(2**64 - 1), np.uint64(0))
+    state = torch.from_numpy(np.repeat(word, 512 // 64, axis=1).view(np.int64)).cuda()
+    cfg = xorsat.make_config(n_clones=512, seed=3, max_sweeps=10, start_sweep=17, resume=True,
+                             stop_on_first=False)
+    out = xorsat.run(h, cfg, state=state.clone())
+    assert torch.equal(out.state, state)
+    assert (out.first_hit.cpu().numpy() == 17).all()
+    assert (out.energy.cpu().numpy() == -64).all()
+    assert out.tts_sweeps == 17 and out.winner_clone == 0
+
+
+@pytest.mark.parametrize("n,clones,sweeps", [(256, 65536, 120), (1024, 1 << 20, 12),
+                                             (2048, 16384, 20)])
+def test_full_size_sampled_clones(n, clones, sweeps):
+    """Full-size shapes (the batched N = 256 workload, the N = 1024 steady-state workload and
+    the largest N): every clone's energy must be a valid E = 2U - N; sampled clones from
+    different tiles match the oracle bit for bit."""
+    _torch()
+    inst = planted_instance(n, 9000 + n)
+    h = xorsat.Instance(inst.tri, inst.J)
+    cfg = xorsat.make_config(n_clones=clones, seed=n, instance_id=n, max_sweeps=sweeps,
+                             stop_on_first=False)
+    out = xorsat.run(h, cfg)
+    en = out.energy.cpu().numpy()
+    assert en.min() >= -n and en.max() <= n and np.all((en + n) % 2 == 0)
+    rng = np.random.default_rng(n)
+    groups = rng.choice(clones // 32, size=6, replace=False)
+    sample = np.sort(np.concatenate([32 * g + np.arange(32) for g in groups]))
+    sample = np.r_[sample, clones - 1]
+    assert_parity(inst, h, cfg, out, clones=sample)
