@@ -27,11 +27,17 @@ if ROOT not in sys.path:
 # Peak of the bound resource: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s of
 # full-rate 32-bit VALU work.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic VALU work per clone-spin update in full-rate lane-op units: the rule and the
-# ground-state test take 9 three-input operations per 32-clone word; one Philox4x32-10 call
-# (10 rounds of 2 quarter-rate 32x32->64 products and 2 three-input XORs) plus 8 threshold
-# compares serve 8 groups = 256 clones.
-ALGO_OPS_PER_UPDATE = 9 / 32 + (10 * (2 * 4 + 2) + 8) / 256
+# Algorithmic VALU work per clone-spin update, in full-rate lane operations (gfx950 issues
+# v_bitop3_b32 and the 32x32->64 v_mad_u64_u32 at full rate): the rule and the ground-state
+# test take 9 three-input operations per 32-clone word; one Philox4x32-10 call (10 rounds of
+# 2 wide products and 2 three-input XORs) plus 8 threshold compares serve 8 groups = 256
+# clones. 9/32 + 48/256 = 0.469 lane-ops per update.
+ALGO_OPS_PER_UPDATE = 9 / 32 + (10 * (2 + 2) + 8) / 256
+# Algorithmic LDS traffic per update: the 7 state bits an update reads (own spin and the two
+# partners in each of its three triplets) and the 1 bit it writes = 1 byte.
+ALGO_LDS_BYTES_PER_UPDATE = 1.0
+# LDS peak: 256 CUs x 128 B/clk x 2.4 GHz.
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 
 
 def parse():
@@ -42,10 +48,14 @@ def parse():
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--clones", type=int, default=65536)
-    ap.add_argument("--budget", type=int, default=400, help="sweep budget per instance and step")
+    ap.add_argument("--budget", type=int, default=50000,
+                    help="sweep budget per instance and step (first ground states at N=256 "
+                         "take far longer, so most instances end at the budget)")
     ap.add_argument("--chunk", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     return ap.parse_args()
 
 
@@ -77,9 +87,10 @@ def cpu_baseline(insts, args, target_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of "
-                                   "it (clones shard by 32-clone group with one min-reduction, "
-                                   "see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this solver runs on one GPU; several GPUs would each take "
+                                   "a share of the 32-clone groups and combine first hits with "
+                                   "one min-reduction, which is not implemented here",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
@@ -88,6 +99,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibrate:
+        src = torch.ones(args.copy_calibrate << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return
     insts = [planted_instance(args.n, gen_seed(2, k)) for k in range(args.instances)]
     handles = [xorsat.Instance(i.tri, i.J) for i in insts]
 
@@ -130,6 +149,7 @@ def main():
     per_launch_updates = prof["clone_spin_updates"] / max(prof["launches"], 1)
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     achieved = ALGO_OPS_PER_UPDATE * per_launch_updates / (avg_ms * 1e-3) / 1e12
+    lds_tbs = ALGO_LDS_BYTES_PER_UPDATE * per_launch_updates / (avg_ms * 1e-3) / 1e12
     line = {
         "metric": "clone-spin updates/ns on 1 MI355X",
         "value": round(value, 3),
@@ -155,7 +175,10 @@ def main():
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
                      "kernel": "qg_chunk", "launches": prof["launches"],
                      "avg_launch_ms": round(avg_ms, 3),
-                     "kernel_updates_per_ns": round(kern_rate, 3)},
+                     "kernel_updates_per_ns": round(kern_rate, 3),
+                     "lds": {"achieved_TBs": round(lds_tbs, 3), "peak_TBs": round(LDS_PEAK_TBS, 2),
+                             "frac": round(lds_tbs / LDS_PEAK_TBS, 4),
+                             "bytes_per_update": ALGO_LDS_BYTES_PER_UPDATE}},
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(insts, args, args.cpu_seconds)

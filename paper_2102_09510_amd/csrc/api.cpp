@@ -160,15 +160,19 @@ uint32_t ilog2(uint32_t v) {
     return r;
 }
 
-// Largest power-of-two tile (in 256-clone blocks) that divides the clone count, keeps LDS byte
-// offsets in 16 bits (n * B <= 2048) and keeps the tile within `max_b`.
-uint32_t auto_tile_blocks(uint32_t n, uint32_t n_blocks, uint32_t max_b) {
+// Largest power-of-two tile (in 256-clone blocks) that divides the clone count and keeps the
+// tile's spin rows within `max_row_blocks` (n * B <= max: state LDS of n * B * 32 bytes).
+uint32_t max_tile_blocks(uint32_t n, uint32_t n_blocks, uint32_t max_nb) {
     uint32_t B = 1;
-    while (B * 2 <= max_b && n_blocks % (B * 2) == 0 && n * (B * 2) <= 2048 &&
-           B * 2 <= (uint32_t)xs::kMaxTileBlocks)
+    while (n_blocks % (B * 2) == 0 && n * (B * 2) <= max_nb && B * 2 <= (uint32_t)xs::kMaxTileBlocks)
         B *= 2;
     return B;
 }
+
+// Default tiling: each workgroup keeps at most 32 KB of clone state (four workgroups per CU
+// fit the 160 KB of LDS next to their tables), then tiles are halved across the batch while it
+// has fewer than kTargetTiles workgroups, so that small batches still spread over the CUs.
+constexpr size_t kTargetTiles = 1024;
 
 xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b) {
     if (!I || !cfg || !b) return fail(XS_EINVAL, "null argument");
@@ -218,7 +222,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         st = ensure_tables(const_cast<xs_instance *>(I), device, &t);
         if (st != XS_OK) return st;
         const uint32_t nb = c.n_clones / 256;
-        const uint32_t B = c.tile_blocks ? c.tile_blocks : auto_tile_blocks(I->n, nb, 8);
+        const uint32_t B = c.tile_blocks ? c.tile_blocks : max_tile_blocks(I->n, nb, 1024);
         xs::InstDev &d = h[k];
         std::memset(&d, 0, sizeof d);
         d.rec = t.rec;
@@ -245,8 +249,30 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         d.hit = 0;
         d.tts = INT32_MAX;
         d.winner = INT32_MAX;
-        for (uint32_t b0 = 0; b0 < nb; b0 += B) tiles.push_back(make_uint2((uint32_t)k, b0));
-        lds = std::max(lds, xs::chunk_lds_bytes(d.n, B));
+    }
+    // Shrink automatic tiles while the batch has too few workgroups.
+    auto count_tiles = [&]() {
+        size_t t = 0;
+        for (int k = 0; k < count; ++k) t += (cfgs[k].n_clones / 256) / h[k].tile_blocks;
+        return t;
+    };
+    for (;;) {
+        if (count_tiles() >= kTargetTiles) break;
+        bool changed = false;
+        for (int k = 0; k < count; ++k)
+            if (!cfgs[k].tile_blocks && h[k].tile_blocks > 1) {
+                h[k].tile_blocks /= 2;
+                changed = true;
+            }
+        if (!changed) break;
+    }
+    for (int k = 0; k < count; ++k) {
+        xs::InstDev &d = h[k];
+        d.log2_tile_blocks = ilog2(d.tile_blocks);
+        const uint32_t nb = cfgs[k].n_clones / 256;
+        for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks)
+            tiles.push_back(make_uint2((uint32_t)k, b0));
+        lds = std::max(lds, xs::chunk_lds_bytes(d.n, d.tile_blocks));
     }
 
     // Per-call device scratch: descriptors, tiles, the running-instance counter and the
