@@ -59,6 +59,25 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(args):
+    """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE record, if it was
+    taken on the current kernel source and the default workload; otherwise None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "qg_chunk_n256x64_hbm_counters.json")
+    if not os.path.exists(path) or (args.instances, args.n, args.clones, args.chunk) != \
+            (64, 256, 65536, 100):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "xs_internal.h"):
+        with open(os.path.join(ROOT, "paper_2102_09510_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(insts, args, target_s):
     """The oracle on a bounded sample: every instance, one 256-clone block, S sweeps."""
     import oracle
@@ -68,8 +87,8 @@ def cpu_baseline(insts, args, target_s):
     # calibrate on one instance
     t0 = time.perf_counter()
     oracle.run(insts[0].tri, insts[0].J, perms[0], seed=1, instance_id=0, thr=3604,
-               n_sweeps=20, clone_count=256, threads=threads)
-    per_sweep = max((time.perf_counter() - t0) / 20, 1e-6)
+               n_sweeps=200, clone_count=256, threads=threads)
+    per_sweep = max((time.perf_counter() - t0) / 200, 1e-6)
     sweeps = int(max(10, min(5000, target_s / (per_sweep * len(insts)))))
     t0 = time.perf_counter()
     updates = 0
@@ -172,7 +191,8 @@ def main():
                        "p99": float(np.percentile(tts, 99)) if tts else None},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": measured_traffic(args),
                      "kernel": "qg_chunk", "launches": prof["launches"],
                      "avg_launch_ms": round(avg_ms, 3),
                      "kernel_updates_per_ns": round(kern_rate, 3),

@@ -47,7 +47,8 @@ typedef int32_t xs_status;
 #define XS_CLONE_QUANTUM 256
 
 /* Run flags (xs_run_config.flags). */
-#define XS_STOP_ON_FIRST 0x1u /* stop after the first chunk in which some clone reached E = -N */
+#define XS_STOP_ON_FIRST 0x1u /* stop at the end of the first chunk after which some clone
+                                 is in a ground state (E = -N) */
 #define XS_RESUME 0x2u        /* state already holds the start configuration (checkpoint)     */
 
 typedef struct xs_instance xs_instance;
@@ -106,8 +107,11 @@ typedef struct {
     uint32_t max_sweeps;   /* sweep budget of this call (0 = only check the start state) */
     uint32_t start_sweep;  /* absolute index of the first sweep (for resumed runs) */
     uint32_t chunk_sweeps; /* sweeps between stop checks, K (0 = 100, as in the paper) */
-    uint32_t tile_blocks;  /* clone blocks of 256 per workgroup; 0 = chosen by the library.
-                              Changes speed only, never results. */
+    uint32_t tile_blocks;  /* clone blocks of 256 per workgroup (power of two <= 32, dividing
+                              n_clones / 256, n * tile_blocks <= 2048); 0 = chosen by the
+                              library. Changes speed only, never results. */
+    uint32_t wg_threads;   /* threads per workgroup: 64 .. 1024, a power of two, at least
+                              8 * tile_blocks; 0 = chosen by the library. Speed only. */
 } xs_run_config;
 
 /*
@@ -134,6 +138,7 @@ typedef struct {
     uint32_t end_sweep;          /* absolute sweep index at which the run stopped */
     uint32_t sweeps_done;        /* end_sweep - start_sweep */
     uint32_t tile_blocks;        /* tiling used (result-neutral) */
+    uint32_t wg_threads;         /* workgroup size used (result-neutral) */
     uint64_t clone_spin_updates; /* n_clones * n * sweeps_done */
     double seconds;              /* wall time of the call */
 } xs_run_result;
@@ -141,7 +146,7 @@ typedef struct {
 /*
  * Run one instance: draw the start configuration (unless XS_RESUME), then sweep in chunks of
  * chunk_sweeps until max_sweeps are done or, with XS_STOP_ON_FIRST, until the end of the first
- * chunk in which some clone reached E = -N. With w0 = 0 a ground state is never left
+ * chunk after which some clone is in a ground state (E = -N). With w0 = 0 a ground state is never left
  * (Section "The quasi-greedy algorithm", property (iii)), so the exact first sweep of every
  * clone is known and the chunk length changes only end_sweep, never first hits, TTS, winner
  * or solved configuration. Work is ordered on `stream`; the call returns after it finished.

@@ -199,8 +199,20 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
                         "n * tile_blocks <= 2048",
                         B, xs::kMaxTileBlocks);
     }
+    if (cfg->wg_threads) {
+        const uint32_t T = cfg->wg_threads;
+        const uint32_t B = cfg->tile_blocks;
+        if ((T & (T - 1)) || T < 64 || T > 1024)
+            return fail(XS_EINVAL, "wg_threads %u must be a power of two in [64, 1024]", T);
+        if (B && T < 8 * B)
+            return fail(XS_EINVAL, "wg_threads %u must be at least 8 * tile_blocks (%u)", T, B);
+    }
     return XS_OK;
 }
+
+// Default workgroup size for a tile of B blocks: one thread per (spin, 16-byte column) task of a
+// full 32-spin class, within [256, 1024].
+uint32_t default_threads(uint32_t B) { return std::min(1024u, std::max(256u, 64u * B)); }
 
 xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
                     const xs_run_buffers *bufs, hipStream_t stream, xs_run_result *results) {
@@ -212,7 +224,6 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
 
     std::vector<xs::InstDev> h(count);
     std::vector<uint2> tiles;
-    size_t lds = 0;
     for (int k = 0; k < count; ++k) {
         const xs_instance *I = insts[k];
         const xs_run_config &c = cfgs[k];
@@ -266,15 +277,32 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             }
         if (!changed) break;
     }
+    // Tiles grouped by workgroup size: one launch per group and chunk.
+    std::map<uint32_t, std::vector<uint2>> by_threads;
+    std::map<uint32_t, size_t> lds_of;
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
         d.log2_tile_blocks = ilog2(d.tile_blocks);
+        uint32_t T = cfgs[k].wg_threads ? cfgs[k].wg_threads : default_threads(d.tile_blocks);
+        T = std::max(T, 8 * d.tile_blocks);
+        d.wg_threads = T;
         const uint32_t nb = cfgs[k].n_clones / 256;
-        for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks)
-            tiles.push_back(make_uint2((uint32_t)k, b0));
-        lds = std::max(lds, xs::chunk_lds_bytes(d.n, d.tile_blocks));
+        auto &v = by_threads[T];
+        for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) v.push_back(make_uint2((uint32_t)k, b0));
+        lds_of[T] = std::max(lds_of[T], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes));
     }
-
+    struct Group {
+        uint32_t threads;
+        size_t first, count, lds;
+    };
+    std::vector<Group> groups;
+    for (auto &kv : by_threads) {
+        groups.push_back(Group{kv.first, tiles.size(), kv.second.size(), lds_of[kv.first]});
+        tiles.insert(tiles.end(), kv.second.begin(), kv.second.end());
+    }
+    for (const Group &g : groups)
+        if (g.lds > 160 * 1024)
+            return fail(XS_EINVAL, "a tile needs %zu bytes of LDS (max 163840)", g.lds);
     // Per-call device scratch: descriptors, tiles, the running-instance counter and the
     // winners' spins.
     size_t solved_bytes = 0;
@@ -333,7 +361,9 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             }
         for (int g = 0; g < group; ++g) {
             if (profile) XS_HIP(hipEventRecord(ev[2 * g], stream));
-            XS_HIP(xs::launch_chunk(d_inst, d_tiles, (int)tiles.size(), lds, stream));
+            for (const Group &gr : groups)
+                XS_HIP(xs::launch_chunk(d_inst, d_tiles + gr.first, (int)gr.count,
+                                        (int)gr.threads, gr.lds, stream));
             if (profile) XS_HIP(hipEventRecord(ev[2 * g + 1], stream));
             XS_HIP(xs::launch_decide(d_inst, count, d_active, stream));
         }
@@ -372,6 +402,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         r.end_sweep = d.t_cur;
         r.sweeps_done = d.t_cur - d.t_start;
         r.tile_blocks = d.tile_blocks;
+        r.wg_threads = d.wg_threads;
         r.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * r.sweeps_done;
         r.seconds = secs;
         if (bufs[k].solved && d.winner != INT32_MAX)

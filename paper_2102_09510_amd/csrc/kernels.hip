@@ -69,7 +69,9 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 
 __device__ __forceinline__ uint32_t below(uint32_t v, uint32_t thr) { return v < thr ? 1u : 0u; }
 
-// One 32-clone word of one spin: nine three-input operations.
+// One 32-clone word of one spin: eight three-input operations, a ninth when ground states are
+// tracked (kAcc: acc collects "k >= 1").
+template <bool kAcc>
 __device__ __forceinline__ uint32_t qg_word(uint32_t x, uint32_t a1, uint32_t b1, uint32_t a2,
                                             uint32_t b2, uint32_t a3, uint32_t b3, uint32_t j1,
                                             uint32_t j2, uint32_t j3, uint32_t accept,
@@ -81,13 +83,10 @@ __device__ __forceinline__ uint32_t qg_word(uint32_t x, uint32_t a1, uint32_t b1
     const uint32_t par = lop3<kXor3>(p1, p2, p3);
     const uint32_t dmaj = x ^ m;                     // k >= 2
     const uint32_t k1 = lop3<kXorAndNot>(x, par, dmaj);  // k == 1
-    acc = lop3<kOr3>(acc, k1, dmaj);                 // k >= 1
+    if (kAcc) acc = lop3<kOr3>(acc, k1, dmaj);       // k >= 1
     return lop3<kXorAnd>(m, k1, accept);
 }
 
-__device__ __forceinline__ uint4 lds_ld16(const uint8_t *base, uint32_t off) {
-    return *reinterpret_cast<const uint4 *>(base + off);
-}
 
 constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
@@ -121,11 +120,192 @@ __global__ __launch_bounds__(256) void qg_init(InstDev *I) {
 
 // ------------------------------------------------------------------------------ chunk
 
+// The workgroup's dynamic LDS. Every LDS access below indexes this array, so the compiler
+// keeps them all as ds_* instructions.
+extern __shared__ __align__(16) uint8_t xs_lds[];
+
+// Per-workgroup view of one tile. LDS locations are byte offsets into xs_lds.
+struct Tile {
+    const InstDev *I;
+    uint32_t n, W, B, lB, rowb, ncol, lcol, ngrp, blk0, tid, col;
+    uint32_t st;         // state rows (records start at 0)
+    uint32_t rb0, rb1;   // acceptance bytes, double-buffered by sweep parity
+    uint32_t acc;        // per-group accumulators [8*B] (uint32)
+    uint32_t flag;       // workgroup flag (uint32)
+    uint32_t colbase;    // st + this thread's column
+    uint32_t rb_sel, rb_shift;
+    uint32_t thr, key0, key1, iid, ncls;
+    uint32_t cls;        // per class: first position | size << 16 (uint32 each)
+};
+
+__device__ __forceinline__ uint4 &lds_rec(uint32_t p) {
+    return reinterpret_cast<uint4 *>(xs_lds)[p];
+}
+__device__ __forceinline__ uint32_t &lds_u32(uint32_t off) {
+    return *reinterpret_cast<uint32_t *>(xs_lds + off);
+}
+__device__ __forceinline__ uint4 lds_ld16(uint32_t base, uint32_t off) {
+    return *reinterpret_cast<const uint4 *>(xs_lds + base + off);
+}
+
+// Acceptance bits of sweep t: one Philox call per (position, block) gives the eight 16-bit draws
+// of the block's eight groups.
+template <int NT>
+__device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t rb) {
+    for (uint32_t q = T.tid; q < T.n * T.B; q += NT) {
+        const uint32_t p = q >> T.lB, b = q & (T.B - 1);
+        const uint32_t i = (lds_rec(p).w >> 16) & 0x1FFFu;
+        const uint4 o = philox10(make_uint4(i, t, T.blk0 + b, T.iid), T.key0, T.key1);
+        const uint32_t thr = T.thr;
+        const uint32_t bits = below(o.x & 0xFFFFu, thr) | below(o.x >> 16, thr) << 1 |
+                              below(o.y & 0xFFFFu, thr) << 2 | below(o.y >> 16, thr) << 3 |
+                              below(o.z & 0xFFFFu, thr) << 4 | below(o.z >> 16, thr) << 5 |
+                              below(o.w & 0xFFFFu, thr) << 6 | below(o.w >> 16, thr) << 7;
+        xs_lds[rb + q] = (uint8_t)bits;
+    }
+}
+
+// One task: the spin whose record is r, this thread's 16-byte column (four 32-clone words).
+template <bool kAcc>
+__device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, uint32_t rb,
+                                            uint32_t (&acc)[4]) {
+    const uint32_t self = r.x & 0xFFFFu;
+    const uint4 x = lds_ld16(T.colbase, self);
+    const uint4 a1 = lds_ld16(T.colbase, r.x >> 16);
+    const uint4 b1 = lds_ld16(T.colbase, r.y & 0xFFFFu);
+    const uint4 a2 = lds_ld16(T.colbase, r.y >> 16);
+    const uint4 b2 = lds_ld16(T.colbase, r.z & 0xFFFFu);
+    const uint4 a3 = lds_ld16(T.colbase, r.z >> 16);
+    const uint4 b3 = lds_ld16(T.colbase, r.w & 0xFFFFu);
+    const uint32_t meta = r.w >> 16;
+    const uint32_t j1 = 0u - ((meta >> 13) & 1u);
+    const uint32_t j2 = 0u - ((meta >> 14) & 1u);
+    const uint32_t j3 = 0u - (meta >> 15);
+    const uint32_t nib = (uint32_t)xs_lds[rb + (p << T.lB) + T.rb_sel] >> T.rb_shift;
+    uint4 y;
+    y.x = qg_word<kAcc>(x.x, a1.x, b1.x, a2.x, b2.x, a3.x, b3.x, j1, j2, j3, 0u - (nib & 1u),
+                        acc[0]);
+    y.y = qg_word<kAcc>(x.y, a1.y, b1.y, a2.y, b2.y, a3.y, b3.y, j1, j2, j3,
+                        0u - ((nib >> 1) & 1u), acc[1]);
+    y.z = qg_word<kAcc>(x.z, a1.z, b1.z, a2.z, b2.z, a3.z, b3.z, j1, j2, j3,
+                        0u - ((nib >> 2) & 1u), acc[2]);
+    y.w = qg_word<kAcc>(x.w, a1.w, b1.w, a2.w, b2.w, a3.w, b3.w, j1, j2, j3,
+                        0u - ((nib >> 3) & 1u), acc[3]);
+    *reinterpret_cast<uint4 *>(xs_lds + T.colbase + self) = y;
+}
+
+// The classes of one sweep, a barrier before each (the first one also publishes the sweep's
+// acceptance bits and the previous sweep's last writes). Records and class descriptors are
+// read-only, so each thread fetches its first record of a class before that class's barrier.
+template <int NT, bool kAcc>
+__device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[4]) {
+    uint32_t cd = lds_u32(T.cls);
+    for (uint32_t c = 0; c < T.ncls; ++c) {
+        const uint32_t cs = cd & 0xFFFFu;
+        const uint32_t ntask = (cd >> 16) << T.lcol;
+        const uint32_t p0 = cs + (T.tid >> T.lcol);
+        uint4 r0 = make_uint4(0, 0, 0, 0);
+        if (T.tid < ntask) r0 = lds_rec(p0);
+        if (c + 1 < T.ncls) cd = lds_u32(T.cls + 4 * (c + 1));
+        __syncthreads();
+        if (T.tid < ntask) update_task<kAcc>(T, r0, p0, rb, acc);
+        for (uint32_t q = T.tid + NT; q < ntask; q += NT) {
+            const uint32_t p = cs + (q >> T.lcol);
+            update_task<kAcc>(T, lds_rec(p), p, rb, acc);
+        }
+    }
+}
+
+// k >= 1 for any visited spin, over every spin of the current LDS state (no update): a zero
+// bit marks a clone whose configuration is a ground state.
+template <int NT>
+__device__ __forceinline__ void unsat_any(const Tile &T, uint32_t (&acc)[4]) {
+    for (uint32_t q = T.tid; q < T.n << T.lcol; q += NT) {
+        const uint4 r = lds_rec(q >> T.lcol);
+        const uint4 x = lds_ld16(T.colbase, r.x & 0xFFFFu);
+        const uint4 a1 = lds_ld16(T.colbase, r.x >> 16);
+        const uint4 b1 = lds_ld16(T.colbase, r.y & 0xFFFFu);
+        const uint4 a2 = lds_ld16(T.colbase, r.y >> 16);
+        const uint4 b2 = lds_ld16(T.colbase, r.z & 0xFFFFu);
+        const uint4 a3 = lds_ld16(T.colbase, r.z >> 16);
+        const uint4 b3 = lds_ld16(T.colbase, r.w & 0xFFFFu);
+        const uint32_t meta = r.w >> 16;
+        const uint32_t j1 = 0u - ((meta >> 13) & 1u);
+        const uint32_t j2 = 0u - ((meta >> 14) & 1u);
+        const uint32_t j3 = 0u - (meta >> 15);
+        qg_word<true>(x.x, a1.x, b1.x, a2.x, b2.x, a3.x, b3.x, j1, j2, j3, 0u, acc[0]);
+        qg_word<true>(x.y, a1.y, b1.y, a2.y, b2.y, a3.y, b3.y, j1, j2, j3, 0u, acc[1]);
+        qg_word<true>(x.z, a1.z, b1.z, a2.z, b2.z, a3.z, b3.z, j1, j2, j3, 0u, acc[2]);
+        qg_word<true>(x.w, a1.w, b1.w, a2.w, b2.w, a3.w, b3.w, j1, j2, j3, 0u, acc[3]);
+    }
+}
+
+// OR the threads' accumulators into the per-group LDS words (threads owning the same column
+// first combine within the wave). Caller synchronises before reading T.acc.
+__device__ __forceinline__ void reduce_acc(const Tile &T, uint32_t (&acc)[4]) {
+    for (uint32_t m = T.ncol; m < 64; m <<= 1)
+        for (int g = 0; g < 4; ++g) acc[g] |= __shfl_xor(acc[g], (int)m);
+    if ((T.tid & 63) < T.ncol)
+        for (int g = 0; g < 4; ++g) atomicOr(&lds_u32(T.acc + 4 * (4 * T.col + g)), acc[g]);
+}
+
+// Record first hits at sweep t for the clones of group T.tid (threads below ngrp) whose bit
+// in the group's accumulator is zero and that had no hit yet, and flag the instance. Returns
+// the new hits.
+__device__ __forceinline__ uint32_t record_hits(const Tile &T, uint32_t t, uint32_t &hm) {
+    const uint32_t v = lds_u32(T.acc + 4 * T.tid);
+    lds_u32(T.acc + 4 * T.tid) = 0;
+    uint32_t fresh = ~v & ~hm;
+    const uint32_t out = fresh;
+    if (fresh) {
+        int32_t *fh = T.I->first_hit + ((size_t)(T.blk0 * 8 + T.tid) << 5);
+        hm |= fresh;
+        while (fresh) {
+            fh[__builtin_ctz(fresh)] = (int32_t)t;
+            fresh &= fresh - 1;
+        }
+        atomicOr(const_cast<uint32_t *>(&T.I->hit), 1u);
+    }
+    return out;
+}
+
+// Ground-state check of the current LDS state, recording hits at sweep t. Returns nonzero in
+// every thread if some clone of the tile got a new hit. Ends synchronised.
+template <int NT>
+__device__ __forceinline__ uint32_t check_state(const Tile &T, uint32_t t, uint32_t &hm) {
+    uint32_t acc[4] = {0, 0, 0, 0};
+    __syncthreads();  // state final, accumulators clear
+    unsat_any<NT>(T, acc);
+    reduce_acc(T, acc);
+    if (T.tid == 0) lds_u32(T.flag) = 0;
+    __syncthreads();
+    if (T.tid < T.ngrp && record_hits(T, t, hm)) atomicOr(&lds_u32(T.flag), 1u);
+    __syncthreads();
+    return lds_u32(T.flag);
+}
+
+template <int NT>
+__device__ __forceinline__ void load_state(const Tile &T) {
+    const uint4 *src0 = reinterpret_cast<const uint4 *>(T.I->state + 4 * (size_t)T.blk0);
+    for (uint32_t q = T.tid; q < T.n * T.ncol; q += NT) {
+        const uint32_t i = q >> T.lcol, k = q & (T.ncol - 1);
+        const uint4 *src = src0 + ((size_t)i * T.W >> 1);
+        *reinterpret_cast<uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k) = src[k];
+    }
+}
+
 // K sweeps (or fewer at the budget end) of one workgroup tile. The grid holds every tile of
 // every instance of the batch; tiles of finished instances return at once.
-__global__ __launch_bounds__(kThreads) void qg_chunk(const InstDev *__restrict__ insts,
-                                                     const uint2 *__restrict__ tiles) {
-    extern __shared__ __align__(16) uint8_t smem[];
+//
+// The hot loop does not track ground states. After the chunk every clone is tested once; with
+// w0 = 0 a ground state is never left, so a clone in a ground state now that had no hit before
+// reached it during this chunk. Only then the chunk is replayed from its start state (still
+// unchanged in global memory: the tile is written back at the end) with a per-sweep test, which
+// gives the exact first sweep; the replay draws the same random numbers, so it reproduces the
+// same trajectory.
+template <int NT>
+__global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts,
+                                               const uint2 *__restrict__ tiles) {
     const uint2 tile = tiles[blockIdx.x];
     const InstDev *I = insts + tile.x;
     if (I->done) return;
@@ -133,137 +313,111 @@ __global__ __launch_bounds__(kThreads) void qg_chunk(const InstDev *__restrict__
     const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
     if (t0 >= t1) return;
 
-    const uint32_t n = I->n, W = I->n_words;
-    const uint32_t B = I->tile_blocks, lB = I->log2_tile_blocks;
-    const uint32_t rowb = B << 5;      // bytes per spin row of the tile
-    const uint32_t ncol = B << 1;      // 16-byte columns per row
-    const uint32_t lcol = lB + 1;
-    const uint32_t ngrp = B << 3;      // 32-clone groups in the tile
-    const uint32_t blk0 = tile.y;
-    const uint32_t tid = threadIdx.x;
-
-    uint4 *rec_l = reinterpret_cast<uint4 *>(smem);
-    uint8_t *st_l = smem + lds_rec_bytes(n);
-    uint8_t *rb_l = st_l + (size_t)n * rowb;
-    uint32_t *acc_l = reinterpret_cast<uint32_t *>(rb_l + align16((size_t)n * B));
+    Tile T;
+    T.I = I;
+    T.n = I->n;
+    T.W = I->n_words;
+    T.B = I->tile_blocks;
+    T.lB = I->log2_tile_blocks;
+    T.rowb = T.B << 5;
+    T.ncol = T.B << 1;
+    T.lcol = T.lB + 1;
+    T.ngrp = T.B << 3;
+    T.blk0 = tile.y;
+    T.tid = threadIdx.x;
+    T.col = T.tid & (T.ncol - 1);  // fixed per thread: NT is a multiple of ncol
+    T.st = (uint32_t)lds_rec_bytes(T.n);
+    const uint32_t rbb = (uint32_t)align16((size_t)T.n * T.B);
+    T.rb0 = T.st + T.n * T.rowb;
+    T.rb1 = T.rb0 + rbb;
+    T.acc = T.rb1 + rbb;
+    T.flag = T.acc + 4 * T.ngrp;
+    T.cls = T.flag + 16;
+    T.colbase = T.st + (T.col << 4);
+    T.rb_sel = T.col >> 1;
+    T.rb_shift = (T.col & 1) << 2;
+    T.thr = I->thr;
+    T.key0 = I->seed_lo;
+    T.key1 = I->seed_hi;
+    T.iid = I->inst_id;
+    T.ncls = I->n_classes;
+    for (uint32_t c = T.tid; c < T.ncls; c += NT) {
+        const uint32_t a = (uint32_t)I->class_off[c], b = (uint32_t)I->class_off[c + 1];
+        lds_u32(T.cls + 4 * c) = a | ((b - a) << 16);
+    }
 
     // Records: spin indices -> byte offsets of the rows in this tile.
-    for (uint32_t p = tid; p < n; p += kThreads) {
+    for (uint32_t p = T.tid; p < T.n; p += NT) {
         const uint4 r = I->rec[p];
+        const uint32_t rowb = T.rowb;
         const uint32_t i = r.x & 0xFFFFu;
         uint4 o;
         o.x = (i * rowb) | (((r.x >> 16) * rowb) << 16);
         o.y = ((r.y & 0xFFFFu) * rowb) | (((r.y >> 16) * rowb) << 16);
         o.z = ((r.z & 0xFFFFu) * rowb) | (((r.z >> 16) * rowb) << 16);
         o.w = ((r.w & 0xFFFFu) * rowb) | ((i | ((r.w >> 16) << 13)) << 16);
-        rec_l[p] = o;
+        lds_rec(p) = o;
     }
-    // State tile: row i holds words [4*blk0, 4*blk0 + 4*B).
-    for (uint32_t q = tid; q < n * ncol; q += kThreads) {
-        const uint32_t i = q >> lcol, k = q & (ncol - 1);
-        const uint4 *src = reinterpret_cast<const uint4 *>(I->state + (size_t)i * W + 4 * blk0);
-        *reinterpret_cast<uint4 *>(st_l + i * rowb + 16 * k) = src[k];
-    }
+    load_state<NT>(T);
     // Groups of the tile already in a ground state keep their recorded first hit.
     uint32_t hm = 0;
-    if (tid < ngrp) {
-        const int32_t *fh = I->first_hit + ((size_t)(blk0 * 8 + tid) << 5);
+    if (T.tid < T.ngrp) {
+        const int32_t *fh = I->first_hit + ((size_t)(T.blk0 * 8 + T.tid) << 5);
         for (int b = 0; b < 32; ++b) hm |= (fh[b] >= 0 ? 1u : 0u) << b;
-        acc_l[tid] = 0;
+        lds_u32(T.acc + 4 * T.tid) = 0;
     }
-    __syncthreads();
+    __syncthreads();  // records, state and accumulators visible to every thread
+    if (t0 == I->t_start) check_state<NT>(T, t0, hm);  // the run's start configuration
 
-    const uint32_t thr = I->thr, key0 = I->seed_lo, key1 = I->seed_hi, iid = I->inst_id;
-    const uint32_t ncls = I->n_classes;
-    const int32_t *coff = I->class_off;
-    const uint32_t col = tid & (ncol - 1);  // fixed per thread: kThreads is a multiple of ncol
-    const uint8_t *colbase = st_l + (col << 4);
-    const uint32_t rb_sel = col >> 1, rb_shift = (col & 1) << 2;
-
-    for (uint32_t t = t0; t < t1; ++t) {
-        // Acceptance bits of this sweep: one Philox call per (position, block) gives the eight
-        // 16-bit draws of the block's eight groups.
-        for (uint32_t q = tid; q < n * B; q += kThreads) {
-            const uint32_t p = q >> lB, b = q & (B - 1);
-            const uint32_t i = (rec_l[p].w >> 16) & 0x1FFFu;
-            const uint4 o = philox10(make_uint4(i, t, blk0 + b, iid), key0, key1);
-            uint32_t bits = below(o.x & 0xFFFFu, thr) | below(o.x >> 16, thr) << 1 |
-                            below(o.y & 0xFFFFu, thr) << 2 | below(o.y >> 16, thr) << 3 |
-                            below(o.z & 0xFFFFu, thr) << 4 | below(o.z >> 16, thr) << 5 |
-                            below(o.w & 0xFFFFu, thr) << 6 | below(o.w >> 16, thr) << 7;
-            rb_l[q] = (uint8_t)bits;
+    if (I->track) {
+        // This instance keeps producing new ground-state clones: test every sweep.
+        uint32_t hm_t = hm;
+        accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+        for (uint32_t t = t0; t < t1; ++t) {
+            uint32_t acc[4] = {0, 0, 0, 0};
+            sweep<NT, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+            reduce_acc(T, acc);
+            __syncthreads();
+            if (T.tid < T.ngrp) record_hits(T, t, hm_t);
+            if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
-        __syncthreads();
-
-        uint32_t acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-        for (uint32_t c = 0; c < ncls; ++c) {
-            const uint32_t cs = (uint32_t)coff[c];
-            const uint32_t ntask = ((uint32_t)coff[c + 1] - cs) << lcol;
-            for (uint32_t q = tid; q < ntask; q += kThreads) {
-                const uint32_t p = cs + (q >> lcol);
-                const uint4 r = rec_l[p];
-                const uint32_t self = r.x & 0xFFFFu;
-                const uint4 x = lds_ld16(colbase, self);
-                const uint4 a1 = lds_ld16(colbase, r.x >> 16);
-                const uint4 b1 = lds_ld16(colbase, r.y & 0xFFFFu);
-                const uint4 a2 = lds_ld16(colbase, r.y >> 16);
-                const uint4 b2 = lds_ld16(colbase, r.z & 0xFFFFu);
-                const uint4 a3 = lds_ld16(colbase, r.z >> 16);
-                const uint4 b3 = lds_ld16(colbase, r.w & 0xFFFFu);
-                const uint32_t meta = r.w >> 16;
-                const uint32_t j1 = 0u - ((meta >> 13) & 1u);
-                const uint32_t j2 = 0u - ((meta >> 14) & 1u);
-                const uint32_t j3 = 0u - (meta >> 15);
-                const uint32_t nib = (uint32_t)rb_l[(p << lB) + rb_sel] >> rb_shift;
-                uint4 y;
-                y.x = qg_word(x.x, a1.x, b1.x, a2.x, b2.x, a3.x, b3.x, j1, j2, j3,
-                              0u - (nib & 1u), acc0);
-                y.y = qg_word(x.y, a1.y, b1.y, a2.y, b2.y, a3.y, b3.y, j1, j2, j3,
-                              0u - ((nib >> 1) & 1u), acc1);
-                y.z = qg_word(x.z, a1.z, b1.z, a2.z, b2.z, a3.z, b3.z, j1, j2, j3,
-                              0u - ((nib >> 2) & 1u), acc2);
-                y.w = qg_word(x.w, a1.w, b1.w, a2.w, b2.w, a3.w, b3.w, j1, j2, j3,
-                              0u - ((nib >> 3) & 1u), acc3);
-                *reinterpret_cast<uint4 *>(const_cast<uint8_t *>(colbase) + self) = y;
+        hm = hm_t;
+        check_state<NT>(T, t1, hm);
+    } else {
+        uint32_t none[4] = {0, 0, 0, 0};  // unused: this loop tracks no ground states
+        accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+        for (uint32_t t = t0; t < t1; ++t) {
+            sweep<NT, false>(T, (t & 1) ? T.rb1 : T.rb0, none);
+            if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+        }
+        if (check_state<NT>(T, t1, hm)) {
+            // Replay from the chunk's start state with a per-sweep ground-state test.
+            uint32_t hm_replay = 0;  // hits before this chunk; the end check's are redone
+            if (T.tid < T.ngrp) {
+                const int32_t *fh = I->first_hit + ((size_t)(T.blk0 * 8 + T.tid) << 5);
+                for (int b = 0; b < 32; ++b)
+                    hm_replay |= (fh[b] >= 0 && fh[b] < (int32_t)t1 ? 1u : 0u) << b;
             }
             __syncthreads();
-        }
-
-        // OR over the threads that own the same column, then per group.
-        for (uint32_t m = ncol; m < 64; m <<= 1) {
-            acc0 |= __shfl_xor(acc0, (int)m);
-            acc1 |= __shfl_xor(acc1, (int)m);
-            acc2 |= __shfl_xor(acc2, (int)m);
-            acc3 |= __shfl_xor(acc3, (int)m);
-        }
-        if ((tid & 63) < ncol) {
-            atomicOr(&acc_l[4 * col + 0], acc0);
-            atomicOr(&acc_l[4 * col + 1], acc1);
-            atomicOr(&acc_l[4 * col + 2], acc2);
-            atomicOr(&acc_l[4 * col + 3], acc3);
-        }
-        __syncthreads();
-        if (tid < ngrp) {
-            const uint32_t v = acc_l[tid];
-            acc_l[tid] = 0;
-            uint32_t fresh = ~v & ~hm;
-            if (fresh) {
-                int32_t *fh = I->first_hit + ((size_t)(blk0 * 8 + tid) << 5);
-                hm |= fresh;
-                while (fresh) {
-                    const int b = __builtin_ctz(fresh);
-                    fh[b] = (int32_t)t;
-                    fresh &= fresh - 1;
-                }
-                atomicOr(const_cast<uint32_t *>(&I->hit), 1u);
+            load_state<NT>(T);
+            accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+            for (uint32_t t = t0; t < t1; ++t) {
+                uint32_t acc[4] = {0, 0, 0, 0};
+                sweep<NT, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+                reduce_acc(T, acc);
+                __syncthreads();
+                if (T.tid < T.ngrp) record_hits(T, t, hm_replay);
+                if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
             }
+            if (T.tid == 0) atomicOr(const_cast<uint32_t *>(&I->track), 1u);
         }
     }
     __syncthreads();
-    for (uint32_t q = tid; q < n * ncol; q += kThreads) {
-        const uint32_t i = q >> lcol, k = q & (ncol - 1);
-        uint4 *dst = reinterpret_cast<uint4 *>(I->state + (size_t)i * W + 4 * blk0);
-        dst[k] = *reinterpret_cast<const uint4 *>(st_l + i * rowb + 16 * k);
+    uint4 *dst0 = reinterpret_cast<uint4 *>(I->state + 4 * (size_t)T.blk0);
+    for (uint32_t q = T.tid; q < T.n * T.ncol; q += NT) {
+        const uint32_t i = q >> T.lcol, k = q & (T.ncol - 1);
+        (dst0 + ((size_t)i * T.W >> 1))[k] =
+            *reinterpret_cast<const uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k);
     }
 }
 
@@ -352,8 +506,9 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 
 }  // namespace
 
-size_t chunk_lds_bytes(uint32_t n, uint32_t B) {
-    return lds_rec_bytes(n) + (size_t)n * B * 32 + align16((size_t)n * B) + (size_t)B * 8 * 4;
+size_t chunk_lds_bytes(uint32_t n, uint32_t B, uint32_t n_classes) {
+    return lds_rec_bytes(n) + (size_t)n * B * 32 + 2 * align16((size_t)n * B) +
+           (size_t)B * 8 * 4 + 16 + 4 * (size_t)n_classes;
 }
 
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
@@ -363,18 +518,31 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
-                        size_t lds_bytes, hipStream_t s) {
+template <int NT>
+hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+                           size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk<NT>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(qg_chunk, dim3(n_tiles), dim3(kThreads), lds_bytes, s, d_insts, d_tiles);
+    hipLaunchKernelGGL(qg_chunk<NT>, dim3(n_tiles), dim3(NT), lds_bytes, s, d_insts, d_tiles);
     return hipGetLastError();
+}
+
+hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
+                        size_t lds_bytes, hipStream_t s) {
+    switch (threads) {
+        case 64: return launch_chunk_nt<64>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 128: return launch_chunk_nt<128>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 256: return launch_chunk_nt<256>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 512: return launch_chunk_nt<512>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 1024: return launch_chunk_nt<1024>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s) {

@@ -7,8 +7,7 @@
 
 namespace xs {
 
-constexpr int kThreads = 256;      // threads per sweep workgroup (4 wave64)
-constexpr int kMaxTileBlocks = 32; // 256-clone blocks per workgroup tile (8*B groups <= threads)
+constexpr int kMaxTileBlocks = 32; // 256-clone blocks per workgroup tile
 constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
 
 // One instance of a batched run as the kernels see it. Lives in device memory; the host fills
@@ -33,7 +32,9 @@ struct InstDev {
     uint32_t hit;     // nonzero once some clone was seen in a ground state
     int32_t tts;      // min first_hit (final pass)
     int32_t winner;   // lowest clone with first_hit == tts (final pass)
-    uint32_t pad[3];
+    uint32_t wg_threads;  // workgroup size of this instance's chunk launches (host side)
+    uint32_t track;       // nonzero once a chunk had to be replayed: later chunks test every sweep
+    uint32_t pad;
 };
 
 }  // namespace xs
@@ -41,9 +42,11 @@ struct InstDev {
 // Launch wrappers implemented in kernels.hip (C++ linkage, internal to the library).
 namespace xs {
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
-hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+// threads: 64, 128, 256, 512 or 1024; a multiple of 2 * tile_blocks of every tile it runs
+// and at least 8 * tile_blocks.
+hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
                         size_t lds_bytes, hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
 hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
-size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks);
+size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, uint32_t n_classes);
 }  // namespace xs

@@ -40,7 +40,8 @@ class RunConfig(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("n_clones", ctypes.c_uint32),
                 ("accept_thr", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("max_sweeps", ctypes.c_uint32), ("start_sweep", ctypes.c_uint32),
-                ("chunk_sweeps", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32)]
+                ("chunk_sweeps", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
+                ("wg_threads", ctypes.c_uint32)]
 
 
 class RunBuffers(ctypes.Structure):
@@ -51,8 +52,8 @@ class RunBuffers(ctypes.Structure):
 class RunResult(ctypes.Structure):
     _fields_ = [("tts_sweeps", ctypes.c_int64), ("winner_clone", ctypes.c_int32),
                 ("end_sweep", ctypes.c_uint32), ("sweeps_done", ctypes.c_uint32),
-                ("tile_blocks", ctypes.c_uint32), ("clone_spin_updates", ctypes.c_uint64),
-                ("seconds", ctypes.c_double)]
+                ("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
+                ("clone_spin_updates", ctypes.c_uint64), ("seconds", ctypes.c_double)]
 
 
 class KernelStats(ctypes.Structure):
@@ -155,6 +156,7 @@ class RunOutput:
     end_sweep: int
     sweeps_done: int
     tile_blocks: int
+    wg_threads: int
     clone_spin_updates: int
     seconds: float
     state: object        # torch int64 [n][n_clones/64] on the device
@@ -165,10 +167,12 @@ class RunOutput:
 
 def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: int = 3604,
                 max_sweeps: int = 100000, stop_on_first: bool = True, resume: bool = False,
-                start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0) -> RunConfig:
+                start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0,
+                wg_threads: int = 0) -> RunConfig:
     flags = (XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0)
     return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
-                     accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks)
+                     accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks,
+                     wg_threads)
 
 
 def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
@@ -189,7 +193,8 @@ def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
 
 def _output(res: RunResult, state, first_hit, energy, solved) -> RunOutput:
     return RunOutput(int(res.tts_sweeps), int(res.winner_clone), int(res.end_sweep),
-                     int(res.sweeps_done), int(res.tile_blocks), int(res.clone_spin_updates),
+                     int(res.sweeps_done), int(res.tile_blocks), int(res.wg_threads),
+                     int(res.clone_spin_updates),
                      float(res.seconds), state, first_hit, energy,
                      solved if res.winner_clone >= 0 else None)
 

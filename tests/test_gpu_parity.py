@@ -119,10 +119,14 @@ def test_tiling_is_result_neutral():
     inst = planted_instance(128, 9)
     h = xorsat.Instance(inst.tri, inst.J)
     outs = []
-    for B in (1, 2, 4, 8, 16):
+    for B, T in ((1, 0), (2, 0), (4, 0), (8, 0), (16, 0), (1, 64), (2, 128), (4, 1024),
+                 (8, 256), (16, 256)):
         cfg = xorsat.make_config(n_clones=8192, seed=99, instance_id=1, max_sweeps=300,
-                                 stop_on_first=False, tile_blocks=B, chunk_sweeps=64)
-        outs.append(xorsat.run(h, cfg))
+                                 stop_on_first=False, tile_blocks=B, chunk_sweeps=64,
+                                 wg_threads=T)
+        out = xorsat.run(h, cfg)
+        assert out.tile_blocks == B and out.wg_threads == (T or out.wg_threads)
+        outs.append(out)
     for o in outs[1:]:
         assert torch.equal(o.state, outs[0].state)
         assert torch.equal(o.first_hit, outs[0].first_hit)
