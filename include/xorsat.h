@@ -164,6 +164,98 @@ xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_
                        const xs_run_buffers *bufs, void *stream, xs_run_result *results);
 
 /*
+ * Server: continuous batching of many runs on one device. Requests are queued by
+ * xs_server_submit; each xs_server_step admits queued requests in arrival order while their
+ * device footprint (state n*n_clones/8 bytes, first_hit and energy 4*n_clones bytes each, n
+ * bytes of solved spins) fits the server's memory budget and resident limit, runs one chunk of
+ * sweeps (each request's own chunk_sweeps) over every resident request in the same launches,
+ * and completes the requests that ended: their final pass runs, results are copied into the
+ * host buffers given at submission and their device memory is released. Admission, tiling and
+ * the mix of other requests never change a request's results: each one is bit-identical to
+ * xs_run with the same instance and configuration (its random numbers are keyed by its own
+ * seed and instance_id). The instance must stay alive until the request completed. Not
+ * thread-safe: drive one server from one thread. XS_RESUME is not supported here.
+ */
+typedef struct xs_server xs_server;
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t max_resident;     /* requests resident at once (0 = no limit besides memory) */
+    uint64_t hbm_budget_bytes; /* device bytes the resident requests may hold */
+} xs_server_config;
+
+/* Host buffers filled when a request completes; each may be NULL. */
+typedef struct {
+    uint64_t *state;    /* [n][n_clones/64] final configuration */
+    int32_t *first_hit; /* [n_clones] */
+    int32_t *energy;    /* [n_clones] */
+    int8_t *solved;     /* [n] spins of the winner (unchanged if no clone hit) */
+} xs_server_outputs;
+
+typedef struct {
+    uint64_t ticket;
+    xs_status status;      /* XS_OK, XS_ECANCELED, or XS_ENOMEM if it can never fit the budget */
+    xs_run_result result;  /* result.seconds = submission to completion */
+    double queued_s;       /* submission to admission */
+} xs_server_completion;
+
+typedef struct {
+    uint64_t steps, admitted, completed, pending, resident;
+    uint64_t clone_spin_updates; /* sweeps run by all requests so far */
+    uint64_t bytes_in_use;       /* device bytes held by resident requests */
+    double step_seconds;         /* wall time spent inside xs_server_step */
+} xs_server_stats;
+
+xs_status xs_server_create(const xs_server_config *cfg, void *stream, xs_server **out);
+/* Releases every request's device memory; pending and resident requests are dropped. */
+void xs_server_destroy(xs_server *srv);
+/* Queue a request; the configuration and output pointers are copied, the instance is not.
+ * XS_EINVAL for an invalid configuration. */
+xs_status xs_server_submit(xs_server *srv, const xs_instance *inst, const xs_run_config *cfg,
+                           const xs_server_outputs *outs, uint64_t *ticket);
+/* One scheduling step (see above). n_active receives resident + pending requests after it. */
+xs_status xs_server_step(xs_server *srv, int32_t *n_active);
+/* Move up to cap completions (oldest first) into done[]; n_done receives how many. */
+xs_status xs_server_poll(xs_server *srv, xs_server_completion *done, int32_t cap,
+                         int32_t *n_done);
+/* Cancel a queued or resident request (it completes with XS_ECANCELED at the next step).
+ * XS_ENOTFOUND if the ticket is unknown or already completed. */
+xs_status xs_server_cancel(xs_server *srv, uint64_t ticket);
+xs_status xs_server_get_stats(const xs_server *srv, xs_server_stats *out);
+
+/*
+ * Autotuner of the result-neutral launch knobs (tile_blocks: clones per workgroup, in blocks of
+ * 256; wg_threads: threads per workgroup, which sets how many spins of a colour class a thread
+ * handles per step). It times every valid pair with short budget runs of `count` copies of
+ * `inst` (fewer if their state would exceed 2 GiB) on `stream`, using HIP events around the
+ * sweep launches, and records the fastest pair for workloads of the same N (rounded up to a
+ * power of two), clone count and batch size (rounded up to a power of two, at most 64). Later
+ * runs whose config leaves both knobs 0 use the recorded pair. Allocates and frees its own
+ * device buffers. Results of any run never depend on these knobs.
+ */
+#define XS_TUNE_MAX_TRIALS 32
+typedef struct {
+    uint32_t tile_blocks, wg_threads;
+    double updates_per_ns; /* sweep-kernel rate of this trial */
+} xs_tune_trial;
+
+typedef struct {
+    uint32_t tile_blocks, wg_threads; /* the fastest pair */
+    double updates_per_ns;
+    int32_t n_trials;
+    xs_tune_trial trials[XS_TUNE_MAX_TRIALS];
+} xs_tune_result;
+
+xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count, void *stream,
+                      xs_tune_result *out);
+/* Write / read the recorded pairs as text ("n_bucket clones count_bucket B T rate" lines).
+ * Loading adds to (and overrides) the table in memory. */
+xs_status xs_tune_save(const char *path);
+xs_status xs_tune_load(const char *path);
+/* Forget every recorded pair. */
+xs_status xs_tune_clear(void);
+
+/*
  * Launch timing of the sweep kernel, for measurement tools. When enabled, the library records
  * a pair of HIP events on the run's stream around every sweep-chunk launch and adds the
  * elapsed times once the run has synchronised. Counters are process-wide.

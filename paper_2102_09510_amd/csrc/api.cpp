@@ -11,14 +11,17 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/xorsat.h"
-#include "xs_internal.h"
+#include "xs_host.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace xsh {
 
 xs_status fail(xs_status st, const char *fmt, ...) {
     char buf[512];
@@ -30,12 +33,12 @@ xs_status fail(xs_status st, const char *fmt, ...) {
     return st;
 }
 
-#define XS_HIP(call)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (call);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(XS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
-    } while (0)
+}  // namespace xsh
+
+using xsh::DeviceTables;
+using xsh::fail;
+
+namespace {
 
 struct ProfileState {
     std::mutex mu;
@@ -44,29 +47,9 @@ struct ProfileState {
 };
 ProfileState g_prof;
 
-struct DeviceTables {
-    uint4 *rec = nullptr;
-    int32_t *class_off = nullptr;
-    uint2 *tri = nullptr;
-};
-
 }  // namespace
 
-struct xs_instance {
-    int32_t n = 0;
-    int32_t cap = 32;
-    std::vector<int32_t> tri;        // [n][3]
-    std::vector<int8_t> J;           // [n]
-    std::vector<int32_t> perm;       // update order
-    std::vector<int32_t> class_off;  // [n_classes + 1]
-    std::vector<uint16_t> rec;       // [n][8] in update order
-    std::vector<uint16_t> tri16;     // [n][4]: a, b, c, j
-    int32_t max_class = 0;
-    std::mutex mu;
-    std::map<int, DeviceTables> dev;  // per HIP device
-};
-
-namespace {
+namespace xsh {
 
 // Greedy partition into independent sets of at most `cap` spins: repeated ascending scans; a
 // scan adds an unassigned spin unless the set is full or the spin shares a triplet with a spin
@@ -174,7 +157,8 @@ uint32_t max_tile_blocks(uint32_t n, uint32_t n_blocks, uint32_t max_nb) {
 // has fewer than kTargetTiles workgroups, so that small batches still spread over the CUs.
 constexpr size_t kTargetTiles = 1024;
 
-xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b) {
+xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b,
+                       bool check_buffers) {
     if (!I || !cfg || !b) return fail(XS_EINVAL, "null argument");
     if (cfg->struct_size < sizeof(xs_run_config))
         return fail(XS_EINVAL, "xs_run_config.struct_size %u < %zu", cfg->struct_size,
@@ -187,8 +171,12 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
         return fail(XS_EINVAL, "unknown flags 0x%x", cfg->flags);
     if ((uint64_t)cfg->start_sweep + cfg->max_sweeps >= 0xFFFFFFFFull)
         return fail(XS_EINVAL, "start_sweep + max_sweeps must stay below 2^32 - 1");
-    if (!b->state || !b->first_hit) return fail(XS_EINVAL, "state and first_hit are required");
-    if (((uintptr_t)b->state & 15) != 0) return fail(XS_EINVAL, "state must be 16-byte aligned");
+    if (check_buffers) {
+        if (!b->state || !b->first_hit)
+            return fail(XS_EINVAL, "state and first_hit are required");
+        if (((uintptr_t)b->state & 15) != 0)
+            return fail(XS_EINVAL, "state must be 16-byte aligned");
+    }
     const uint32_t nb = cfg->n_clones / 256;
     if (cfg->tile_blocks) {
         const uint32_t B = cfg->tile_blocks;
@@ -214,52 +202,102 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
 // full 32-spin class, within [256, 1024].
 uint32_t default_threads(uint32_t B) { return std::min(1024u, std::max(256u, 64u * B)); }
 
-xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
-                    const xs_run_buffers *bufs, hipStream_t stream, xs_run_result *results) {
-    const auto wall0 = std::chrono::steady_clock::now();
-    if (count <= 0 || !insts || !cfgs || !bufs || !results)
-        return fail(XS_EINVAL, "empty or null batch");
-    int device = 0;
-    XS_HIP(hipGetDevice(&device));
+// Options of one driver call beyond the public configuration.
+struct RunOpts {
+    bool graph = true;             // replay the chunk loop as a captured hipGraph
+    double *kernel_ms = nullptr;   // if set: time every sweep-chunk launch, add the sum here
+};
 
-    std::vector<xs::InstDev> h(count);
-    std::vector<uint2> tiles;
+// Tuned (tile_blocks, wg_threads) per workload key, filled by xs_autotune or xs_tune_load.
+struct TuneKey {
+    uint32_t n_bucket, clones, count_bucket;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(n_bucket, clones, count_bucket) <
+               std::tie(o.n_bucket, o.clones, o.count_bucket);
+    }
+};
+struct TuneVal {
+    uint32_t tile_blocks, wg_threads;
+    double rate;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+uint32_t pow2_ceil(uint32_t v) {
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+TuneKey tune_key(uint32_t n, uint32_t clones, int32_t count) {
+    return TuneKey{pow2_ceil(n), clones, std::min<uint32_t>(64, pow2_ceil((uint32_t)count))};
+}
+
+// Capture of the chunk loop: `group` chunk iterations recorded once on a private stream and
+// replayed on the caller's stream (the caller's stream may be the null stream, which cannot be
+// captured).
+struct ChunkGraph {
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int group = 0;
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        group = 0;
+    }
+    ~ChunkGraph() {
+        reset();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+void fill_desc(const xs_instance *I, const xs_run_config &c, const DeviceTables &t,
+               uint64_t *state, int32_t *first_hit, int32_t *energy, xs::InstDev &d) {
+    std::memset(&d, 0, sizeof d);
+    d.rec = t.rec;
+    d.class_off = t.class_off;
+    d.tri = t.tri;
+    d.state = state;
+    d.first_hit = first_hit;
+    d.energy = energy;
+    d.n = (uint32_t)I->n;
+    d.n_words = c.n_clones / 64;
+    d.n_classes = (uint32_t)I->class_off.size() - 1;
+    d.inst_id = c.instance_id;
+    d.thr = c.accept_thr;
+    d.seed_lo = (uint32_t)c.seed;
+    d.seed_hi = (uint32_t)(c.seed >> 32);
+    d.flags = c.flags;
+    d.t_start = c.start_sweep;
+    d.t_stop = c.start_sweep + c.max_sweeps;
+    d.chunk = c.chunk_sweeps ? c.chunk_sweeps : 100;
+    d.t_cur = c.start_sweep;
+    d.done = c.max_sweeps == 0 ? 1u : 0u;
+    d.tts = INT32_MAX;
+    d.winner = INT32_MAX;
+}
+
+xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs, int count,
+                         std::vector<uint2> &tiles, std::vector<TileGroup> &groups) {
     for (int k = 0; k < count; ++k) {
-        const xs_instance *I = insts[k];
         const xs_run_config &c = cfgs[k];
-        xs_status st = validate_run(I, &c, &bufs[k]);
-        if (st != XS_OK) return st;
-        DeviceTables t;
-        st = ensure_tables(const_cast<xs_instance *>(I), device, &t);
-        if (st != XS_OK) return st;
-        const uint32_t nb = c.n_clones / 256;
-        const uint32_t B = c.tile_blocks ? c.tile_blocks : max_tile_blocks(I->n, nb, 1024);
         xs::InstDev &d = h[k];
-        std::memset(&d, 0, sizeof d);
-        d.rec = t.rec;
-        d.class_off = t.class_off;
-        d.tri = t.tri;
-        d.state = bufs[k].state;
-        d.first_hit = bufs[k].first_hit;
-        d.energy = bufs[k].energy;
-        d.n = (uint32_t)I->n;
-        d.n_words = c.n_clones / 64;
-        d.n_classes = (uint32_t)I->class_off.size() - 1;
+        const uint32_t nb = c.n_clones / 256;
+        uint32_t B = c.tile_blocks ? c.tile_blocks : max_tile_blocks(d.n, nb, 1024);
+        uint32_t tuned_T = 0;
+        if (!c.tile_blocks && !c.wg_threads) {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune.find(tune_key(d.n, c.n_clones, count));
+            if (it != g_tune.end() && nb % it->second.tile_blocks == 0 &&
+                d.n * it->second.tile_blocks <= 2048) {
+                B = it->second.tile_blocks;
+                tuned_T = it->second.wg_threads;
+            }
+        }
         d.tile_blocks = B;
-        d.log2_tile_blocks = ilog2(B);
-        d.inst_id = c.instance_id;
-        d.thr = c.accept_thr;
-        d.seed_lo = (uint32_t)c.seed;
-        d.seed_hi = (uint32_t)(c.seed >> 32);
-        d.flags = c.flags;
-        d.t_start = c.start_sweep;
-        d.t_stop = c.start_sweep + c.max_sweeps;
-        d.chunk = c.chunk_sweeps ? c.chunk_sweeps : 100;
-        d.t_cur = c.start_sweep;
-        d.done = c.max_sweeps == 0 ? 1u : 0u;
-        d.hit = 0;
-        d.tts = INT32_MAX;
-        d.winner = INT32_MAX;
+        d.wg_threads = tuned_T;  // 0 unless tuned
     }
     // Shrink automatic tiles while the batch has too few workgroups.
     auto count_tiles = [&]() {
@@ -271,7 +309,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         if (count_tiles() >= kTargetTiles) break;
         bool changed = false;
         for (int k = 0; k < count; ++k)
-            if (!cfgs[k].tile_blocks && h[k].tile_blocks > 1) {
+            if (!cfgs[k].tile_blocks && !h[k].wg_threads && h[k].tile_blocks > 1) {
                 h[k].tile_blocks /= 2;
                 changed = true;
             }
@@ -283,7 +321,9 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
         d.log2_tile_blocks = ilog2(d.tile_blocks);
-        uint32_t T = cfgs[k].wg_threads ? cfgs[k].wg_threads : default_threads(d.tile_blocks);
+        uint32_t T = cfgs[k].wg_threads ? cfgs[k].wg_threads
+                     : d.wg_threads       ? d.wg_threads
+                                          : default_threads(d.tile_blocks);
         T = std::max(T, 8 * d.tile_blocks);
         d.wg_threads = T;
         const uint32_t nb = cfgs[k].n_clones / 256;
@@ -291,18 +331,42 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) v.push_back(make_uint2((uint32_t)k, b0));
         lds_of[T] = std::max(lds_of[T], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes));
     }
-    struct Group {
-        uint32_t threads;
-        size_t first, count, lds;
-    };
-    std::vector<Group> groups;
+    tiles.clear();
+    groups.clear();
     for (auto &kv : by_threads) {
-        groups.push_back(Group{kv.first, tiles.size(), kv.second.size(), lds_of[kv.first]});
+        groups.push_back(TileGroup{kv.first, tiles.size(), kv.second.size(), lds_of[kv.first]});
         tiles.insert(tiles.end(), kv.second.begin(), kv.second.end());
     }
-    for (const Group &g : groups)
+    for (const TileGroup &g : groups)
         if (g.lds > 160 * 1024)
             return fail(XS_EINVAL, "a tile needs %zu bytes of LDS (max 163840)", g.lds);
+    return XS_OK;
+}
+
+xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
+                    const xs_run_buffers *bufs, hipStream_t stream, xs_run_result *results,
+                    const RunOpts &opt) {
+    const auto wall0 = std::chrono::steady_clock::now();
+    if (count <= 0 || !insts || !cfgs || !bufs || !results)
+        return fail(XS_EINVAL, "empty or null batch");
+    int device = 0;
+    XS_HIP(hipGetDevice(&device));
+
+    std::vector<xs::InstDev> h(count);
+    std::vector<uint2> tiles;
+    for (int k = 0; k < count; ++k) {
+        xs_status st = validate_run(insts[k], &cfgs[k], &bufs[k], true);
+        if (st != XS_OK) return st;
+        DeviceTables t;
+        st = ensure_tables(const_cast<xs_instance *>(insts[k]), device, &t);
+        if (st != XS_OK) return st;
+        fill_desc(insts[k], cfgs[k], t, bufs[k].state, bufs[k].first_hit, bufs[k].energy, h[k]);
+    }
+    std::vector<TileGroup> groups;
+    {
+        const xs_status st = tile_instances(h, cfgs, count, tiles, groups);
+        if (st != XS_OK) return st;
+    }
     // Per-call device scratch: descriptors, tiles, the running-instance counter and the
     // winners' spins.
     size_t solved_bytes = 0;
@@ -344,34 +408,64 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         std::lock_guard<std::mutex> lock(g_prof.mu);
         profile = g_prof.on;
     }
+    const bool timed = profile || opt.kernel_ms;
     std::vector<hipEvent_t> ev;
     struct Events {
         std::vector<hipEvent_t> *v;
         ~Events() { for (auto e : *v) (void)hipEventDestroy(e); }
     } ev_guard{&ev};
     xs_kernel_stats local{};
-    // Active instances' updates per chunk are accounted from the sweep counters afterwards.
+    ChunkGraph cg;
+    auto enqueue_chunks = [&](hipStream_t s, int n, bool with_events) -> xs_status {
+        for (int g = 0; g < n; ++g) {
+            if (with_events) XS_HIP(hipEventRecord(ev[2 * g], s));
+            for (const TileGroup &gr : groups)
+                XS_HIP(xs::launch_chunk(d_inst, d_tiles + gr.first, (int)gr.count,
+                                        (int)gr.threads, gr.lds, s));
+            if (with_events) XS_HIP(hipEventRecord(ev[2 * g + 1], s));
+            XS_HIP(xs::launch_decide(d_inst, count, d_active, s));
+        }
+        return XS_OK;
+    };
+    // Chunk loop: chunk launches over all tiles, then the device-side decision. The host reads
+    // the count of running instances every `group` chunks (finished instances' tiles exit at
+    // once, so launching ahead changes no result). Untimed loops of two or more chunks are
+    // replayed from a captured graph.
     while (any_running) {
         const auto c0 = std::chrono::steady_clock::now();
-        if (profile)
+        if (timed)
             while (ev.size() < 2 * (size_t)group) {
                 hipEvent_t e;
                 XS_HIP(hipEventCreate(&e));
                 ev.push_back(e);
             }
-        for (int g = 0; g < group; ++g) {
-            if (profile) XS_HIP(hipEventRecord(ev[2 * g], stream));
-            for (const Group &gr : groups)
-                XS_HIP(xs::launch_chunk(d_inst, d_tiles + gr.first, (int)gr.count,
-                                        (int)gr.threads, gr.lds, stream));
-            if (profile) XS_HIP(hipEventRecord(ev[2 * g + 1], stream));
-            XS_HIP(xs::launch_decide(d_inst, count, d_active, stream));
+        if (!timed && opt.graph && group >= 2) {
+            if (cg.group != group) {
+                cg.reset();
+                if (!cg.cap) XS_HIP(hipStreamCreateWithFlags(&cg.cap, hipStreamNonBlocking));
+                XS_HIP(hipStreamBeginCapture(cg.cap, hipStreamCaptureModeRelaxed));
+                const xs_status st = enqueue_chunks(cg.cap, group, false);
+                hipGraph_t gph = nullptr;
+                const hipError_t e_end = hipStreamEndCapture(cg.cap, &gph);
+                if (st != XS_OK) {
+                    if (gph) (void)hipGraphDestroy(gph);
+                    return st;
+                }
+                XS_HIP(e_end);
+                cg.graph = gph;
+                XS_HIP(hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0));
+                cg.group = group;
+            }
+            XS_HIP(hipGraphLaunch(cg.exec, stream));
+        } else {
+            const xs_status st = enqueue_chunks(stream, group, timed);
+            if (st != XS_OK) return st;
         }
         uint32_t active = 0;
         XS_HIP(hipMemcpyAsync(&active, d_active, sizeof active, hipMemcpyDeviceToHost, stream));
         XS_HIP(hipStreamSynchronize(stream));
         any_running = active != 0;
-        if (profile)
+        if (timed)
             for (int g = 0; g < group; ++g) {
                 float ms = 0.f;
                 XS_HIP(hipEventElapsedTime(&ms, ev[2 * g], ev[2 * g + 1]));
@@ -409,6 +503,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             std::memcpy(bufs[k].solved, solved.data() + solved_off[k], d.n);
         local.clone_spin_updates += r.clone_spin_updates;
     }
+    if (opt.kernel_ms) *opt.kernel_ms += local.total_ms;
     if (profile) {
         std::lock_guard<std::mutex> lock(g_prof.mu);
         g_prof.stats.launches += local.launches;
@@ -418,7 +513,9 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     return XS_OK;
 }
 
-}  // namespace
+}  // namespace xsh
+
+using namespace xsh;
 
 extern "C" {
 
@@ -504,6 +601,125 @@ xs_status xs_instance_get_partition(const xs_instance *I, int32_t *perm, int32_t
     return XS_OK;
 }
 
+xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count, void *stream_v,
+                      xs_tune_result *out) {
+    if (!inst || !out || count <= 0) return fail(XS_EINVAL, "null argument or count <= 0");
+    if (n_clones == 0 || n_clones % XS_CLONE_QUANTUM)
+        return fail(XS_EINVAL, "n_clones %u is not a positive multiple of %d", n_clones,
+                    XS_CLONE_QUANTUM);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+    const uint32_t n = (uint32_t)inst->n, nb = n_clones / 256;
+    const uint32_t ncls = (uint32_t)inst->class_off.size() - 1;
+    const size_t state_bytes = (size_t)n * n_clones / 8;
+    const int copies = (int)std::max<size_t>(1, std::min<size_t>((size_t)count,
+                                                                 (size_t(2) << 30) / state_bytes));
+    // Sweeps per trial: about 4e10 clone-spin updates, between 8 and 200.
+    const double upd_per_sweep = (double)copies * n_clones * n;
+    const uint32_t sweeps = (uint32_t)std::min(200.0, std::max(8.0, 4e10 / upd_per_sweep));
+    uint8_t *mem = nullptr;
+    const size_t fh_bytes = sizeof(int32_t) * n_clones;
+    const size_t per = ((state_bytes + 255) & ~size_t(255)) + ((fh_bytes + 255) & ~size_t(255));
+    XS_HIP(hipMalloc(&mem, per * copies));
+    struct Free {
+        uint8_t *p;
+        ~Free() { if (p) (void)hipFree(p); }
+    } guard{mem};
+    std::vector<const xs_instance *> insts(copies, inst);
+    std::vector<xs_run_config> cfgs(copies);
+    std::vector<xs_run_buffers> bufs(copies);
+    std::vector<xs_run_result> res(copies);
+    for (int k = 0; k < copies; ++k) {
+        xs_run_config &c = cfgs[k];
+        std::memset(&c, 0, sizeof c);
+        c.struct_size = sizeof c;
+        c.instance_id = (uint32_t)k;
+        c.seed = 0x5EEDull + k;
+        c.n_clones = n_clones;
+        c.accept_thr = 3604;
+        c.max_sweeps = sweeps;
+        c.chunk_sweeps = sweeps;
+        bufs[k].state = reinterpret_cast<uint64_t *>(mem + per * k);
+        bufs[k].first_hit = reinterpret_cast<int32_t *>(mem + per * k + ((state_bytes + 255) & ~size_t(255)));
+        bufs[k].energy = nullptr;
+        bufs[k].solved = nullptr;
+    }
+    std::memset(out, 0, sizeof *out);
+    for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
+        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls) > 160 * 1024) continue;
+        for (uint32_t T = 64; T <= 1024; T *= 2) {
+            if (T < 8 * B || out->n_trials >= XS_TUNE_MAX_TRIALS) continue;
+            for (auto &c : cfgs) {
+                c.tile_blocks = B;
+                c.wg_threads = T;
+            }
+            RunOpts opt;
+            double ms = 0.0;
+            opt.kernel_ms = &ms;
+            xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
+                                     res.data(), opt);  // warm
+            if (st != XS_OK) return st;
+            ms = 0.0;
+            st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream, res.data(),
+                           opt);
+            if (st != XS_OK) return st;
+            uint64_t upd = 0;
+            for (auto &r : res) upd += r.clone_spin_updates;
+            const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
+            out->trials[out->n_trials++] = xs_tune_trial{B, T, rate};
+            if (rate > out->updates_per_ns) {
+                out->updates_per_ns = rate;
+                out->tile_blocks = B;
+                out->wg_threads = T;
+            }
+        }
+    }
+    if (!out->n_trials) return fail(XS_EINVAL, "no valid launch configuration");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[tune_key(n, n_clones, count)] = TuneVal{out->tile_blocks, out->wg_threads,
+                                                   out->updates_per_ns};
+    return XS_OK;
+}
+
+xs_status xs_tune_save(const char *path) {
+    if (!path) return fail(XS_EINVAL, "null path");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(XS_EINVAL, "cannot open %s for writing", path);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    std::fprintf(f, "# n_bucket clones count_bucket tile_blocks wg_threads updates_per_ns\n");
+    for (auto &kv : g_tune)
+        std::fprintf(f, "%u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
+                     kv.first.count_bucket, kv.second.tile_blocks, kv.second.wg_threads,
+                     kv.second.rate);
+    std::fclose(f);
+    return XS_OK;
+}
+
+xs_status xs_tune_load(const char *path) {
+    if (!path) return fail(XS_EINVAL, "null path");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(XS_ENOTFOUND, "cannot open %s", path);
+    char line[256];
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        unsigned nb_, cl, cb, B, T;
+        double rate;
+        if (std::sscanf(line, "%u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &rate) != 6) continue;
+        if (!B || (B & (B - 1)) || B > (unsigned)xs::kMaxTileBlocks || !T || (T & (T - 1)) ||
+            T < 64 || T > 1024 || T < 8 * B)
+            continue;
+        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, rate};
+    }
+    std::fclose(f);
+    return XS_OK;
+}
+
+xs_status xs_tune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    return XS_OK;
+}
+
 xs_status xs_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> lock(g_prof.mu);
     g_prof.on = on != 0;
@@ -520,12 +736,14 @@ xs_status xs_profile_read(xs_kernel_stats *out, int32_t reset) {
 
 xs_status xs_run(const xs_instance *inst, const xs_run_config *cfg, const xs_run_buffers *bufs,
                  void *stream, xs_run_result *result) {
-    return run_batch(1, &inst, cfg, bufs, reinterpret_cast<hipStream_t>(stream), result);
+    return run_batch(1, &inst, cfg, bufs, reinterpret_cast<hipStream_t>(stream), result,
+                     RunOpts{});
 }
 
 xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
                        const xs_run_buffers *bufs, void *stream, xs_run_result *results) {
-    return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results);
+    return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results,
+                     RunOpts{});
 }
 
 }  // extern "C"

@@ -1,0 +1,69 @@
+// Host-side internals shared by the run driver (api.cpp) and the server (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/xorsat.h"
+#include "xs_internal.h"
+
+namespace xsh {
+
+struct DeviceTables {
+    uint4 *rec = nullptr;
+    int32_t *class_off = nullptr;
+    uint2 *tri = nullptr;
+};
+
+
+}  // namespace xsh
+
+struct xs_instance {
+    int32_t n = 0;
+    int32_t cap = 32;
+    std::vector<int32_t> tri;        // [n][3]
+    std::vector<int8_t> J;           // [n]
+    std::vector<int32_t> perm;       // update order
+    std::vector<int32_t> class_off;  // [n_classes + 1]
+    std::vector<uint16_t> rec;       // [n][8] in update order
+    std::vector<uint16_t> tri16;     // [n][4]: a, b, c, j
+    int32_t max_class = 0;
+    std::mutex mu;
+    std::map<int, xsh::DeviceTables> dev;  // per HIP device
+};
+
+// Return XS_EDEVICE (with the HIP message) from the enclosing function if a HIP call fails.
+#define XS_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return xsh::fail(XS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace xsh {
+
+// Set the calling thread's last error message and return st.
+xs_status fail(xs_status st, const char *fmt, ...);
+// Device tables of an instance on `device`, uploaded on first use.
+xs_status ensure_tables(xs_instance *I, int device, DeviceTables *out);
+// Check a run configuration and its buffers (state buffer ignored if check_buffers is false).
+xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b,
+                       bool check_buffers);
+// Fill the constant and initial control fields of a descriptor (tiling left to tile_instances).
+void fill_desc(const xs_instance *I, const xs_run_config &c, const DeviceTables &t,
+               uint64_t *state, int32_t *first_hit, int32_t *energy, xs::InstDev &d);
+
+// One chunk launch per workgroup size over a list of tiles.
+struct TileGroup {
+    uint32_t threads;
+    size_t first, count, lds;
+};
+// Choose tiling for descriptors h[0..count) (explicit config knobs, then the tuned table, then
+// the default rule), fill tile_blocks / log2 / wg_threads, and build the tile list and groups.
+xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs, int count,
+                         std::vector<uint2> &tiles, std::vector<TileGroup> &groups);
+
+}  // namespace xsh

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libxorsat.so")
 XS_OK = 0
 XS_STATUS = {0: "XS_OK", 1: "XS_EINVAL", 2: "XS_ENOMEM", 3: "XS_EDEVICE", 4: "XS_EAGAIN",
              5: "XS_ENOTFOUND", 6: "XS_ECANCELED"}
+XS_STATUS_CODES = {v: k for k, v in XS_STATUS.items()}
 XS_STOP_ON_FIRST = 0x1
 XS_RESUME = 0x2
 XS_MAX_N = 2048
@@ -26,7 +27,11 @@ XS_CLONE_QUANTUM = 256
 # Every function the header declares, for the export check.
 EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_create",
            "xs_instance_destroy", "xs_instance_get_info", "xs_instance_get_partition",
-           "xs_run", "xs_run_batch", "xs_profile_enable", "xs_profile_read"]
+           "xs_run", "xs_run_batch", "xs_profile_enable", "xs_profile_read",
+           "xs_autotune", "xs_tune_save", "xs_tune_load", "xs_tune_clear",
+           "xs_server_create", "xs_server_destroy", "xs_server_submit", "xs_server_step",
+           "xs_server_poll", "xs_server_cancel", "xs_server_get_stats"]
+XS_TUNE_MAX_TRIALS = 32
 
 
 class XsError(RuntimeError):
@@ -59,6 +64,39 @@ class RunResult(ctypes.Structure):
 class KernelStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
                 ("clone_spin_updates", ctypes.c_uint64)]
+
+
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
+                ("updates_per_ns", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
+                ("updates_per_ns", ctypes.c_double), ("n_trials", ctypes.c_int32),
+                ("trials", TuneTrial * XS_TUNE_MAX_TRIALS)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_resident", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class ServerOutputs(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_void_p), ("first_hit", ctypes.c_void_p),
+                ("energy", ctypes.c_void_p), ("solved", ctypes.c_void_p)]
+
+
+class ServerCompletion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("result", RunResult), ("queued_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+                ("resident", ctypes.c_uint64), ("clone_spin_updates", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_uint64), ("step_seconds", ctypes.c_double)]
 
 
 class InstanceInfo(ctypes.Structure):
@@ -96,6 +134,29 @@ def load():
     lib.xs_run.restype = i32
     lib.xs_run_batch.argtypes = [i32, P, P, P, P, P]
     lib.xs_run_batch.restype = i32
+    lib.xs_autotune.argtypes = [P, ctypes.c_uint32, i32, P, ctypes.POINTER(TuneResult)]
+    lib.xs_autotune.restype = i32
+    lib.xs_tune_save.argtypes = [ctypes.c_char_p]
+    lib.xs_tune_save.restype = i32
+    lib.xs_tune_load.argtypes = [ctypes.c_char_p]
+    lib.xs_tune_load.restype = i32
+    lib.xs_tune_clear.argtypes = []
+    lib.xs_tune_clear.restype = i32
+    lib.xs_server_create.argtypes = [ctypes.POINTER(ServerConfig), P, ctypes.POINTER(P)]
+    lib.xs_server_create.restype = i32
+    lib.xs_server_destroy.argtypes = [P]
+    lib.xs_server_destroy.restype = None
+    lib.xs_server_submit.argtypes = [P, P, ctypes.POINTER(RunConfig),
+                                     ctypes.POINTER(ServerOutputs), ctypes.POINTER(ctypes.c_uint64)]
+    lib.xs_server_submit.restype = i32
+    lib.xs_server_step.argtypes = [P, ctypes.POINTER(i32)]
+    lib.xs_server_step.restype = i32
+    lib.xs_server_poll.argtypes = [P, ctypes.POINTER(ServerCompletion), i32, ctypes.POINTER(i32)]
+    lib.xs_server_poll.restype = i32
+    lib.xs_server_cancel.argtypes = [P, ctypes.c_uint64]
+    lib.xs_server_cancel.restype = i32
+    lib.xs_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.xs_server_get_stats.restype = i32
     lib.xs_profile_enable.argtypes = [i32]
     lib.xs_profile_enable.restype = i32
     lib.xs_profile_read.argtypes = [ctypes.POINTER(KernelStats), i32]
@@ -239,3 +300,110 @@ def profile_read(reset: bool = False) -> dict:
     _check(load().xs_profile_read(ctypes.byref(st), 1 if reset else 0))
     return dict(launches=int(st.launches), total_ms=float(st.total_ms),
                 clone_spin_updates=int(st.clone_spin_updates))
+
+
+def autotune(inst: Instance, n_clones: int, count: int = 1) -> dict:
+    """Time every valid (tile_blocks, wg_threads) pair for `count` instances like `inst` and
+    record the fastest for later runs that leave both knobs at 0."""
+    res = TuneResult()
+    _check(load().xs_autotune(inst.handle, n_clones, count, _stream(), ctypes.byref(res)))
+    trials = [(res.trials[k].tile_blocks, res.trials[k].wg_threads,
+               res.trials[k].updates_per_ns) for k in range(res.n_trials)]
+    return dict(tile_blocks=res.tile_blocks, wg_threads=res.wg_threads,
+                updates_per_ns=res.updates_per_ns, trials=trials)
+
+
+def tune_save(path: str):
+    _check(load().xs_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(load().xs_tune_load(path.encode()))
+
+
+def tune_clear():
+    _check(load().xs_tune_clear())
+
+
+@dataclass
+class Completion:
+    ticket: int
+    status: int
+    tts_sweeps: int
+    winner_clone: int
+    end_sweep: int
+    sweeps_done: int
+    clone_spin_updates: int
+    latency_s: float   # submission to completion
+    queued_s: float    # submission to admission
+    outputs: dict      # host numpy arrays given at submission (state, first_hit, energy, solved)
+
+
+class Server:
+    """Continuous-batching server (xs_server_*). Host numpy buffers receive each request's
+    outputs when it completes."""
+
+    def __init__(self, hbm_budget_bytes: int, max_resident: int = 0):
+        cfg = ServerConfig(ctypes.sizeof(ServerConfig), max_resident, hbm_budget_bytes)
+        h = ctypes.c_void_p()
+        _check(load().xs_server_create(ctypes.byref(cfg), _stream(), ctypes.byref(h)))
+        self._h = h
+        self._outs = {}  # ticket -> (instance, dict of numpy buffers) kept alive until done
+
+    def submit(self, inst: Instance, cfg: RunConfig, *, want_state: bool = False,
+               want_first_hit: bool = True, want_energy: bool = True) -> int:
+        n, nc = inst.n, cfg.n_clones
+        bufs = {"solved": np.zeros(n, dtype=np.int8)}
+        if want_state:
+            bufs["state"] = np.zeros((n, nc // 64), dtype=np.uint64)
+        if want_first_hit:
+            bufs["first_hit"] = np.zeros(nc, dtype=np.int32)
+        if want_energy:
+            bufs["energy"] = np.zeros(nc, dtype=np.int32)
+        outs = ServerOutputs(*(bufs[k].ctypes.data if k in bufs else None
+                               for k in ("state", "first_hit", "energy", "solved")))
+        t = ctypes.c_uint64()
+        _check(load().xs_server_submit(self._h, inst.handle, ctypes.byref(cfg),
+                                       ctypes.byref(outs), ctypes.byref(t)))
+        self._outs[t.value] = (inst, bufs)
+        return t.value
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        _check(load().xs_server_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, cap: int = 1024) -> list[Completion]:
+        arr = (ServerCompletion * cap)()
+        n = ctypes.c_int32()
+        _check(load().xs_server_poll(self._h, arr, cap, ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            c = arr[k]
+            _, bufs = self._outs.pop(c.ticket)
+            if c.result.winner_clone < 0:
+                bufs["solved"] = None
+            out.append(Completion(int(c.ticket), int(c.status), int(c.result.tts_sweeps),
+                                  int(c.result.winner_clone), int(c.result.end_sweep),
+                                  int(c.result.sweeps_done), int(c.result.clone_spin_updates),
+                                  float(c.result.seconds), float(c.queued_s), bufs))
+        return out
+
+    def cancel(self, ticket: int):
+        _check(load().xs_server_cancel(self._h, ticket))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().xs_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().xs_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -32,7 +32,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) >= 9
+    assert len(names) >= 20
     assert sorted(xorsat.EXPORTS) == names
     for name in names:
         assert hasattr(lib, name), name
@@ -45,6 +45,11 @@ def test_struct_layouts():
     assert ctypes.sizeof(xorsat.RunBuffers) == 32
     assert ctypes.sizeof(xorsat.RunResult) == 48
     assert ctypes.sizeof(xorsat.InstanceInfo) == 16
+    assert ctypes.sizeof(xorsat.ServerConfig) == 16
+    assert ctypes.sizeof(xorsat.ServerOutputs) == 32
+    assert ctypes.sizeof(xorsat.ServerCompletion) == 72
+    assert ctypes.sizeof(xorsat.ServerStats) == 64
+    assert ctypes.sizeof(xorsat.TuneResult) == 8 + 8 + 8 + 32 * 16
 
 
 @pytest.mark.parametrize("n,cap", [(10, 32), (10, 2), (64, 32), (256, 32), (1024, 32),
@@ -86,3 +91,23 @@ def test_last_error_is_thread_local_message(lib):
     with pytest.raises(xorsat.XsError):
         xorsat.Instance(np.zeros((4, 3), dtype=np.int32), np.ones(4, dtype=np.int8))
     assert lib.xs_last_error().decode()
+
+
+def test_tune_table_roundtrip(lib, tmp_path):
+    """The tuned-knob table loads, rejects invalid rows and saves what it holds (no GPU)."""
+    src = tmp_path / "tune.txt"
+    src.write_text("# comment\n256 65536 64 4 256 40000.0\n1024 1048576 16 1 256 19000.5\n"
+                   "64 1024 1 3 256 1.0\n64 1024 1 2 32 1.0\nnot a row\n")
+    xorsat.tune_clear()
+    xorsat.tune_load(str(src))
+    out = tmp_path / "out.txt"
+    xorsat.tune_save(str(out))
+    rows = [r.split() for r in out.read_text().splitlines() if not r.startswith("#")]
+    assert rows == [["256", "65536", "64", "4", "256", "40000.0"],
+                    ["1024", "1048576", "16", "1", "256", "19000.5"]]
+    xorsat.tune_clear()
+    xorsat.tune_save(str(out))
+    assert [r for r in out.read_text().splitlines() if not r.startswith("#")] == []
+    with pytest.raises(xorsat.XsError) as e:
+        xorsat.tune_load(str(tmp_path / "missing.txt"))
+    assert e.value.status == 5
