@@ -56,6 +56,17 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "steady", "uneven", "serve", "tts"],
+                    help="batched: the default line; steady: 16 x N=1024 x 2^20 clones, fixed "
+                         "sweeps; uneven: 512 instances of uneven N and clone count, batched vs "
+                         "served vs one at a time; serve: Poisson stream through the server vs "
+                         "one run at a time; tts: the exponential TTS law on many runs of one "
+                         "small instance, tau x N_cl scaling and the short-timeout estimate")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+                    help="serve: device memory the server may hold for resident requests")
     return ap.parse_args()
 
 
@@ -103,6 +114,254 @@ def cpu_baseline(insts, args, target_s):
                       f"{updates:.3e} updates in {dt:.1f} s"}
 
 
+def pct(v, q):
+    return float(np.percentile(v, q)) if len(v) else None
+
+
+def workload_steady(args, xorsat, torch):
+    """16 instances, N = 1024, 2^20 clones each, a fixed sweep budget (default 10^4)."""
+    from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance, run_seed
+
+    count, n, clones = 16, 1024, 1 << 20
+    sweeps = args.budget if args.budget != 50000 else 10000
+    insts = [planted_instance(n, gen_seed(3, k)) for k in range(count)]
+    hs = [xorsat.Instance(i.tri, i.J) for i in insts]
+    cfgs = [xorsat.make_config(n_clones=clones, seed=run_seed(3, k), instance_id=k,
+                               accept_thr=THR_PAPER, max_sweeps=sweeps, stop_on_first=False,
+                               chunk_sweeps=args.chunk) for k in range(count)]
+    print(f"# steady: {count} x N={n} x {clones} clones, {sweeps} sweeps", flush=True)
+    xorsat.profile_read(reset=True)
+    xorsat.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = xorsat.run_batch(hs, cfgs, want_energy=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    xorsat.profile_enable(False)
+    prof = xorsat.profile_read(reset=True)
+    upd = sum(o.clone_spin_updates for o in outs)
+    tts = [o.tts_sweeps for o in outs if o.tts_sweeps >= 0]
+    return {"metric": "clone-spin updates/ns on 1 MI355X (steady state)",
+            "value": round(upd / dt / 1e9, 3), "unit": "clone-spin updates/ns",
+            "kernel_updates_per_ns": round(prof["clone_spin_updates"] / prof["total_ms"] / 1e6, 3),
+            "seconds": round(dt, 3), "config": {"workload": f"{count} planted instances, N={n}, "
+                                                            f"{clones} clones each, {sweeps} sweeps",
+                                                "tile_blocks": outs[0].tile_blocks,
+                                                "wg_threads": outs[0].wg_threads},
+            "tts_sweeps": {"solved": len(tts), "censored": count - len(tts)}}
+
+
+def workload_uneven(args, xorsat, torch):
+    """512 planted instances of uneven N and clone count, each to its first ground state or
+    10^4 sweeps: one batched run, the server with every request queued at once, and one run
+    per instance in sequence. Results are bit-identical across the three (checked)."""
+    from paper_2102_09510_amd.instances import (THR_PAPER, gen_seed, planted_instance, run_seed,
+                                                uneven_sizes)
+
+    sizes = uneven_sizes(512)
+    insts = [planted_instance(n, gen_seed(4, k)) for k, (n, _) in enumerate(sizes)]
+    hs = [xorsat.Instance(i.tri, i.J) for i in insts]
+    budget = args.budget if args.budget != 50000 else 10000
+
+    def cfg(k):
+        return xorsat.make_config(n_clones=sizes[k][1], seed=run_seed(4, k), instance_id=k,
+                                  accept_thr=THR_PAPER, max_sweeps=budget, stop_on_first=True,
+                                  chunk_sweeps=args.chunk)
+
+    print(f"# uneven: {len(sizes)} instances, budget {budget}", flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = xorsat.run_batch(hs, [cfg(k) for k in range(len(hs))], want_energy=False)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    upd = sum(o.clone_spin_updates for o in batch)
+    print(f"# batched run done in {t_batch:.2f} s", flush=True)
+
+    srv = xorsat.Server(hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)))
+    t0 = time.perf_counter()
+    tickets = {srv.submit(hs[k], cfg(k), want_first_hit=False, want_energy=False): k
+               for k in range(len(hs))}
+    served = {}
+    while True:
+        active = srv.step()
+        for c in srv.poll():
+            served[tickets[c.ticket]] = c
+        if active == 0:
+            break
+    for c in srv.poll():
+        served[tickets[c.ticket]] = c
+    t_serve = time.perf_counter() - t0
+    srv.close()
+    print(f"# served run done in {t_serve:.2f} s", flush=True)
+
+    single_done = []
+    t0 = time.perf_counter()
+    single = []
+    for k in range(len(hs)):
+        single.append(xorsat.run(hs[k], cfg(k), want_energy=False))
+        torch.cuda.synchronize()
+        single_done.append(time.perf_counter() - t0)
+    t_single = single_done[-1]
+    print(f"# one-at-a-time done in {t_single:.2f} s", flush=True)
+    for k in range(len(hs)):
+        a, b, c = batch[k], served[k], single[k]
+        assert (a.tts_sweeps, a.winner_clone, a.end_sweep) == \
+            (b.tts_sweeps, b.winner_clone, b.end_sweep) == \
+            (c.tts_sweeps, c.winner_clone, c.end_sweep), k
+    tts = [o.tts_sweeps for o in batch if o.tts_sweeps >= 0]
+    lat_srv = [served[k].latency_s for k in range(len(hs))]
+    solved = [k for k in range(len(hs)) if batch[k].tts_sweeps >= 0]
+    return {"metric": "clone-spin updates/ns and completion latency, uneven batch",
+            "config": {"workload": "512 planted instances, N uniform on {32..1024}, clones "
+                                   "uniform on {4096..65536}, to first ground state or "
+                                   f"{budget} sweeps"},
+            "updates": upd,
+            "batched": {"seconds": round(t_batch, 3), "updates_per_ns": round(upd / t_batch / 1e9, 1)},
+            "served": {"seconds": round(t_serve, 3), "updates_per_ns": round(upd / t_serve / 1e9, 1),
+                       "latency_s_p50": pct(lat_srv, 50), "latency_s_p99": pct(lat_srv, 99),
+                       "solved_latency_s_p50": pct([lat_srv[k] for k in solved], 50),
+                       "solved_latency_s_p99": pct([lat_srv[k] for k in solved], 99)},
+            "one_at_a_time": {"seconds": round(t_single, 3),
+                              "updates_per_ns": round(upd / t_single / 1e9, 1),
+                              "latency_s_p50": pct(single_done, 50),
+                              "latency_s_p99": pct(single_done, 99),
+                              "solved_latency_s_p50": pct([single_done[k] for k in solved], 50),
+                              "solved_latency_s_p99": pct([single_done[k] for k in solved], 99)},
+            "tts_sweeps": {"solved": len(tts), "censored": len(hs) - len(tts),
+                           "p50": pct(tts, 50), "p99": pct(tts, 99)},
+            "identical_results": True}
+
+
+def workload_serve(args, xorsat, torch):
+    """Poisson arrivals of planted instances (N log-uniform in [64, 2048], 16384 clones, first
+    ground state or 10^4 sweeps) through the server, then the first requests of the same stream
+    served one run at a time in arrival order (FIFO) for comparison."""
+    from paper_2102_09510_amd.instances import (THR_PAPER, gen_seed, planted_instance,
+                                                poisson_stream, run_seed)
+
+    arrivals = poisson_stream(args.rate, args.duration)
+    budget = args.budget if args.budget != 50000 else 10000
+    print(f"# serve: {len(arrivals)} requests over {args.duration} s, preparing instances",
+          flush=True)
+    hs = []
+    for k, (_, n) in enumerate(arrivals):
+        inst = planted_instance(n, gen_seed(5, k))
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+
+    def cfg(k):
+        return xorsat.make_config(n_clones=16384, seed=run_seed(5, k), instance_id=k,
+                                  accept_thr=THR_PAPER, max_sweeps=budget, stop_on_first=True,
+                                  chunk_sweeps=args.chunk)
+
+    srv = xorsat.Server(hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)))
+    tickets = {}
+    done = {}
+    nxt = 0
+    max_resident = 0
+    print("# serving", flush=True)
+    t0 = time.perf_counter()
+    last_report = t0
+    while nxt < len(arrivals) or len(done) < len(arrivals):
+        now = time.perf_counter() - t0
+        while nxt < len(arrivals) and arrivals[nxt][0] <= now:
+            tickets[srv.submit(hs[nxt], cfg(nxt), want_first_hit=False, want_energy=False)] = nxt
+            nxt += 1
+        active = srv.step()
+        for c in srv.poll():
+            done[tickets[c.ticket]] = c
+        max_resident = max(max_resident, srv.stats()["resident"])
+        if time.perf_counter() - last_report > 10:
+            last_report = time.perf_counter()
+            print(f"# t={last_report - t0:.0f}s submitted {nxt} done {len(done)} "
+                  f"resident {srv.stats()['resident']}", flush=True)
+        if active == 0 and nxt < len(arrivals):
+            time.sleep(max(0.0, min(0.002, arrivals[nxt][0] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = [done[k].latency_s for k in range(len(arrivals))]
+    solved = [k for k in range(len(arrivals)) if done[k].tts_sweeps >= 0]
+    tts = [done[k].tts_sweeps for k in solved]
+    # One run at a time, FIFO in arrival order, on the first requests of the same stream.
+    m = min(len(arrivals), 400)
+    finish = 0.0
+    single_lat = []
+    service = []
+    print(f"# one-at-a-time on the first {m} requests", flush=True)
+    for k in range(m):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o = xorsat.run(hs[k], cfg(k), want_energy=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        assert (o.tts_sweeps, o.end_sweep) == (done[k].tts_sweeps, done[k].end_sweep), k
+        service.append(dt)
+        start = max(arrivals[k][0], finish)
+        finish = start + dt
+        single_lat.append(finish - arrivals[k][0])
+    offered = sum(service) / max(arrivals[m - 1][0], 1e-9)
+    return {"metric": "served TTS latency p50/p99 and sustained clone-spin updates/ns",
+            "config": {"workload": f"Poisson stream, {args.rate}/s for {args.duration} s "
+                                   f"({len(arrivals)} requests), N log-uniform in [64, 2048], "
+                                   f"16384 clones, first ground state or {budget} sweeps",
+                       "hbm_budget_gib": args.serve_budget_gib},
+            "served": {"wall_s": round(wall, 2),
+                       "sustained_updates_per_ns": round(st["clone_spin_updates"] / wall / 1e9, 1),
+                       "latency_s_p50": pct(lat, 50), "latency_s_p99": pct(lat, 99),
+                       "solved": len(solved), "censored": len(arrivals) - len(solved),
+                       "solved_latency_s_p50": pct([lat[k] for k in solved], 50),
+                       "solved_latency_s_p99": pct([lat[k] for k in solved], 99),
+                       "tts_sweeps_p50": pct(tts, 50), "tts_sweeps_p99": pct(tts, 99),
+                       "max_resident": max_resident, "steps": st["steps"]},
+            "one_at_a_time_first_requests": {
+                "requests": m, "latency_s_p50": pct(single_lat, 50),
+                "latency_s_p99": pct(single_lat, 99),
+                "service_s_mean": float(np.mean(service)),
+                "offered_load": round(offered, 2),
+                "same_requests_served_latency_s_p50": pct(lat[:m], 50),
+                "same_requests_served_latency_s_p99": pct(lat[:m], 99)},
+            "identical_results_checked": m}
+
+
+def workload_tts(args, xorsat, torch):
+    """Many independent runs (different seeds) of one planted N = 80 instance at two clone
+    counts: the fastest-clone TTS law (Eq. 2), tau estimators, tau x N_cl (SM), and tau from
+    runs capped at a short timeout (inverse-gamma posterior)."""
+    from paper_2102_09510_amd import tts_stats as ts
+    from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance
+
+    n, runs = 80, 512
+    inst = planted_instance(n, gen_seed(6, 0))
+    h = xorsat.Instance(inst.tri, inst.J)
+    out = {"metric": "TTS distribution of many-clone runs (sweeps)",
+           "config": {"workload": f"1 planted instance, N={n}, {runs} runs per clone count, "
+                                  "to first ground state"}}
+    taus = {}
+    for ncl in (1024, 4096):
+        cfgs = [xorsat.make_config(n_clones=ncl, seed=0xC0FFEE + 7919 * r, instance_id=r,
+                                   accept_thr=THR_PAPER, max_sweeps=10**6, stop_on_first=True,
+                                   chunk_sweeps=20) for r in range(runs)]
+        t0 = time.perf_counter()
+        res = xorsat.run_batch([h] * runs, cfgs, want_energy=False)
+        dt = time.perf_counter() - t0
+        tts = np.array([r.tts_sweeps for r in res])
+        assert (tts >= 0).all()
+        s = ts.summarize(tts, n_clones=ncl)
+        s["seconds"] = round(dt, 2)
+        taus[ncl] = s["tau"]
+        # short timeout: cap every run at tau/10 and estimate tau from the successes alone
+        cap = max(1, int(s["tau"] / 10))
+        n_succ = int((tts < cap).sum())
+        post = ts.TimeoutPosterior(n_succ, runs, cap)
+        s["timeout"] = {"t_max": cap, "successes": n_succ,
+                        "tau_posterior_mean": post.mean() if n_succ > 1 else None,
+                        "tau_posterior_median": post.quantile(0.5) if n_succ > 0 else None}
+        out[f"clones_{ncl}"] = s
+        print(f"# {ncl} clones: tau {s['tau']:.1f} sweeps, KS p {s['ks_pvalue']:.3f}", flush=True)
+    out["tau_ratio_1024_over_4096"] = taus[1024] / taus[4096]
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,6 +384,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return
+    if args.workload != "batched":
+        fn = {"steady": workload_steady, "uneven": workload_uneven,
+              "serve": workload_serve, "tts": workload_tts}[args.workload]
+        print(json.dumps(fn(args, xorsat, torch)), flush=True)
         return
     insts = [planted_instance(args.n, gen_seed(2, k)) for k in range(args.instances)]
     handles = [xorsat.Instance(i.tri, i.J) for i in insts]

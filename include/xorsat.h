@@ -112,6 +112,8 @@ typedef struct {
                               library. Changes speed only, never results. */
     uint32_t wg_threads;   /* threads per workgroup: 64 .. 1024, a power of two, at least
                               8 * tile_blocks; 0 = chosen by the library. Speed only. */
+    uint32_t col_bytes;    /* bytes of a spin row one thread updates per step: 4, 8 or 16
+                              (32, 64 or 128 clones); 0 = chosen by the library. Speed only. */
 } xs_run_config;
 
 /*
@@ -139,6 +141,7 @@ typedef struct {
     uint32_t sweeps_done;        /* end_sweep - start_sweep */
     uint32_t tile_blocks;        /* tiling used (result-neutral) */
     uint32_t wg_threads;         /* workgroup size used (result-neutral) */
+    uint32_t col_bytes;          /* task column width used (result-neutral) */
     uint64_t clone_spin_updates; /* n_clones * n * sweeps_done */
     double seconds;              /* wall time of the call */
 } xs_run_result;
@@ -225,22 +228,23 @@ xs_status xs_server_get_stats(const xs_server *srv, xs_server_stats *out);
 
 /*
  * Autotuner of the result-neutral launch knobs (tile_blocks: clones per workgroup, in blocks of
- * 256; wg_threads: threads per workgroup, which sets how many spins of a colour class a thread
- * handles per step). It times every valid pair with short budget runs of `count` copies of
+ * 256; wg_threads: threads per workgroup; col_bytes: clones one thread updates per step, which
+ * with the class size sets how a colour class is spread over the threads). It times the valid
+ * combinations with short budget runs of `count` copies of
  * `inst` (fewer if their state would exceed 2 GiB) on `stream`, using HIP events around the
- * sweep launches, and records the fastest pair for workloads of the same N (rounded up to a
+ * sweep launches, and records the fastest combination for workloads of the same N (rounded up to a
  * power of two), clone count and batch size (rounded up to a power of two, at most 64). Later
  * runs whose config leaves both knobs 0 use the recorded pair. Allocates and frees its own
  * device buffers. Results of any run never depend on these knobs.
  */
-#define XS_TUNE_MAX_TRIALS 32
+#define XS_TUNE_MAX_TRIALS 64
 typedef struct {
-    uint32_t tile_blocks, wg_threads;
+    uint32_t tile_blocks, wg_threads, col_bytes;
     double updates_per_ns; /* sweep-kernel rate of this trial */
 } xs_tune_trial;
 
 typedef struct {
-    uint32_t tile_blocks, wg_threads; /* the fastest pair */
+    uint32_t tile_blocks, wg_threads, col_bytes; /* the fastest choice */
     double updates_per_ns;
     int32_t n_trials;
     xs_tune_trial trials[XS_TUNE_MAX_TRIALS];
@@ -248,11 +252,11 @@ typedef struct {
 
 xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count, void *stream,
                       xs_tune_result *out);
-/* Write / read the recorded pairs as text ("n_bucket clones count_bucket B T rate" lines).
+/* Write / read the recorded choices as text ("n_bucket clones count_bucket B T CW rate" lines).
  * Loading adds to (and overrides) the table in memory. */
 xs_status xs_tune_save(const char *path);
 xs_status xs_tune_load(const char *path);
-/* Forget every recorded pair. */
+/* Forget every recorded choice. */
 xs_status xs_tune_clear(void);
 
 /*

@@ -187,6 +187,8 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
                         "n * tile_blocks <= 2048",
                         B, xs::kMaxTileBlocks);
     }
+    if (cfg->col_bytes && cfg->col_bytes != 4 && cfg->col_bytes != 8 && cfg->col_bytes != 16)
+        return fail(XS_EINVAL, "col_bytes %u must be 4, 8 or 16", cfg->col_bytes);
     if (cfg->wg_threads) {
         const uint32_t T = cfg->wg_threads;
         const uint32_t B = cfg->tile_blocks;
@@ -201,6 +203,10 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
 // Default workgroup size for a tile of B blocks: one thread per (spin, 16-byte column) task of a
 // full 32-spin class, within [256, 1024].
 uint32_t default_threads(uint32_t B) { return std::min(1024u, std::max(256u, 64u * B)); }
+
+// Default task column: narrow columns for small tiles, so that a 32-spin class still spreads
+// over the workgroup (a one-block tile has 64 tasks of 16 bytes but 256 of 4 bytes).
+uint32_t default_col_bytes(uint32_t B) { return B >= 4 ? 16u : B == 2 ? 8u : 4u; }
 
 // Options of one driver call beyond the public configuration.
 struct RunOpts {
@@ -217,7 +223,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    uint32_t tile_blocks, wg_threads;
+    uint32_t tile_blocks, wg_threads, col_bytes;
     double rate;
 };
 std::mutex g_tune_mu;
@@ -286,18 +292,20 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         xs::InstDev &d = h[k];
         const uint32_t nb = c.n_clones / 256;
         uint32_t B = c.tile_blocks ? c.tile_blocks : max_tile_blocks(d.n, nb, 1024);
-        uint32_t tuned_T = 0;
-        if (!c.tile_blocks && !c.wg_threads) {
+        uint32_t tuned_T = 0, tuned_C = 0;
+        if (!c.tile_blocks && !c.wg_threads && !c.col_bytes) {
             std::lock_guard<std::mutex> lock(g_tune_mu);
             auto it = g_tune.find(tune_key(d.n, c.n_clones, count));
             if (it != g_tune.end() && nb % it->second.tile_blocks == 0 &&
                 d.n * it->second.tile_blocks <= 2048) {
                 B = it->second.tile_blocks;
                 tuned_T = it->second.wg_threads;
+                tuned_C = it->second.col_bytes;
             }
         }
         d.tile_blocks = B;
         d.wg_threads = tuned_T;  // 0 unless tuned
+        d.col_bytes = tuned_C;
     }
     // Shrink automatic tiles while the batch has too few workgroups.
     auto count_tiles = [&]() {
@@ -315,9 +323,9 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
             }
         if (!changed) break;
     }
-    // Tiles grouped by workgroup size: one launch per group and chunk.
-    std::map<uint32_t, std::vector<uint2>> by_threads;
-    std::map<uint32_t, size_t> lds_of;
+    // Tiles grouped by (workgroup size, column width): one launch per group and chunk.
+    std::map<std::pair<uint32_t, uint32_t>, std::vector<uint2>> by_launch;
+    std::map<std::pair<uint32_t, uint32_t>, size_t> lds_of;
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
         d.log2_tile_blocks = ilog2(d.tile_blocks);
@@ -326,15 +334,21 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
                                           : default_threads(d.tile_blocks);
         T = std::max(T, 8 * d.tile_blocks);
         d.wg_threads = T;
+        const uint32_t C = cfgs[k].col_bytes ? cfgs[k].col_bytes
+                           : d.col_bytes      ? d.col_bytes
+                                              : default_col_bytes(d.tile_blocks);
+        d.col_bytes = C;
         const uint32_t nb = cfgs[k].n_clones / 256;
-        auto &v = by_threads[T];
+        const auto key = std::make_pair(T, C);
+        auto &v = by_launch[key];
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) v.push_back(make_uint2((uint32_t)k, b0));
-        lds_of[T] = std::max(lds_of[T], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes));
+        lds_of[key] = std::max(lds_of[key], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes));
     }
     tiles.clear();
     groups.clear();
-    for (auto &kv : by_threads) {
-        groups.push_back(TileGroup{kv.first, tiles.size(), kv.second.size(), lds_of[kv.first]});
+    for (auto &kv : by_launch) {
+        groups.push_back(TileGroup{kv.first.first, kv.first.second, tiles.size(), kv.second.size(),
+                                   lds_of[kv.first]});
         tiles.insert(tiles.end(), kv.second.begin(), kv.second.end());
     }
     for (const TileGroup &g : groups)
@@ -421,7 +435,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             if (with_events) XS_HIP(hipEventRecord(ev[2 * g], s));
             for (const TileGroup &gr : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + gr.first, (int)gr.count,
-                                        (int)gr.threads, gr.lds, s));
+                                        (int)gr.threads, (int)gr.col_bytes, gr.lds, s));
             if (with_events) XS_HIP(hipEventRecord(ev[2 * g + 1], s));
             XS_HIP(xs::launch_decide(d_inst, count, d_active, s));
         }
@@ -497,6 +511,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         r.sweeps_done = d.t_cur - d.t_start;
         r.tile_blocks = d.tile_blocks;
         r.wg_threads = d.wg_threads;
+        r.col_bytes = d.col_bytes;
         r.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * r.sweeps_done;
         r.seconds = secs;
         if (bufs[k].solved && d.winner != INT32_MAX)
@@ -646,37 +661,44 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
     std::memset(out, 0, sizeof *out);
     for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
         if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls) > 160 * 1024) continue;
-        for (uint32_t T = 64; T <= 1024; T *= 2) {
-            if (T < 8 * B || out->n_trials >= XS_TUNE_MAX_TRIALS) continue;
-            for (auto &c : cfgs) {
-                c.tile_blocks = B;
-                c.wg_threads = T;
-            }
-            RunOpts opt;
-            double ms = 0.0;
-            opt.kernel_ms = &ms;
-            xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
-                                     res.data(), opt);  // warm
-            if (st != XS_OK) return st;
-            ms = 0.0;
-            st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream, res.data(),
-                           opt);
-            if (st != XS_OK) return st;
-            uint64_t upd = 0;
-            for (auto &r : res) upd += r.clone_spin_updates;
-            const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
-            out->trials[out->n_trials++] = xs_tune_trial{B, T, rate};
-            if (rate > out->updates_per_ns) {
-                out->updates_per_ns = rate;
-                out->tile_blocks = B;
-                out->wg_threads = T;
+        for (uint32_t T = 128; T <= 1024; T *= 2) {
+            if (T < 8 * B || (T == 128 && B > 2)) continue;
+            for (uint32_t C = 4; C <= 16; C *= 2) {
+                // skip columns that leave most threads without a task in a full class
+                if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
+                    continue;
+                for (auto &c : cfgs) {
+                    c.tile_blocks = B;
+                    c.wg_threads = T;
+                    c.col_bytes = C;
+                }
+                RunOpts opt;
+                double ms = 0.0;
+                opt.kernel_ms = &ms;
+                xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
+                                         res.data(), opt);  // warm
+                if (st != XS_OK) return st;
+                ms = 0.0;
+                st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
+                               res.data(), opt);
+                if (st != XS_OK) return st;
+                uint64_t upd = 0;
+                for (auto &r : res) upd += r.clone_spin_updates;
+                const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
+                out->trials[out->n_trials++] = xs_tune_trial{B, T, C, rate};
+                if (rate > out->updates_per_ns) {
+                    out->updates_per_ns = rate;
+                    out->tile_blocks = B;
+                    out->wg_threads = T;
+                    out->col_bytes = C;
+                }
             }
         }
     }
     if (!out->n_trials) return fail(XS_EINVAL, "no valid launch configuration");
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[tune_key(n, n_clones, count)] = TuneVal{out->tile_blocks, out->wg_threads,
-                                                   out->updates_per_ns};
+                                                   out->col_bytes, out->updates_per_ns};
     return XS_OK;
 }
 
@@ -685,11 +707,12 @@ xs_status xs_tune_save(const char *path) {
     FILE *f = std::fopen(path, "w");
     if (!f) return fail(XS_EINVAL, "cannot open %s for writing", path);
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    std::fprintf(f, "# n_bucket clones count_bucket tile_blocks wg_threads updates_per_ns\n");
+    std::fprintf(f, "# n_bucket clones count_bucket tile_blocks wg_threads col_bytes "
+                    "updates_per_ns\n");
     for (auto &kv : g_tune)
-        std::fprintf(f, "%u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
+        std::fprintf(f, "%u %u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
                      kv.first.count_bucket, kv.second.tile_blocks, kv.second.wg_threads,
-                     kv.second.rate);
+                     kv.second.col_bytes, kv.second.rate);
     std::fclose(f);
     return XS_OK;
 }
@@ -702,13 +725,14 @@ xs_status xs_tune_load(const char *path) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        unsigned nb_, cl, cb, B, T;
+        unsigned nb_, cl, cb, B, T, C;
         double rate;
-        if (std::sscanf(line, "%u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &rate) != 6) continue;
-        if (!B || (B & (B - 1)) || B > (unsigned)xs::kMaxTileBlocks || !T || (T & (T - 1)) ||
-            T < 64 || T > 1024 || T < 8 * B)
+        if (std::sscanf(line, "%u %u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &C, &rate) != 7)
             continue;
-        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, rate};
+        if (!B || (B & (B - 1)) || B > (unsigned)xs::kMaxTileBlocks || !T || (T & (T - 1)) ||
+            T < 64 || T > 1024 || T < 8 * B || (C != 4 && C != 8 && C != 16))
+            continue;
+        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, C, rate};
     }
     std::fclose(f);
     return XS_OK;

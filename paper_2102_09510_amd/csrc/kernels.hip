@@ -124,10 +124,13 @@ __global__ __launch_bounds__(256) void qg_init(InstDev *I) {
 // keeps them all as ds_* instructions.
 extern __shared__ __align__(16) uint8_t xs_lds[];
 
-// Per-workgroup view of one tile. LDS locations are byte offsets into xs_lds.
+// Per-workgroup view of one tile. LDS locations are byte offsets into xs_lds. A task is one
+// spin of the current class and one column of CW bytes of the tile's rows (CW / 4 groups of 32
+// clones); `col` is this thread's column, fixed because the workgroup size is a multiple of the
+// column count.
 struct Tile {
     const InstDev *I;
-    uint32_t n, W, B, lB, rowb, ncol, lcol, ngrp, blk0, tid, col;
+    uint32_t n, W, B, lB, rowb, ncol, lcol, n16, l16, ngrp, blk0, tid, col;
     uint32_t st;         // state rows (records start at 0)
     uint32_t rb0, rb1;   // acceptance bytes, double-buffered by sweep parity
     uint32_t acc;        // per-group accumulators [8*B] (uint32)
@@ -144,8 +147,23 @@ __device__ __forceinline__ uint4 &lds_rec(uint32_t p) {
 __device__ __forceinline__ uint32_t &lds_u32(uint32_t off) {
     return *reinterpret_cast<uint32_t *>(xs_lds + off);
 }
-__device__ __forceinline__ uint4 lds_ld16(uint32_t base, uint32_t off) {
-    return *reinterpret_cast<const uint4 *>(xs_lds + base + off);
+
+// Column access: CW = 16, 8 or 4 bytes as one ds_read_b128 / b64 / b32.
+template <int CW> struct ColVec;
+template <> struct ColVec<16> { using T = uint4; };
+template <> struct ColVec<8> { using T = uint2; };
+template <> struct ColVec<4> { using T = uint32_t; };
+
+template <int CW>
+__device__ __forceinline__ void col_load(uint32_t addr, uint32_t (&w)[CW / 4]) {
+    const typename ColVec<CW>::T v = *reinterpret_cast<const typename ColVec<CW>::T *>(xs_lds + addr);
+    __builtin_memcpy(w, &v, CW);
+}
+template <int CW>
+__device__ __forceinline__ void col_store(uint32_t addr, const uint32_t (&w)[CW / 4]) {
+    typename ColVec<CW>::T v;
+    __builtin_memcpy(&v, w, CW);
+    *reinterpret_cast<typename ColVec<CW>::T *>(xs_lds + addr) = v;
 }
 
 // Acceptance bits of sweep t: one Philox call per (position, block) gives the eight 16-bit draws
@@ -165,40 +183,37 @@ __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t 
     }
 }
 
-// One task: the spin whose record is r, this thread's 16-byte column (four 32-clone words).
-template <bool kAcc>
+// One task: the spin whose record is r (position p), this thread's column.
+template <int CW, bool kAcc>
 __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, uint32_t rb,
-                                            uint32_t (&acc)[4]) {
-    const uint32_t self = r.x & 0xFFFFu;
-    const uint4 x = lds_ld16(T.colbase, self);
-    const uint4 a1 = lds_ld16(T.colbase, r.x >> 16);
-    const uint4 b1 = lds_ld16(T.colbase, r.y & 0xFFFFu);
-    const uint4 a2 = lds_ld16(T.colbase, r.y >> 16);
-    const uint4 b2 = lds_ld16(T.colbase, r.z & 0xFFFFu);
-    const uint4 a3 = lds_ld16(T.colbase, r.z >> 16);
-    const uint4 b3 = lds_ld16(T.colbase, r.w & 0xFFFFu);
+                                            uint32_t (&acc)[CW / 4]) {
+    constexpr int G = CW / 4;
+    const uint32_t self = T.colbase + (r.x & 0xFFFFu);
+    uint32_t x[G], a1[G], b1[G], a2[G], b2[G], a3[G], b3[G], y[G];
+    col_load<CW>(self, x);
+    col_load<CW>(T.colbase + (r.x >> 16), a1);
+    col_load<CW>(T.colbase + (r.y & 0xFFFFu), b1);
+    col_load<CW>(T.colbase + (r.y >> 16), a2);
+    col_load<CW>(T.colbase + (r.z & 0xFFFFu), b2);
+    col_load<CW>(T.colbase + (r.z >> 16), a3);
+    col_load<CW>(T.colbase + (r.w & 0xFFFFu), b3);
     const uint32_t meta = r.w >> 16;
     const uint32_t j1 = 0u - ((meta >> 13) & 1u);
     const uint32_t j2 = 0u - ((meta >> 14) & 1u);
     const uint32_t j3 = 0u - (meta >> 15);
-    const uint32_t nib = (uint32_t)xs_lds[rb + (p << T.lB) + T.rb_sel] >> T.rb_shift;
-    uint4 y;
-    y.x = qg_word<kAcc>(x.x, a1.x, b1.x, a2.x, b2.x, a3.x, b3.x, j1, j2, j3, 0u - (nib & 1u),
-                        acc[0]);
-    y.y = qg_word<kAcc>(x.y, a1.y, b1.y, a2.y, b2.y, a3.y, b3.y, j1, j2, j3,
-                        0u - ((nib >> 1) & 1u), acc[1]);
-    y.z = qg_word<kAcc>(x.z, a1.z, b1.z, a2.z, b2.z, a3.z, b3.z, j1, j2, j3,
-                        0u - ((nib >> 2) & 1u), acc[2]);
-    y.w = qg_word<kAcc>(x.w, a1.w, b1.w, a2.w, b2.w, a3.w, b3.w, j1, j2, j3,
-                        0u - ((nib >> 3) & 1u), acc[3]);
-    *reinterpret_cast<uint4 *>(xs_lds + T.colbase + self) = y;
+    const uint32_t bits = (uint32_t)xs_lds[rb + (p << T.lB) + T.rb_sel] >> T.rb_shift;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        y[g] = qg_word<kAcc>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
+                             0u - ((bits >> g) & 1u), acc[g]);
+    col_store<CW>(self, y);
 }
 
 // The classes of one sweep, a barrier before each (the first one also publishes the sweep's
 // acceptance bits and the previous sweep's last writes). Records and class descriptors are
 // read-only, so each thread fetches its first record of a class before that class's barrier.
-template <int NT, bool kAcc>
-__device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[4]) {
+template <int NT, int CW, bool kAcc>
+__device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
     uint32_t cd = lds_u32(T.cls);
     for (uint32_t c = 0; c < T.ncls; ++c) {
         const uint32_t cs = cd & 0xFFFFu;
@@ -208,45 +223,48 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
         if (T.tid < ntask) r0 = lds_rec(p0);
         if (c + 1 < T.ncls) cd = lds_u32(T.cls + 4 * (c + 1));
         __syncthreads();
-        if (T.tid < ntask) update_task<kAcc>(T, r0, p0, rb, acc);
+        if (T.tid < ntask) update_task<CW, kAcc>(T, r0, p0, rb, acc);
         for (uint32_t q = T.tid + NT; q < ntask; q += NT) {
             const uint32_t p = cs + (q >> T.lcol);
-            update_task<kAcc>(T, lds_rec(p), p, rb, acc);
+            update_task<CW, kAcc>(T, lds_rec(p), p, rb, acc);
         }
     }
 }
 
 // k >= 1 for any visited spin, over every spin of the current LDS state (no update): a zero
 // bit marks a clone whose configuration is a ground state.
-template <int NT>
-__device__ __forceinline__ void unsat_any(const Tile &T, uint32_t (&acc)[4]) {
+template <int NT, int CW>
+__device__ __forceinline__ void unsat_any(const Tile &T, uint32_t (&acc)[CW / 4]) {
+    constexpr int G = CW / 4;
     for (uint32_t q = T.tid; q < T.n << T.lcol; q += NT) {
         const uint4 r = lds_rec(q >> T.lcol);
-        const uint4 x = lds_ld16(T.colbase, r.x & 0xFFFFu);
-        const uint4 a1 = lds_ld16(T.colbase, r.x >> 16);
-        const uint4 b1 = lds_ld16(T.colbase, r.y & 0xFFFFu);
-        const uint4 a2 = lds_ld16(T.colbase, r.y >> 16);
-        const uint4 b2 = lds_ld16(T.colbase, r.z & 0xFFFFu);
-        const uint4 a3 = lds_ld16(T.colbase, r.z >> 16);
-        const uint4 b3 = lds_ld16(T.colbase, r.w & 0xFFFFu);
+        uint32_t x[G], a1[G], b1[G], a2[G], b2[G], a3[G], b3[G];
+        col_load<CW>(T.colbase + (r.x & 0xFFFFu), x);
+        col_load<CW>(T.colbase + (r.x >> 16), a1);
+        col_load<CW>(T.colbase + (r.y & 0xFFFFu), b1);
+        col_load<CW>(T.colbase + (r.y >> 16), a2);
+        col_load<CW>(T.colbase + (r.z & 0xFFFFu), b2);
+        col_load<CW>(T.colbase + (r.z >> 16), a3);
+        col_load<CW>(T.colbase + (r.w & 0xFFFFu), b3);
         const uint32_t meta = r.w >> 16;
         const uint32_t j1 = 0u - ((meta >> 13) & 1u);
         const uint32_t j2 = 0u - ((meta >> 14) & 1u);
         const uint32_t j3 = 0u - (meta >> 15);
-        qg_word<true>(x.x, a1.x, b1.x, a2.x, b2.x, a3.x, b3.x, j1, j2, j3, 0u, acc[0]);
-        qg_word<true>(x.y, a1.y, b1.y, a2.y, b2.y, a3.y, b3.y, j1, j2, j3, 0u, acc[1]);
-        qg_word<true>(x.z, a1.z, b1.z, a2.z, b2.z, a3.z, b3.z, j1, j2, j3, 0u, acc[2]);
-        qg_word<true>(x.w, a1.w, b1.w, a2.w, b2.w, a3.w, b3.w, j1, j2, j3, 0u, acc[3]);
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            qg_word<true>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3, 0u, acc[g]);
     }
 }
 
 // OR the threads' accumulators into the per-group LDS words (threads owning the same column
 // first combine within the wave). Caller synchronises before reading T.acc.
-__device__ __forceinline__ void reduce_acc(const Tile &T, uint32_t (&acc)[4]) {
+template <int CW>
+__device__ __forceinline__ void reduce_acc(const Tile &T, uint32_t (&acc)[CW / 4]) {
+    constexpr int G = CW / 4;
     for (uint32_t m = T.ncol; m < 64; m <<= 1)
-        for (int g = 0; g < 4; ++g) acc[g] |= __shfl_xor(acc[g], (int)m);
+        for (int g = 0; g < G; ++g) acc[g] |= __shfl_xor(acc[g], (int)m);
     if ((T.tid & 63) < T.ncol)
-        for (int g = 0; g < 4; ++g) atomicOr(&lds_u32(T.acc + 4 * (4 * T.col + g)), acc[g]);
+        for (int g = 0; g < G; ++g) atomicOr(&lds_u32(T.acc + 4 * (G * T.col + g)), acc[g]);
 }
 
 // Record first hits at sweep t for the clones of group T.tid (threads below ngrp) whose bit
@@ -271,12 +289,12 @@ __device__ __forceinline__ uint32_t record_hits(const Tile &T, uint32_t t, uint3
 
 // Ground-state check of the current LDS state, recording hits at sweep t. Returns nonzero in
 // every thread if some clone of the tile got a new hit. Ends synchronised.
-template <int NT>
+template <int NT, int CW>
 __device__ __forceinline__ uint32_t check_state(const Tile &T, uint32_t t, uint32_t &hm) {
-    uint32_t acc[4] = {0, 0, 0, 0};
+    uint32_t acc[CW / 4] = {};
     __syncthreads();  // state final, accumulators clear
-    unsat_any<NT>(T, acc);
-    reduce_acc(T, acc);
+    unsat_any<NT, CW>(T, acc);
+    reduce_acc<CW>(T, acc);
     if (T.tid == 0) lds_u32(T.flag) = 0;
     __syncthreads();
     if (T.tid < T.ngrp && record_hits(T, t, hm)) atomicOr(&lds_u32(T.flag), 1u);
@@ -284,11 +302,12 @@ __device__ __forceinline__ uint32_t check_state(const Tile &T, uint32_t t, uint3
     return lds_u32(T.flag);
 }
 
+// Stage the tile's rows global -> LDS in 16-byte pieces.
 template <int NT>
 __device__ __forceinline__ void load_state(const Tile &T) {
     const uint4 *src0 = reinterpret_cast<const uint4 *>(T.I->state + 4 * (size_t)T.blk0);
-    for (uint32_t q = T.tid; q < T.n * T.ncol; q += NT) {
-        const uint32_t i = q >> T.lcol, k = q & (T.ncol - 1);
+    for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
+        const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
         const uint4 *src = src0 + ((size_t)i * T.W >> 1);
         *reinterpret_cast<uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k) = src[k];
     }
@@ -303,9 +322,11 @@ __device__ __forceinline__ void load_state(const Tile &T) {
 // unchanged in global memory: the tile is written back at the end) with a per-sweep test, which
 // gives the exact first sweep; the replay draws the same random numbers, so it reproduces the
 // same trajectory.
-template <int NT>
+template <int NT, int CW>
 __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts,
                                                const uint2 *__restrict__ tiles) {
+    constexpr int G = CW / 4;        // groups per column
+    constexpr int LG = G == 4 ? 2 : G == 2 ? 1 : 0;
     const uint2 tile = tiles[blockIdx.x];
     const InstDev *I = insts + tile.x;
     if (I->done) return;
@@ -320,8 +341,10 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     T.B = I->tile_blocks;
     T.lB = I->log2_tile_blocks;
     T.rowb = T.B << 5;
-    T.ncol = T.B << 1;
-    T.lcol = T.lB + 1;
+    T.ncol = T.B << (3 - LG);
+    T.lcol = T.lB + 3 - LG;
+    T.n16 = T.B << 1;
+    T.l16 = T.lB + 1;
     T.ngrp = T.B << 3;
     T.blk0 = tile.y;
     T.tid = threadIdx.x;
@@ -333,9 +356,9 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     T.acc = T.rb1 + rbb;
     T.flag = T.acc + 4 * T.ngrp;
     T.cls = T.flag + 16;
-    T.colbase = T.st + (T.col << 4);
-    T.rb_sel = T.col >> 1;
-    T.rb_shift = (T.col & 1) << 2;
+    T.colbase = T.st + T.col * CW;
+    T.rb_sel = (T.col << LG) >> 3;
+    T.rb_shift = (T.col << LG) & 7;
     T.thr = I->thr;
     T.key0 = I->seed_lo;
     T.key1 = I->seed_hi;
@@ -367,30 +390,30 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
         lds_u32(T.acc + 4 * T.tid) = 0;
     }
     __syncthreads();  // records, state and accumulators visible to every thread
-    if (t0 == I->t_start) check_state<NT>(T, t0, hm);  // the run's start configuration
+    if (t0 == I->t_start) check_state<NT, CW>(T, t0, hm);  // the run's start configuration
 
     if (I->track) {
         // This instance keeps producing new ground-state clones: test every sweep.
         uint32_t hm_t = hm;
         accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
-            uint32_t acc[4] = {0, 0, 0, 0};
-            sweep<NT, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
-            reduce_acc(T, acc);
+            uint32_t acc[G] = {};
+            sweep<NT, CW, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+            reduce_acc<CW>(T, acc);
             __syncthreads();
             if (T.tid < T.ngrp) record_hits(T, t, hm_t);
             if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
         hm = hm_t;
-        check_state<NT>(T, t1, hm);
+        check_state<NT, CW>(T, t1, hm);
     } else {
-        uint32_t none[4] = {0, 0, 0, 0};  // unused: this loop tracks no ground states
+        uint32_t none[G] = {};  // unused: this loop tracks no ground states
         accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
-            sweep<NT, false>(T, (t & 1) ? T.rb1 : T.rb0, none);
+            sweep<NT, CW, false>(T, (t & 1) ? T.rb1 : T.rb0, none);
             if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
-        if (check_state<NT>(T, t1, hm)) {
+        if (check_state<NT, CW>(T, t1, hm)) {
             // Replay from the chunk's start state with a per-sweep ground-state test.
             uint32_t hm_replay = 0;  // hits before this chunk; the end check's are redone
             if (T.tid < T.ngrp) {
@@ -402,9 +425,9 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
             load_state<NT>(T);
             accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
             for (uint32_t t = t0; t < t1; ++t) {
-                uint32_t acc[4] = {0, 0, 0, 0};
-                sweep<NT, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
-                reduce_acc(T, acc);
+                uint32_t acc[G] = {};
+                sweep<NT, CW, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+                reduce_acc<CW>(T, acc);
                 __syncthreads();
                 if (T.tid < T.ngrp) record_hits(T, t, hm_replay);
                 if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
@@ -414,8 +437,8 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     }
     __syncthreads();
     uint4 *dst0 = reinterpret_cast<uint4 *>(I->state + 4 * (size_t)T.blk0);
-    for (uint32_t q = T.tid; q < T.n * T.ncol; q += NT) {
-        const uint32_t i = q >> T.lcol, k = q & (T.ncol - 1);
+    for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
+        const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
         (dst0 + ((size_t)i * T.W >> 1))[k] =
             *reinterpret_cast<const uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k);
     }
@@ -518,29 +541,41 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NT>
+template <int NT, int CW>
 hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk<NT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk<NT, CW>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(qg_chunk<NT>, dim3(n_tiles), dim3(NT), lds_bytes, s, d_insts, d_tiles);
+    hipLaunchKernelGGL((qg_chunk<NT, CW>), dim3(n_tiles), dim3(NT), lds_bytes, s, d_insts,
+                       d_tiles);
     return hipGetLastError();
 }
 
-hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        size_t lds_bytes, hipStream_t s) {
+template <int CW>
+hipError_t launch_chunk_cw(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+                           int threads, size_t lds_bytes, hipStream_t s) {
     switch (threads) {
-        case 64: return launch_chunk_nt<64>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 128: return launch_chunk_nt<128>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 256: return launch_chunk_nt<256>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 512: return launch_chunk_nt<512>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 1024: return launch_chunk_nt<1024>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 64: return launch_chunk_nt<64, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 128: return launch_chunk_nt<128, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 256: return launch_chunk_nt<256, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 512: return launch_chunk_nt<512, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 1024: return launch_chunk_nt<1024, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
+                        int col_bytes, size_t lds_bytes, hipStream_t s) {
+    switch (col_bytes) {
+        case 4: return launch_chunk_cw<4>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
+        case 8: return launch_chunk_cw<8>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
+        case 16: return launch_chunk_cw<16>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -88,7 +88,7 @@ struct xs_server {
             Request *r = pending.front();
             if (r->canceled) {
                 pending.pop_front();
-                complete(r, XS_ECANCELED, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0});
+                complete(r, XS_ECANCELED, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0});
                 delete r;
                 continue;
             }
@@ -96,7 +96,7 @@ struct xs_server {
             if (stats.bytes_in_use + r->bytes > cfg.hbm_budget_bytes) {
                 if (!resident.empty()) break;  // wait for memory to free up
                 pending.pop_front();           // can never fit
-                complete(r, XS_ENOMEM, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0});
+                complete(r, XS_ENOMEM, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0});
                 delete r;
                 continue;
             }
@@ -145,7 +145,7 @@ struct xs_server {
                 ++k;
                 continue;
             }
-            xs_run_result res{-1, -1, r->desc.t_cur, r->desc.t_cur - r->desc.t_start, 0, 0,
+            xs_run_result res{-1, -1, r->desc.t_cur, r->desc.t_cur - r->desc.t_start, 0, 0, 0,
                               (uint64_t)r->desc.n_words * 64 * r->desc.n *
                                   (r->desc.t_cur - r->desc.t_start),
                               0};
@@ -188,7 +188,7 @@ struct xs_server {
                 }
             for (const xsh::TileGroup &g : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + g.first, (int)g.count, (int)g.threads,
-                                        g.lds, stream));
+                                        (int)g.col_bytes, g.lds, stream));
             XS_HIP(xs::launch_decide(d_inst, R, d_active, stream));
             XS_HIP(hipMemcpyAsync(h.data(), d_inst, sizeof(xs::InstDev) * R,
                                   hipMemcpyDeviceToHost, stream));
@@ -223,6 +223,7 @@ struct xs_server {
                 res.sweeps_done = d.t_cur - d.t_start;
                 res.tile_blocks = d.tile_blocks;
                 res.wg_threads = d.wg_threads;
+                res.col_bytes = d.col_bytes;
                 res.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * res.sweeps_done;
                 const size_t n = d.n, nc = (size_t)d.n_words * 64;
                 if (r->outs.state)

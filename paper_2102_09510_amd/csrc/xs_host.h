@@ -58,7 +58,7 @@ void fill_desc(const xs_instance *I, const xs_run_config &c, const DeviceTables 
 
 // One chunk launch per workgroup size over a list of tiles.
 struct TileGroup {
-    uint32_t threads;
+    uint32_t threads, col_bytes;
     size_t first, count, lds;
 };
 // Choose tiling for descriptors h[0..count) (explicit config knobs, then the tuned table, then

@@ -34,7 +34,7 @@ struct InstDev {
     int32_t winner;   // lowest clone with first_hit == tts (final pass)
     uint32_t wg_threads;  // workgroup size of this instance's chunk launches (host side)
     uint32_t track;       // nonzero once a chunk had to be replayed: later chunks test every sweep
-    uint32_t pad;
+    uint32_t col_bytes;   // task column width of this instance's launches (host side)
 };
 
 }  // namespace xs
@@ -42,10 +42,10 @@ struct InstDev {
 // Launch wrappers implemented in kernels.hip (C++ linkage, internal to the library).
 namespace xs {
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
-// threads: 64, 128, 256, 512 or 1024; a multiple of 2 * tile_blocks of every tile it runs
-// and at least 8 * tile_blocks.
+// threads: 64, 128, 256, 512 or 1024, at least 8 * tile_blocks of every tile it runs;
+// col_bytes: 4, 8 or 16 bytes of a spin row per task.
 hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        size_t lds_bytes, hipStream_t s);
+                        int col_bytes, size_t lds_bytes, hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
 hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
 size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, uint32_t n_classes);

@@ -1,0 +1,141 @@
+"""Time-to-solution statistics of many-clone runs (host-side, on the solver's outputs).
+
+Section "Numerical results" and SM, "Derivation of the exponential distribution for the TTS":
+with many clones the run's TTS (its fastest clone) is exponentially distributed,
+P[TTS > t] = exp(-t / tau) (Eq. 2), with tau = t0 / N_cl where t0 is the single-clone scale. The
+p-th percentile is TTS_p = -ln(1 - p/100) tau, so tau can be estimated from any percentile or,
+better, from all runs (the mean).
+
+Section "Running with a short timeout": N_run runs capped at t_max, n of them successful. The
+posterior of tau under the scale-invariant prior 1/tau is proportional to
+(1/tau) (1 - exp(-t_max/tau))^n exp(-t_max/tau)^(N_run - n); for t_max << tau it becomes the
+inverse-gamma law with shape n and scale T_tot = N_run t_max.
+
+Times can be in any unit (sweeps here); censored runs are those that reached the cap.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def ttsp_from_tau(tau: float, p: float) -> float:
+    """TTS_p = -ln(1 - p/100) tau for the exponential law."""
+    return -math.log1p(-p / 100.0) * tau
+
+
+def tau_from_percentile(tts, p: float) -> float:
+    """tau estimated from the empirical p-th percentile of uncensored TTS values."""
+    return float(np.percentile(np.asarray(tts, dtype=float), p)) / -math.log1p(-p / 100.0)
+
+
+def tau_mean(tts) -> float:
+    """tau estimated as the mean TTS (maximum likelihood for uncensored exponential data)."""
+    return float(np.mean(np.asarray(tts, dtype=float)))
+
+
+def tau_censored_mle(times, solved) -> float:
+    """Maximum-likelihood tau from runs that either solved at `times` or were censored there:
+    total observed time over the number of successes."""
+    t = np.asarray(times, dtype=float)
+    s = np.asarray(solved, dtype=bool)
+    if not s.any():
+        return math.inf
+    return float(t.sum() / s.sum())
+
+
+def ks_exponential(tts, tau: float) -> tuple[float, float]:
+    """Kolmogorov-Smirnov distance of the sample to the exponential law with scale tau and the
+    asymptotic p-value (Kolmogorov distribution)."""
+    x = np.sort(np.asarray(tts, dtype=float))
+    n = x.size
+    cdf = 1.0 - np.exp(-x / tau)
+    i = np.arange(1, n + 1)
+    d = float(max(np.max(i / n - cdf), np.max(cdf - (i - 1) / n)))
+    # Kolmogorov series for P[sqrt(n) D > lam]
+    lam = (math.sqrt(n) + 0.12 + 0.11 / math.sqrt(n)) * d
+    pval = 2.0 * sum((-1) ** (k - 1) * math.exp(-2.0 * (k * lam) ** 2) for k in range(1, 101))
+    return d, float(min(max(pval, 0.0), 1.0))
+
+
+def single_clone_scale(tau: float, n_clones: int) -> float:
+    """t0 = tau N_cl (SM): the scale that stays fixed when the clone count changes."""
+    return tau * n_clones
+
+
+@dataclass
+class TimeoutPosterior:
+    """Posterior of tau after n successes among n_run runs capped at t_max (Section "Running
+    with a short timeout")."""
+    n: int
+    n_run: int
+    t_max: float
+
+    @property
+    def t_tot(self) -> float:
+        return self.n_run * self.t_max
+
+    def log_exact(self, tau):
+        """Unnormalised log posterior with the 1/tau prior and the binomial likelihood."""
+        tau = np.asarray(tau, dtype=float)
+        q = np.exp(-self.t_max / tau)
+        return (-np.log(tau) + self.n * np.log1p(-q) + (self.n_run - self.n) * (-self.t_max / tau)
+                + math.lgamma(self.n_run + 1) - math.lgamma(self.n + 1)
+                - math.lgamma(self.n_run - self.n + 1))
+
+    def pdf_inverse_gamma(self, tau):
+        """The t_max << tau form: T^n / (n-1)! exp(-T/tau) / tau^(n+1)."""
+        tau = np.asarray(tau, dtype=float)
+        T, n = self.t_tot, self.n
+        return np.exp(n * math.log(T) - math.lgamma(n) - T / tau - (n + 1) * np.log(tau))
+
+    def mean(self) -> float:
+        """Posterior mean of the inverse-gamma form, T/(n-1) (n > 1)."""
+        return self.t_tot / (self.n - 1) if self.n > 1 else math.inf
+
+    def mode(self) -> float:
+        return self.t_tot / (self.n + 1)
+
+    def quantile(self, q: float) -> float:
+        """Quantile of the inverse-gamma form: tau = T / x with x the (1-q) quantile of the
+        Gamma(n, 1) law, found by bisection on its regularised incomplete gamma function."""
+        from scipy.special import gammaincc
+
+        lo, hi = 1e-12, max(10.0, 10.0 * self.n)
+        target = q  # P[tau <= T/x] = P[X >= x] = Q(n, x)
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if gammaincc(self.n, mid) > target:
+                lo = mid
+            else:
+                hi = mid
+        return self.t_tot / (0.5 * (lo + hi))
+
+
+def summarize(tts, censored: int = 0, cap: float | None = None,
+              n_clones: int | None = None) -> dict:
+    """Estimates of tau from run TTS values; `censored` runs reached `cap` without a solution
+    (their time enters the maximum-likelihood estimate). Adds the predicted and empirical
+    TTS_99 and the exponential-law check of the solved runs."""
+    tts = np.asarray(tts, dtype=float)
+    out = {"runs": int(tts.size + censored), "solved": int(tts.size), "censored": int(censored)}
+    if tts.size >= 2:
+        if censored:
+            if cap is None:
+                raise ValueError("censored runs need the cap")
+            tau = tau_censored_mle(np.r_[tts, np.full(censored, cap)],
+                                   np.r_[np.ones(tts.size, bool), np.zeros(censored, bool)])
+        else:
+            tau = tau_mean(tts)
+        out.update(tau=tau, tts99_from_tau=ttsp_from_tau(tau, 99))
+        if not censored:
+            out.update(tau_from_p50=tau_from_percentile(tts, 50),
+                       tau_from_p90=tau_from_percentile(tts, 90),
+                       tts99_empirical=float(np.percentile(tts, 99)))
+            d, pv = ks_exponential(tts, tau)
+            out.update(ks_distance=d, ks_pvalue=pv)
+        if n_clones:
+            out["t0"] = single_clone_scale(tau, n_clones)
+    return out

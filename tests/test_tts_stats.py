@@ -1,0 +1,90 @@
+"""Pins of the TTS statistics against closed forms: the exponential law of the fastest clone
+(Eq. 2 and its derivation in the SM), percentile and mean estimators of tau, and the
+short-timeout posterior of tau (Section "Running with a short timeout")."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_2102_09510_amd import tts_stats as ts
+
+
+def test_percentile_closed_forms():
+    assert ts.ttsp_from_tau(2.0, 99) == pytest.approx(2.0 * math.log(100.0))
+    assert ts.ttsp_from_tau(3.0, 50) == pytest.approx(3.0 * math.log(2.0))
+    assert ts.ttsp_from_tau(1.0, 90) == pytest.approx(math.log(10.0))
+
+
+def test_estimators_on_exponential_samples():
+    rng = np.random.default_rng(1)
+    tau = 137.0
+    x = rng.exponential(tau, size=40000)
+    sd = tau / math.sqrt(x.size)
+    assert abs(ts.tau_mean(x) - tau) < 4 * sd
+    assert ts.tau_from_percentile(x, 50) == pytest.approx(tau, rel=0.03)
+    assert ts.tau_from_percentile(x, 90) == pytest.approx(tau, rel=0.03)
+    d, p = ts.ks_exponential(x, tau)
+    assert p > 0.01 and d < 0.01
+    d, p = ts.ks_exponential(rng.uniform(0, 2 * tau, size=4000), tau)
+    assert p < 1e-6
+
+
+def test_censored_mle():
+    rng = np.random.default_rng(2)
+    tau, cap = 50.0, 30.0
+    x = rng.exponential(tau, size=50000)
+    solved = x < cap
+    est = ts.tau_censored_mle(np.minimum(x, cap), solved)
+    assert est == pytest.approx(tau, rel=0.03)
+    s = ts.summarize(x[solved], censored=int((~solved).sum()), cap=cap)
+    assert s["tau"] == pytest.approx(est)
+
+
+def test_fastest_of_many_clones_is_exponential():
+    """SM derivation: single-clone times with p1(t) = 1 - t/t0 near 0 (here uniform on [0, t0])
+    give a fastest-of-N_cl time that is exponential with tau = t0 / N_cl."""
+    rng = np.random.default_rng(3)
+    t0, ncl, runs = 1.0e6, 2000, 3000
+    tts = np.array([rng.uniform(0, t0, size=ncl).min() for _ in range(runs)])
+    tau = ts.tau_mean(tts)
+    assert tau == pytest.approx(t0 / ncl, rel=0.06)
+    assert ts.ks_exponential(tts, tau)[1] > 0.01
+    assert ts.single_clone_scale(tau, ncl) == pytest.approx(t0, rel=0.06)
+
+
+@pytest.mark.parametrize("n,n_run,t_max", [(5, 1000, 1.0), (20, 400, 2.5), (3, 50, 10.0)])
+def test_inverse_gamma_posterior(n, n_run, t_max):
+    post = ts.TimeoutPosterior(n, n_run, t_max)
+    T = post.t_tot
+    f = lambda u: float(post.pdf_inverse_gamma(u))
+    total, _ = integrate.quad(f, 0, np.inf, limit=200)
+    assert total == pytest.approx(1.0, rel=1e-6)
+    if n > 1:
+        m, _ = integrate.quad(lambda u: u * f(u), 0, np.inf, limit=200)
+        assert m == pytest.approx(post.mean(), rel=1e-5)
+    grid = np.linspace(T / (n + 20), T / max(n - 0.9, 0.1), 20001)
+    assert grid[np.argmax(post.pdf_inverse_gamma(grid))] == pytest.approx(post.mode(), rel=1e-3)
+    med = post.quantile(0.5)
+    c, _ = integrate.quad(f, 0, med, limit=200)
+    assert c == pytest.approx(0.5, abs=1e-6)
+
+
+def test_exact_posterior_approaches_inverse_gamma_for_short_timeouts():
+    """With t_max << tau the binomial posterior with the 1/tau prior and the inverse-gamma
+    form agree (total variation small); with t_max comparable to tau they differ."""
+    for t_max, tv_max in ((0.01, 0.02), (3.0, None)):
+        post = ts.TimeoutPosterior(8, 800 if t_max < 1 else 10, t_max)
+        T = post.t_tot
+        grid = np.geomspace(T / 200, T * 5, 40001)
+        le = post.log_exact(grid)
+        pe = np.exp(le - le.max())
+        pe /= np.trapezoid(pe, grid)
+        pg = post.pdf_inverse_gamma(grid)
+        tv = 0.5 * np.trapezoid(np.abs(pe - pg), grid)
+        if tv_max is not None:
+            assert tv < tv_max
+        else:
+            assert tv > 0.05
