@@ -129,7 +129,7 @@ def workload_steady(args, xorsat, torch):
     cfgs = [xorsat.make_config(n_clones=clones, seed=run_seed(3, k), instance_id=k,
                                accept_thr=THR_PAPER, max_sweeps=sweeps, stop_on_first=False,
                                chunk_sweeps=args.chunk) for k in range(count)]
-    print(f"# steady: {count} x N={n} x {clones} clones, {sweeps} sweeps", flush=True)
+    print(f"# steady: {count} x N={n} x {clones} clones, {sweeps} sweeps", file=sys.stderr, flush=True)
     xorsat.profile_read(reset=True)
     xorsat.profile_enable(True)
     torch.cuda.synchronize()
@@ -168,14 +168,14 @@ def workload_uneven(args, xorsat, torch):
                                   accept_thr=THR_PAPER, max_sweeps=budget, stop_on_first=True,
                                   chunk_sweeps=args.chunk)
 
-    print(f"# uneven: {len(sizes)} instances, budget {budget}", flush=True)
+    print(f"# uneven: {len(sizes)} instances, budget {budget}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch = xorsat.run_batch(hs, [cfg(k) for k in range(len(hs))], want_energy=False)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     upd = sum(o.clone_spin_updates for o in batch)
-    print(f"# batched run done in {t_batch:.2f} s", flush=True)
+    print(f"# batched run done in {t_batch:.2f} s", file=sys.stderr, flush=True)
 
     srv = xorsat.Server(hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)))
     t0 = time.perf_counter()
@@ -192,7 +192,7 @@ def workload_uneven(args, xorsat, torch):
         served[tickets[c.ticket]] = c
     t_serve = time.perf_counter() - t0
     srv.close()
-    print(f"# served run done in {t_serve:.2f} s", flush=True)
+    print(f"# served run done in {t_serve:.2f} s", file=sys.stderr, flush=True)
 
     single_done = []
     t0 = time.perf_counter()
@@ -202,7 +202,7 @@ def workload_uneven(args, xorsat, torch):
         torch.cuda.synchronize()
         single_done.append(time.perf_counter() - t0)
     t_single = single_done[-1]
-    print(f"# one-at-a-time done in {t_single:.2f} s", flush=True)
+    print(f"# one-at-a-time done in {t_single:.2f} s", file=sys.stderr, flush=True)
     for k in range(len(hs)):
         a, b, c = batch[k], served[k], single[k]
         assert (a.tts_sweeps, a.winner_clone, a.end_sweep) == \
@@ -242,7 +242,7 @@ def workload_serve(args, xorsat, torch):
     arrivals = poisson_stream(args.rate, args.duration)
     budget = args.budget if args.budget != 50000 else 10000
     print(f"# serve: {len(arrivals)} requests over {args.duration} s, preparing instances",
-          flush=True)
+          file=sys.stderr, flush=True)
     hs = []
     for k, (_, n) in enumerate(arrivals):
         inst = planted_instance(n, gen_seed(5, k))
@@ -258,7 +258,7 @@ def workload_serve(args, xorsat, torch):
     done = {}
     nxt = 0
     max_resident = 0
-    print("# serving", flush=True)
+    print("# serving", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     last_report = t0
     while nxt < len(arrivals) or len(done) < len(arrivals):
@@ -273,7 +273,7 @@ def workload_serve(args, xorsat, torch):
         if time.perf_counter() - last_report > 10:
             last_report = time.perf_counter()
             print(f"# t={last_report - t0:.0f}s submitted {nxt} done {len(done)} "
-                  f"resident {srv.stats()['resident']}", flush=True)
+                  f"resident {srv.stats()['resident']}", file=sys.stderr, flush=True)
         if active == 0 and nxt < len(arrivals):
             time.sleep(max(0.0, min(0.002, arrivals[nxt][0] - (time.perf_counter() - t0))))
     wall = time.perf_counter() - t0
@@ -287,7 +287,7 @@ def workload_serve(args, xorsat, torch):
     finish = 0.0
     single_lat = []
     service = []
-    print(f"# one-at-a-time on the first {m} requests", flush=True)
+    print(f"# one-at-a-time on the first {m} requests", file=sys.stderr, flush=True)
     for k in range(m):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -357,8 +357,10 @@ def workload_tts(args, xorsat, torch):
                         "tau_posterior_mean": post.mean() if n_succ > 1 else None,
                         "tau_posterior_median": post.quantile(0.5) if n_succ > 0 else None}
         out[f"clones_{ncl}"] = s
-        print(f"# {ncl} clones: tau {s['tau']:.1f} sweeps, KS p {s['ks_pvalue']:.3f}", flush=True)
+        print(f"# {ncl} clones: tau {s['tau']:.1f} sweeps, KS p {s['ks_pvalue']:.3f}", file=sys.stderr, flush=True)
     out["tau_ratio_1024_over_4096"] = taus[1024] / taus[4096]
+    out["shifted_scale_ratio_1024_over_4096"] = (out["clones_1024"]["shifted_scale"] /
+                                                 out["clones_4096"]["shifted_scale"])
     return out
 
 
@@ -402,11 +404,12 @@ def main():
         return xorsat.run_batch(handles, cfgs, want_energy=True)
 
     print(f"# bench: {args.instances} x N={args.n} x {args.clones} clones, budget "
-          f"{args.budget} sweeps/step, warmup {args.warmup}, steps {args.steps}", flush=True)
+          f"{args.budget} sweeps/step, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
     for s in range(args.warmup):
         step(1000 + s)
         torch.cuda.synchronize()
-        print(f"# warmup step {s} done", flush=True)
+        print(f"# warmup step {s} done", file=sys.stderr, flush=True)
     xorsat.profile_read(reset=True)
     xorsat.profile_enable(True)
     torch.cuda.synchronize()
@@ -422,7 +425,7 @@ def main():
                 tts.append(o.tts_sweeps)
             else:
                 censored += 1
-        print(f"# step {s} done", flush=True)
+        print(f"# step {s} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     xorsat.profile_enable(False)

@@ -114,6 +114,9 @@ typedef struct {
                               8 * tile_blocks; 0 = chosen by the library. Speed only. */
     uint32_t col_bytes;    /* bytes of a spin row one thread updates per step: 4, 8 or 16
                               (32, 64 or 128 clones); 0 = chosen by the library. Speed only. */
+    uint32_t rec_global;   /* where a workgroup reads the per-spin neighbour records: 1 = global
+                              memory (through the caches; frees LDS for clone state), 2 = LDS,
+                              0 = chosen by the library. Speed only. */
 } xs_run_config;
 
 /*
@@ -142,6 +145,7 @@ typedef struct {
     uint32_t tile_blocks;        /* tiling used (result-neutral) */
     uint32_t wg_threads;         /* workgroup size used (result-neutral) */
     uint32_t col_bytes;          /* task column width used (result-neutral) */
+    uint32_t rec_global;         /* 1 if records were read from global memory (result-neutral) */
     uint64_t clone_spin_updates; /* n_clones * n * sweeps_done */
     double seconds;              /* wall time of the call */
 } xs_run_result;
@@ -239,12 +243,12 @@ xs_status xs_server_get_stats(const xs_server *srv, xs_server_stats *out);
  */
 #define XS_TUNE_MAX_TRIALS 64
 typedef struct {
-    uint32_t tile_blocks, wg_threads, col_bytes;
+    uint32_t tile_blocks, wg_threads, col_bytes, rec_global;
     double updates_per_ns; /* sweep-kernel rate of this trial */
 } xs_tune_trial;
 
 typedef struct {
-    uint32_t tile_blocks, wg_threads, col_bytes; /* the fastest choice */
+    uint32_t tile_blocks, wg_threads, col_bytes, rec_global; /* the fastest choice */
     double updates_per_ns;
     int32_t n_trials;
     xs_tune_trial trials[XS_TUNE_MAX_TRIALS];
@@ -252,7 +256,8 @@ typedef struct {
 
 xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count, void *stream,
                       xs_tune_result *out);
-/* Write / read the recorded choices as text ("n_bucket clones count_bucket B T CW rate" lines).
+/* Write / read the recorded choices as text ("n_bucket clones count_bucket B T CW GR rate"
+ * lines, GR = 1 for records in global memory, 2 for LDS).
  * Loading adds to (and overrides) the table in memory. */
 xs_status xs_tune_save(const char *path);
 xs_status xs_tune_load(const char *path);

@@ -137,6 +137,39 @@ xs_status ensure_tables(xs_instance *I, int device, DeviceTables *out) {
     return XS_OK;
 }
 
+xs_status attach_global_records(std::vector<xs::InstDev> &h, const xs_instance *const *insts,
+                                int count, int device) {
+    for (int k = 0; k < count; ++k) {
+        xs::InstDev &d = h[k];
+        if (!d.rec_global) {
+            d.grec = nullptr;
+            continue;
+        }
+        xs_instance *I = const_cast<xs_instance *>(insts[k]);
+        std::lock_guard<std::mutex> lock(I->mu);
+        auto &tabs = I->dev[device];
+        auto it = tabs.grec.find(d.tile_blocks);
+        if (it == tabs.grec.end()) {
+            const uint32_t rowb = 32u * d.tile_blocks;
+            std::vector<uint32_t> g(4 * (size_t)I->n);
+            for (int p = 0; p < I->n; ++p) {
+                const uint16_t *r = &I->rec[8 * (size_t)p];
+                const uint32_t i = r[0];
+                g[4 * p + 0] = (i * rowb) | ((r[1] * rowb) << 16);
+                g[4 * p + 1] = (r[2] * rowb) | ((r[3] * rowb) << 16);
+                g[4 * p + 2] = (r[4] * rowb) | ((r[5] * rowb) << 16);
+                g[4 * p + 3] = (r[6] * rowb) | ((i | ((uint32_t)r[7] << 13)) << 16);
+            }
+            uint4 *dp = nullptr;
+            XS_HIP(hipMalloc(&dp, 16 * (size_t)I->n));
+            XS_HIP(hipMemcpy(dp, g.data(), 16 * (size_t)I->n, hipMemcpyHostToDevice));
+            it = tabs.grec.emplace(d.tile_blocks, dp).first;
+        }
+        d.grec = it->second;
+    }
+    return XS_OK;
+}
+
 uint32_t ilog2(uint32_t v) {
     uint32_t r = 0;
     while ((1u << (r + 1)) <= v) ++r;
@@ -189,6 +222,7 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
     }
     if (cfg->col_bytes && cfg->col_bytes != 4 && cfg->col_bytes != 8 && cfg->col_bytes != 16)
         return fail(XS_EINVAL, "col_bytes %u must be 4, 8 or 16", cfg->col_bytes);
+    if (cfg->rec_global > 2) return fail(XS_EINVAL, "rec_global %u must be 0, 1 or 2", cfg->rec_global);
     if (cfg->wg_threads) {
         const uint32_t T = cfg->wg_threads;
         const uint32_t B = cfg->tile_blocks;
@@ -204,9 +238,13 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
 // full 32-spin class, within [256, 1024].
 uint32_t default_threads(uint32_t B) { return std::min(1024u, std::max(256u, 64u * B)); }
 
-// Default task column: narrow columns for small tiles, so that a 32-spin class still spreads
-// over the workgroup (a one-block tile has 64 tasks of 16 bytes but 256 of 4 bytes).
-uint32_t default_col_bytes(uint32_t B) { return B >= 4 ? 16u : B == 2 ? 8u : 4u; }
+// Default task column: narrower columns for small tiles, so that a 32-spin class still spreads
+// over the workgroup (a one-block tile has 64 tasks of 16 bytes, 128 of 8 bytes).
+uint32_t default_col_bytes(uint32_t B) { return B >= 4 ? 16u : 8u; }
+
+// Default record placement: global memory once the records would take a large share of the
+// workgroup's LDS (n >= 1024: 16 KB or more).
+uint32_t default_rec_global(uint32_t n) { return n >= 1024 ? 1u : 0u; }
 
 // Options of one driver call beyond the public configuration.
 struct RunOpts {
@@ -223,7 +261,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    uint32_t tile_blocks, wg_threads, col_bytes;
+    uint32_t tile_blocks, wg_threads, col_bytes, rec_global;
     double rate;
 };
 std::mutex g_tune_mu;
@@ -292,8 +330,8 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         xs::InstDev &d = h[k];
         const uint32_t nb = c.n_clones / 256;
         uint32_t B = c.tile_blocks ? c.tile_blocks : max_tile_blocks(d.n, nb, 1024);
-        uint32_t tuned_T = 0, tuned_C = 0;
-        if (!c.tile_blocks && !c.wg_threads && !c.col_bytes) {
+        uint32_t tuned_T = 0, tuned_C = 0, tuned_G = 0;
+        if (!c.tile_blocks && !c.wg_threads && !c.col_bytes && !c.rec_global) {
             std::lock_guard<std::mutex> lock(g_tune_mu);
             auto it = g_tune.find(tune_key(d.n, c.n_clones, count));
             if (it != g_tune.end() && nb % it->second.tile_blocks == 0 &&
@@ -301,11 +339,13 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
                 B = it->second.tile_blocks;
                 tuned_T = it->second.wg_threads;
                 tuned_C = it->second.col_bytes;
+                tuned_G = it->second.rec_global;
             }
         }
         d.tile_blocks = B;
         d.wg_threads = tuned_T;  // 0 unless tuned
         d.col_bytes = tuned_C;
+        d.rec_global = tuned_G;  // 0 = not tuned, 1 = global, 2 = LDS
     }
     // Shrink automatic tiles while the batch has too few workgroups.
     auto count_tiles = [&]() {
@@ -323,9 +363,10 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
             }
         if (!changed) break;
     }
-    // Tiles grouped by (workgroup size, column width): one launch per group and chunk.
-    std::map<std::pair<uint32_t, uint32_t>, std::vector<uint2>> by_launch;
-    std::map<std::pair<uint32_t, uint32_t>, size_t> lds_of;
+    // Tiles grouped by (workgroup size, column width, record placement): one launch per group
+    // and chunk.
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<uint2>> by_launch;
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, size_t> lds_of;
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
         d.log2_tile_blocks = ilog2(d.tile_blocks);
@@ -338,16 +379,22 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
                            : d.col_bytes      ? d.col_bytes
                                               : default_col_bytes(d.tile_blocks);
         d.col_bytes = C;
+        const uint32_t GRc = cfgs[k].rec_global ? cfgs[k].rec_global
+                             : d.rec_global       ? d.rec_global
+                                                  : (default_rec_global(d.n) ? 1u : 2u);
+        d.rec_global = GRc == 1 ? 1u : 0u;
         const uint32_t nb = cfgs[k].n_clones / 256;
-        const auto key = std::make_pair(T, C);
+        const auto key = std::make_tuple(T, C, d.rec_global);
         auto &v = by_launch[key];
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) v.push_back(make_uint2((uint32_t)k, b0));
-        lds_of[key] = std::max(lds_of[key], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes));
+        lds_of[key] = std::max(lds_of[key], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes,
+                                                                d.rec_global != 0));
     }
     tiles.clear();
     groups.clear();
     for (auto &kv : by_launch) {
-        groups.push_back(TileGroup{kv.first.first, kv.first.second, tiles.size(), kv.second.size(),
+        groups.push_back(TileGroup{std::get<0>(kv.first), std::get<1>(kv.first),
+                                   std::get<2>(kv.first), tiles.size(), kv.second.size(),
                                    lds_of[kv.first]});
         tiles.insert(tiles.end(), kv.second.begin(), kv.second.end());
     }
@@ -378,7 +425,9 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     }
     std::vector<TileGroup> groups;
     {
-        const xs_status st = tile_instances(h, cfgs, count, tiles, groups);
+        xs_status st = tile_instances(h, cfgs, count, tiles, groups);
+        if (st != XS_OK) return st;
+        st = attach_global_records(h, insts, count, device);
         if (st != XS_OK) return st;
     }
     // Per-call device scratch: descriptors, tiles, the running-instance counter and the
@@ -435,7 +484,8 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             if (with_events) XS_HIP(hipEventRecord(ev[2 * g], s));
             for (const TileGroup &gr : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + gr.first, (int)gr.count,
-                                        (int)gr.threads, (int)gr.col_bytes, gr.lds, s));
+                                        (int)gr.threads, (int)gr.col_bytes, gr.rec_global != 0,
+                                        gr.lds, s));
             if (with_events) XS_HIP(hipEventRecord(ev[2 * g + 1], s));
             XS_HIP(xs::launch_decide(d_inst, count, d_active, s));
         }
@@ -512,6 +562,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         r.tile_blocks = d.tile_blocks;
         r.wg_threads = d.wg_threads;
         r.col_bytes = d.col_bytes;
+        r.rec_global = d.rec_global;
         r.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * r.sweeps_done;
         r.seconds = secs;
         if (bufs[k].solved && d.winner != INT32_MAX)
@@ -595,6 +646,7 @@ void xs_instance_destroy(xs_instance *I) {
         (void)hipFree(kv.second.rec);
         (void)hipFree(kv.second.class_off);
         (void)hipFree(kv.second.tri);
+        for (auto &g : kv.second.grec) (void)hipFree(g.second);
     }
     if (cur >= 0 && !I->dev.empty()) (void)hipSetDevice(cur);
     delete I;
@@ -660,45 +712,50 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
     }
     std::memset(out, 0, sizeof *out);
     for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
-        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls) > 160 * 1024) continue;
+        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls, true) > 160 * 1024) continue;
         for (uint32_t T = 128; T <= 1024; T *= 2) {
             if (T < 8 * B || (T == 128 && B > 2)) continue;
-            for (uint32_t C = 4; C <= 16; C *= 2) {
-                // skip columns that leave most threads without a task in a full class
-                if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
-                    continue;
-                for (auto &c : cfgs) {
-                    c.tile_blocks = B;
-                    c.wg_threads = T;
-                    c.col_bytes = C;
+            for (uint32_t C = 4; C <= 16; C *= 2)
+                for (uint32_t G = (n >= 512 ? 1u : 2u); G <= 2; ++G) {
+                    // skip columns that leave most threads without a task in a full class
+                    if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
+                        continue;
+                    if (xs::chunk_lds_bytes(n, B, ncls, G == 1) > 160 * 1024) continue;
+                    for (auto &c : cfgs) {
+                        c.tile_blocks = B;
+                        c.wg_threads = T;
+                        c.col_bytes = C;
+                        c.rec_global = G;
+                    }
+                    RunOpts opt;
+                    double ms = 0.0;
+                    opt.kernel_ms = &ms;
+                    xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(),
+                                             stream, res.data(), opt);  // warm
+                    if (st != XS_OK) return st;
+                    ms = 0.0;
+                    st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
+                                   res.data(), opt);
+                    if (st != XS_OK) return st;
+                    uint64_t upd = 0;
+                    for (auto &r : res) upd += r.clone_spin_updates;
+                    const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
+                    out->trials[out->n_trials++] = xs_tune_trial{B, T, C, G, rate};
+                    if (rate > out->updates_per_ns) {
+                        out->updates_per_ns = rate;
+                        out->tile_blocks = B;
+                        out->wg_threads = T;
+                        out->col_bytes = C;
+                        out->rec_global = G;
+                    }
                 }
-                RunOpts opt;
-                double ms = 0.0;
-                opt.kernel_ms = &ms;
-                xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
-                                         res.data(), opt);  // warm
-                if (st != XS_OK) return st;
-                ms = 0.0;
-                st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
-                               res.data(), opt);
-                if (st != XS_OK) return st;
-                uint64_t upd = 0;
-                for (auto &r : res) upd += r.clone_spin_updates;
-                const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
-                out->trials[out->n_trials++] = xs_tune_trial{B, T, C, rate};
-                if (rate > out->updates_per_ns) {
-                    out->updates_per_ns = rate;
-                    out->tile_blocks = B;
-                    out->wg_threads = T;
-                    out->col_bytes = C;
-                }
-            }
         }
     }
     if (!out->n_trials) return fail(XS_EINVAL, "no valid launch configuration");
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[tune_key(n, n_clones, count)] = TuneVal{out->tile_blocks, out->wg_threads,
-                                                   out->col_bytes, out->updates_per_ns};
+                                                   out->col_bytes, out->rec_global,
+                                                   out->updates_per_ns};
     return XS_OK;
 }
 
@@ -708,11 +765,11 @@ xs_status xs_tune_save(const char *path) {
     if (!f) return fail(XS_EINVAL, "cannot open %s for writing", path);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     std::fprintf(f, "# n_bucket clones count_bucket tile_blocks wg_threads col_bytes "
-                    "updates_per_ns\n");
+                    "rec_global updates_per_ns\n");
     for (auto &kv : g_tune)
-        std::fprintf(f, "%u %u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
+        std::fprintf(f, "%u %u %u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
                      kv.first.count_bucket, kv.second.tile_blocks, kv.second.wg_threads,
-                     kv.second.col_bytes, kv.second.rate);
+                     kv.second.col_bytes, kv.second.rec_global, kv.second.rate);
     std::fclose(f);
     return XS_OK;
 }
@@ -725,14 +782,16 @@ xs_status xs_tune_load(const char *path) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        unsigned nb_, cl, cb, B, T, C;
+        unsigned nb_, cl, cb, B, T, C, G;
         double rate;
-        if (std::sscanf(line, "%u %u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &C, &rate) != 7)
+        if (std::sscanf(line, "%u %u %u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &C, &G,
+                        &rate) != 8)
             continue;
         if (!B || (B & (B - 1)) || B > (unsigned)xs::kMaxTileBlocks || !T || (T & (T - 1)) ||
-            T < 64 || T > 1024 || T < 8 * B || (C != 4 && C != 8 && C != 16))
+            T < 64 || T > 1024 || T < 8 * B || (C != 4 && C != 8 && C != 16) ||
+            (G != 1 && G != 2))
             continue;
-        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, C, rate};
+        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, C, G, rate};
     }
     std::fclose(f);
     return XS_OK;

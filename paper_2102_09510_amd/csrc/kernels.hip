@@ -130,6 +130,7 @@ extern __shared__ __align__(16) uint8_t xs_lds[];
 // column count.
 struct Tile {
     const InstDev *I;
+    const uint4 *grec;   // records in global memory (GR kernels), offsets for this tile's rows
     uint32_t n, W, B, lB, rowb, ncol, lcol, n16, l16, ngrp, blk0, tid, col;
     uint32_t st;         // state rows (records start at 0)
     uint32_t rb0, rb1;   // acceptance bytes, double-buffered by sweep parity
@@ -146,6 +147,13 @@ __device__ __forceinline__ uint4 &lds_rec(uint32_t p) {
 }
 __device__ __forceinline__ uint32_t &lds_u32(uint32_t off) {
     return *reinterpret_cast<uint32_t *>(xs_lds + off);
+}
+// The record of position p: in LDS, or in global memory (read through the caches) when the
+// tile keeps its LDS for clone state (GR).
+template <bool GR>
+__device__ __forceinline__ uint4 rec_at(const Tile &T, uint32_t p) {
+    if (GR) return T.grec[p];
+    return lds_rec(p);
 }
 
 // Column access: CW = 16, 8 or 4 bytes as one ds_read_b128 / b64 / b32.
@@ -168,11 +176,11 @@ __device__ __forceinline__ void col_store(uint32_t addr, const uint32_t (&w)[CW 
 
 // Acceptance bits of sweep t: one Philox call per (position, block) gives the eight 16-bit draws
 // of the block's eight groups.
-template <int NT>
+template <int NT, bool GR>
 __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t rb) {
     for (uint32_t q = T.tid; q < T.n * T.B; q += NT) {
         const uint32_t p = q >> T.lB, b = q & (T.B - 1);
-        const uint32_t i = (lds_rec(p).w >> 16) & 0x1FFFu;
+        const uint32_t i = (rec_at<GR>(T, p).w >> 16) & 0x1FFFu;
         const uint4 o = philox10(make_uint4(i, t, T.blk0 + b, T.iid), T.key0, T.key1);
         const uint32_t thr = T.thr;
         const uint32_t bits = below(o.x & 0xFFFFu, thr) | below(o.x >> 16, thr) << 1 |
@@ -212,7 +220,7 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, 
 // The classes of one sweep, a barrier before each (the first one also publishes the sweep's
 // acceptance bits and the previous sweep's last writes). Records and class descriptors are
 // read-only, so each thread fetches its first record of a class before that class's barrier.
-template <int NT, int CW, bool kAcc>
+template <int NT, int CW, bool GR, bool kAcc>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
     uint32_t cd = lds_u32(T.cls);
     for (uint32_t c = 0; c < T.ncls; ++c) {
@@ -220,24 +228,24 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
         const uint32_t ntask = (cd >> 16) << T.lcol;
         const uint32_t p0 = cs + (T.tid >> T.lcol);
         uint4 r0 = make_uint4(0, 0, 0, 0);
-        if (T.tid < ntask) r0 = lds_rec(p0);
+        if (T.tid < ntask) r0 = rec_at<GR>(T, p0);
         if (c + 1 < T.ncls) cd = lds_u32(T.cls + 4 * (c + 1));
         __syncthreads();
         if (T.tid < ntask) update_task<CW, kAcc>(T, r0, p0, rb, acc);
         for (uint32_t q = T.tid + NT; q < ntask; q += NT) {
             const uint32_t p = cs + (q >> T.lcol);
-            update_task<CW, kAcc>(T, lds_rec(p), p, rb, acc);
+            update_task<CW, kAcc>(T, rec_at<GR>(T, p), p, rb, acc);
         }
     }
 }
 
 // k >= 1 for any visited spin, over every spin of the current LDS state (no update): a zero
 // bit marks a clone whose configuration is a ground state.
-template <int NT, int CW>
+template <int NT, int CW, bool GR>
 __device__ __forceinline__ void unsat_any(const Tile &T, uint32_t (&acc)[CW / 4]) {
     constexpr int G = CW / 4;
     for (uint32_t q = T.tid; q < T.n << T.lcol; q += NT) {
-        const uint4 r = lds_rec(q >> T.lcol);
+        const uint4 r = rec_at<GR>(T, q >> T.lcol);
         uint32_t x[G], a1[G], b1[G], a2[G], b2[G], a3[G], b3[G];
         col_load<CW>(T.colbase + (r.x & 0xFFFFu), x);
         col_load<CW>(T.colbase + (r.x >> 16), a1);
@@ -289,11 +297,11 @@ __device__ __forceinline__ uint32_t record_hits(const Tile &T, uint32_t t, uint3
 
 // Ground-state check of the current LDS state, recording hits at sweep t. Returns nonzero in
 // every thread if some clone of the tile got a new hit. Ends synchronised.
-template <int NT, int CW>
+template <int NT, int CW, bool GR>
 __device__ __forceinline__ uint32_t check_state(const Tile &T, uint32_t t, uint32_t &hm) {
     uint32_t acc[CW / 4] = {};
     __syncthreads();  // state final, accumulators clear
-    unsat_any<NT, CW>(T, acc);
+    unsat_any<NT, CW, GR>(T, acc);
     reduce_acc<CW>(T, acc);
     if (T.tid == 0) lds_u32(T.flag) = 0;
     __syncthreads();
@@ -322,7 +330,7 @@ __device__ __forceinline__ void load_state(const Tile &T) {
 // unchanged in global memory: the tile is written back at the end) with a per-sweep test, which
 // gives the exact first sweep; the replay draws the same random numbers, so it reproduces the
 // same trajectory.
-template <int NT, int CW>
+template <int NT, int CW, bool GR>
 __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts,
                                                const uint2 *__restrict__ tiles) {
     constexpr int G = CW / 4;        // groups per column
@@ -349,7 +357,8 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     T.blk0 = tile.y;
     T.tid = threadIdx.x;
     T.col = T.tid & (T.ncol - 1);  // fixed per thread: NT is a multiple of ncol
-    T.st = (uint32_t)lds_rec_bytes(T.n);
+    T.grec = I->grec;
+    T.st = GR ? 0u : (uint32_t)lds_rec_bytes(T.n);
     const uint32_t rbb = (uint32_t)align16((size_t)T.n * T.B);
     T.rb0 = T.st + T.n * T.rowb;
     T.rb1 = T.rb0 + rbb;
@@ -369,8 +378,8 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
         lds_u32(T.cls + 4 * c) = a | ((b - a) << 16);
     }
 
-    // Records: spin indices -> byte offsets of the rows in this tile.
-    for (uint32_t p = T.tid; p < T.n; p += NT) {
+    // Records: spin indices -> byte offsets of the rows in this tile (GR: done by the host).
+    for (uint32_t p = T.tid; !GR && p < T.n; p += NT) {
         const uint4 r = I->rec[p];
         const uint32_t rowb = T.rowb;
         const uint32_t i = r.x & 0xFFFFu;
@@ -390,30 +399,30 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
         lds_u32(T.acc + 4 * T.tid) = 0;
     }
     __syncthreads();  // records, state and accumulators visible to every thread
-    if (t0 == I->t_start) check_state<NT, CW>(T, t0, hm);  // the run's start configuration
+    if (t0 == I->t_start) check_state<NT, CW, GR>(T, t0, hm);  // the run's start configuration
 
     if (I->track) {
         // This instance keeps producing new ground-state clones: test every sweep.
         uint32_t hm_t = hm;
-        accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+        accept_bits<NT, GR>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
             uint32_t acc[G] = {};
-            sweep<NT, CW, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+            sweep<NT, CW, GR, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
             reduce_acc<CW>(T, acc);
             __syncthreads();
             if (T.tid < T.ngrp) record_hits(T, t, hm_t);
-            if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+            if (t + 1 < t1) accept_bits<NT, GR>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
         hm = hm_t;
-        check_state<NT, CW>(T, t1, hm);
+        check_state<NT, CW, GR>(T, t1, hm);
     } else {
         uint32_t none[G] = {};  // unused: this loop tracks no ground states
-        accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+        accept_bits<NT, GR>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
-            sweep<NT, CW, false>(T, (t & 1) ? T.rb1 : T.rb0, none);
-            if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+            sweep<NT, CW, GR, false>(T, (t & 1) ? T.rb1 : T.rb0, none);
+            if (t + 1 < t1) accept_bits<NT, GR>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
-        if (check_state<NT, CW>(T, t1, hm)) {
+        if (check_state<NT, CW, GR>(T, t1, hm)) {
             // Replay from the chunk's start state with a per-sweep ground-state test.
             uint32_t hm_replay = 0;  // hits before this chunk; the end check's are redone
             if (T.tid < T.ngrp) {
@@ -423,14 +432,14 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
             }
             __syncthreads();
             load_state<NT>(T);
-            accept_bits<NT>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+            accept_bits<NT, GR>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
             for (uint32_t t = t0; t < t1; ++t) {
                 uint32_t acc[G] = {};
-                sweep<NT, CW, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+                sweep<NT, CW, GR, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
                 reduce_acc<CW>(T, acc);
                 __syncthreads();
                 if (T.tid < T.ngrp) record_hits(T, t, hm_replay);
-                if (t + 1 < t1) accept_bits<NT>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+                if (t + 1 < t1) accept_bits<NT, GR>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
             }
             if (T.tid == 0) atomicOr(const_cast<uint32_t *>(&I->track), 1u);
         }
@@ -529,9 +538,9 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 
 }  // namespace
 
-size_t chunk_lds_bytes(uint32_t n, uint32_t B, uint32_t n_classes) {
-    return lds_rec_bytes(n) + (size_t)n * B * 32 + 2 * align16((size_t)n * B) +
-           (size_t)B * 8 * 4 + 16 + 4 * (size_t)n_classes;
+size_t chunk_lds_bytes(uint32_t n, uint32_t B, uint32_t n_classes, bool rec_global) {
+    return (rec_global ? 0 : lds_rec_bytes(n)) + (size_t)n * B * 32 +
+           2 * align16((size_t)n * B) + (size_t)B * 8 * 4 + 16 + 4 * (size_t)n_classes;
 }
 
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
@@ -541,43 +550,52 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NT, int CW>
+template <int NT, int CW, bool GR>
 hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk<NT, CW>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk<NT, CW, GR>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((qg_chunk<NT, CW>), dim3(n_tiles), dim3(NT), lds_bytes, s, d_insts,
+    hipLaunchKernelGGL((qg_chunk<NT, CW, GR>), dim3(n_tiles), dim3(NT), lds_bytes, s, d_insts,
                        d_tiles);
     return hipGetLastError();
 }
 
-template <int CW>
+template <int CW, bool GR>
 hipError_t launch_chunk_cw(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            int threads, size_t lds_bytes, hipStream_t s) {
     switch (threads) {
-        case 64: return launch_chunk_nt<64, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 128: return launch_chunk_nt<128, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 256: return launch_chunk_nt<256, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 512: return launch_chunk_nt<512, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 1024: return launch_chunk_nt<1024, CW>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 64: return launch_chunk_nt<64, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 128: return launch_chunk_nt<128, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 256: return launch_chunk_nt<256, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 512: return launch_chunk_nt<512, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 1024: return launch_chunk_nt<1024, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool GR>
+hipError_t launch_chunk_gr(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+                           int threads, int col_bytes, size_t lds_bytes, hipStream_t s) {
+    switch (col_bytes) {
+        case 4: return launch_chunk_cw<4, GR>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
+        case 8: return launch_chunk_cw<8, GR>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
+        case 16: return launch_chunk_cw<16, GR>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        int col_bytes, size_t lds_bytes, hipStream_t s) {
-    switch (col_bytes) {
-        case 4: return launch_chunk_cw<4>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
-        case 8: return launch_chunk_cw<8>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
-        case 16: return launch_chunk_cw<16>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
-        default: return hipErrorInvalidValue;
-    }
+                        int col_bytes, bool rec_global, size_t lds_bytes, hipStream_t s) {
+    return rec_global ? launch_chunk_gr<true>(d_insts, d_tiles, n_tiles, threads, col_bytes,
+                                              lds_bytes, s)
+                      : launch_chunk_gr<false>(d_insts, d_tiles, n_tiles, threads, col_bytes,
+                                               lds_bytes, s);
 }
 
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s) {

@@ -88,7 +88,7 @@ struct xs_server {
             Request *r = pending.front();
             if (r->canceled) {
                 pending.pop_front();
-                complete(r, XS_ECANCELED, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0});
+                complete(r, XS_ECANCELED, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0, 0});
                 delete r;
                 continue;
             }
@@ -96,7 +96,7 @@ struct xs_server {
             if (stats.bytes_in_use + r->bytes > cfg.hbm_budget_bytes) {
                 if (!resident.empty()) break;  // wait for memory to free up
                 pending.pop_front();           // can never fit
-                complete(r, XS_ENOMEM, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0});
+                complete(r, XS_ENOMEM, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0, 0});
                 delete r;
                 continue;
             }
@@ -145,7 +145,7 @@ struct xs_server {
                 ++k;
                 continue;
             }
-            xs_run_result res{-1, -1, r->desc.t_cur, r->desc.t_cur - r->desc.t_start, 0, 0, 0,
+            xs_run_result res{-1, -1, r->desc.t_cur, r->desc.t_cur - r->desc.t_start, 0, 0, 0, 0,
                               (uint64_t)r->desc.n_words * 64 * r->desc.n *
                                   (r->desc.t_cur - r->desc.t_start),
                               0};
@@ -170,6 +170,10 @@ struct xs_server {
             std::vector<xsh::TileGroup> groups;
             st = xsh::tile_instances(h, cfgs.data(), R, tiles, groups);
             if (st != XS_OK) return st;
+            std::vector<const xs_instance *> insts(R);
+            for (int k = 0; k < R; ++k) insts[k] = resident[k]->inst;
+            st = xsh::attach_global_records(h, insts.data(), R, device);
+            if (st != XS_OK) return st;
             const size_t off_tiles = align256(sizeof(xs::InstDev) * R);
             const size_t off_active = off_tiles + align256(sizeof(uint2) * tiles.size());
             st = ensure_scratch(off_active + 256);
@@ -188,7 +192,7 @@ struct xs_server {
                 }
             for (const xsh::TileGroup &g : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + g.first, (int)g.count, (int)g.threads,
-                                        (int)g.col_bytes, g.lds, stream));
+                                        (int)g.col_bytes, g.rec_global != 0, g.lds, stream));
             XS_HIP(xs::launch_decide(d_inst, R, d_active, stream));
             XS_HIP(hipMemcpyAsync(h.data(), d_inst, sizeof(xs::InstDev) * R,
                                   hipMemcpyDeviceToHost, stream));
@@ -224,6 +228,7 @@ struct xs_server {
                 res.tile_blocks = d.tile_blocks;
                 res.wg_threads = d.wg_threads;
                 res.col_bytes = d.col_bytes;
+                res.rec_global = d.rec_global;
                 res.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * res.sweeps_done;
                 const size_t n = d.n, nc = (size_t)d.n_words * 64;
                 if (r->outs.state)

@@ -13,6 +13,7 @@
 namespace xsh {
 
 struct DeviceTables {
+    std::map<uint32_t, uint4 *> grec;  // records as row offsets, per tile_blocks
     uint4 *rec = nullptr;
     int32_t *class_off = nullptr;
     uint2 *tri = nullptr;
@@ -58,9 +59,13 @@ void fill_desc(const xs_instance *I, const xs_run_config &c, const DeviceTables 
 
 // One chunk launch per workgroup size over a list of tiles.
 struct TileGroup {
-    uint32_t threads, col_bytes;
+    uint32_t threads, col_bytes, rec_global;
     size_t first, count, lds;
 };
+// Point every descriptor that reads its records from global memory at its instance's table for
+// its tiling (uploaded on first use).
+xs_status attach_global_records(std::vector<xs::InstDev> &h, const xs_instance *const *insts,
+                                int count, int device);
 // Choose tiling for descriptors h[0..count) (explicit config knobs, then the tuned table, then
 // the default rule), fill tile_blocks / log2 / wg_threads, and build the tile list and groups.
 xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs, int count,

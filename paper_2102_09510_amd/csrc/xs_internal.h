@@ -17,6 +17,7 @@ struct InstDev {
     const uint4 *rec;        // [n] 16-byte records in update order: u16 {i, a1, b1, a2, b2, a3, b3, jbits}
     const int32_t *class_off; // [n_classes + 1]
     const uint2 *tri;        // [n] triplets: x = a | b << 16, y = c | j << 16 (j = 1 <=> J = -1)
+    const uint4 *grec;       // [n] records with row offsets for this tiling (global-record kernels)
     // caller buffers
     uint64_t *state;         // [n][n_words]
     int32_t *first_hit;      // [n_clones]
@@ -35,6 +36,8 @@ struct InstDev {
     uint32_t wg_threads;  // workgroup size of this instance's chunk launches (host side)
     uint32_t track;       // nonzero once a chunk had to be replayed: later chunks test every sweep
     uint32_t col_bytes;   // task column width of this instance's launches (host side)
+    uint32_t rec_global;  // records read from global memory (host side: selects the kernel)
+    uint32_t pad;
 };
 
 }  // namespace xs
@@ -43,10 +46,11 @@ struct InstDev {
 namespace xs {
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
 // threads: 64, 128, 256, 512 or 1024, at least 8 * tile_blocks of every tile it runs;
-// col_bytes: 4, 8 or 16 bytes of a spin row per task.
+// col_bytes: 4, 8 or 16 bytes of a spin row per task; rec_global: every tile's instance has
+// grec set (records in global memory), else records are staged in LDS.
 hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        int col_bytes, size_t lds_bytes, hipStream_t s);
+                        int col_bytes, bool rec_global, size_t lds_bytes, hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
 hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
-size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, uint32_t n_classes);
+size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, uint32_t n_classes, bool rec_global);
 }  // namespace xs

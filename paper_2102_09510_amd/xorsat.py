@@ -46,7 +46,8 @@ class RunConfig(ctypes.Structure):
                 ("accept_thr", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("max_sweeps", ctypes.c_uint32), ("start_sweep", ctypes.c_uint32),
                 ("chunk_sweeps", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
-                ("wg_threads", ctypes.c_uint32), ("col_bytes", ctypes.c_uint32)]
+                ("wg_threads", ctypes.c_uint32), ("col_bytes", ctypes.c_uint32),
+                ("rec_global", ctypes.c_uint32)]
 
 
 class RunBuffers(ctypes.Structure):
@@ -58,7 +59,7 @@ class RunResult(ctypes.Structure):
     _fields_ = [("tts_sweeps", ctypes.c_int64), ("winner_clone", ctypes.c_int32),
                 ("end_sweep", ctypes.c_uint32), ("sweeps_done", ctypes.c_uint32),
                 ("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
-                ("col_bytes", ctypes.c_uint32),
+                ("col_bytes", ctypes.c_uint32), ("rec_global", ctypes.c_uint32),
                 ("clone_spin_updates", ctypes.c_uint64), ("seconds", ctypes.c_double)]
 
 
@@ -69,12 +70,13 @@ class KernelStats(ctypes.Structure):
 
 class TuneTrial(ctypes.Structure):
     _fields_ = [("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
-                ("col_bytes", ctypes.c_uint32), ("updates_per_ns", ctypes.c_double)]
+                ("col_bytes", ctypes.c_uint32), ("rec_global", ctypes.c_uint32),
+                ("updates_per_ns", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
-                ("col_bytes", ctypes.c_uint32),
+                ("col_bytes", ctypes.c_uint32), ("rec_global", ctypes.c_uint32),
                 ("updates_per_ns", ctypes.c_double), ("n_trials", ctypes.c_int32),
                 ("trials", TuneTrial * XS_TUNE_MAX_TRIALS)]
 
@@ -221,6 +223,7 @@ class RunOutput:
     tile_blocks: int
     wg_threads: int
     col_bytes: int
+    rec_global: int
     clone_spin_updates: int
     seconds: float
     state: object        # torch int64 [n][n_clones/64] on the device
@@ -232,11 +235,11 @@ class RunOutput:
 def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: int = 3604,
                 max_sweeps: int = 100000, stop_on_first: bool = True, resume: bool = False,
                 start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0,
-                wg_threads: int = 0, col_bytes: int = 0) -> RunConfig:
+                wg_threads: int = 0, col_bytes: int = 0, rec_global: int = 0) -> RunConfig:
     flags = (XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0)
     return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
                      accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks,
-                     wg_threads, col_bytes)
+                     wg_threads, col_bytes, rec_global)
 
 
 def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
@@ -258,7 +261,7 @@ def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
 def _output(res: RunResult, state, first_hit, energy, solved) -> RunOutput:
     return RunOutput(int(res.tts_sweeps), int(res.winner_clone), int(res.end_sweep),
                      int(res.sweeps_done), int(res.tile_blocks), int(res.wg_threads),
-                     int(res.col_bytes), int(res.clone_spin_updates),
+                     int(res.col_bytes), int(res.rec_global), int(res.clone_spin_updates),
                      float(res.seconds), state, first_hit, energy,
                      solved if res.winner_clone >= 0 else None)
 
@@ -311,9 +314,11 @@ def autotune(inst: Instance, n_clones: int, count: int = 1) -> dict:
     res = TuneResult()
     _check(load().xs_autotune(inst.handle, n_clones, count, _stream(), ctypes.byref(res)))
     trials = [(res.trials[k].tile_blocks, res.trials[k].wg_threads, res.trials[k].col_bytes,
-               res.trials[k].updates_per_ns) for k in range(res.n_trials)]
+               res.trials[k].rec_global, res.trials[k].updates_per_ns)
+              for k in range(res.n_trials)]
     return dict(tile_blocks=res.tile_blocks, wg_threads=res.wg_threads,
-                col_bytes=res.col_bytes, updates_per_ns=res.updates_per_ns, trials=trials)
+                col_bytes=res.col_bytes, rec_global=res.rec_global,
+                updates_per_ns=res.updates_per_ns, trials=trials)
 
 
 def tune_save(path: str):

@@ -119,13 +119,16 @@ def test_tiling_is_result_neutral():
     inst = planted_instance(128, 9)
     h = xorsat.Instance(inst.tri, inst.J)
     outs = []
-    for B, T, C in ((1, 0, 0), (2, 0, 0), (4, 0, 0), (8, 0, 0), (16, 0, 0), (1, 64, 16),
-                    (2, 128, 16), (4, 1024, 16), (8, 256, 16), (16, 256, 16), (1, 256, 4),
-                    (1, 64, 8), (2, 256, 4), (4, 256, 8), (16, 128, 4), (8, 512, 8)):
+    for B, T, C, G in ((1, 0, 0, 0), (2, 0, 0, 0), (4, 0, 0, 0), (8, 0, 0, 0), (16, 0, 0, 0),
+                       (1, 64, 16, 2), (2, 128, 16, 1), (4, 1024, 16, 2), (8, 256, 16, 1),
+                       (16, 256, 16, 2), (1, 256, 4, 1), (1, 64, 8, 2), (2, 256, 4, 1),
+                       (4, 256, 8, 1), (16, 128, 4, 1), (8, 512, 8, 2)):
         cfg = xorsat.make_config(n_clones=8192, seed=99, instance_id=1, max_sweeps=300,
                                  stop_on_first=False, tile_blocks=B, chunk_sweeps=64,
-                                 wg_threads=T, col_bytes=C)
+                                 wg_threads=T, col_bytes=C, rec_global=G)
         out = xorsat.run(h, cfg)
+        if G:
+            assert out.rec_global == (G == 1)
         assert out.tile_blocks == B and out.wg_threads == (T or out.wg_threads)
         assert out.col_bytes == (C or out.col_bytes)
         outs.append(out)

@@ -88,3 +88,13 @@ def test_exact_posterior_approaches_inverse_gamma_for_short_timeouts():
             assert tv < tv_max
         else:
             assert tv > 0.05
+
+
+def test_shifted_exponential():
+    rng = np.random.default_rng(4)
+    x = 25.0 + rng.exponential(300.0, size=20000)
+    loc, scale = ts.shifted_exponential(x)
+    assert loc == pytest.approx(25.0, abs=0.5)
+    assert scale == pytest.approx(300.0, rel=0.03)
+    s = ts.summarize(x)
+    assert s["shifted_ks_pvalue"] > 0.01
