@@ -361,6 +361,8 @@ def workload_tts(args, xorsat, torch):
     out["tau_ratio_1024_over_4096"] = taus[1024] / taus[4096]
     out["shifted_scale_ratio_1024_over_4096"] = (out["clones_1024"]["shifted_scale"] /
                                                  out["clones_4096"]["shifted_scale"])
+    out["tail_tau_ratio_1024_over_4096"] = (out["clones_1024"]["tail_tau"] /
+                                            out["clones_4096"]["tail_tau"])
     return out
 
 

@@ -242,9 +242,9 @@ uint32_t default_threads(uint32_t B) { return std::min(1024u, std::max(256u, 64u
 // over the workgroup (a one-block tile has 64 tasks of 16 bytes, 128 of 8 bytes).
 uint32_t default_col_bytes(uint32_t B) { return B >= 4 ? 16u : 8u; }
 
-// Default record placement: global memory once the records would take a large share of the
-// workgroup's LDS (n >= 1024: 16 KB or more).
-uint32_t default_rec_global(uint32_t n) { return n >= 1024 ? 1u : 0u; }
+// Default record placement: global memory once the records take a sizeable share of the
+// workgroup's LDS (n >= 512: 8 KB or more); measured neutral at n = 256, faster above.
+uint32_t default_rec_global(uint32_t n) { return n >= 512 ? 1u : 0u; }
 
 // Options of one driver call beyond the public configuration.
 struct RunOpts {

@@ -71,6 +71,15 @@ def shifted_exponential(tts) -> tuple[float, float]:
     return loc, float(x.mean() - loc)
 
 
+def tail_tau(tts, t_c: float) -> tuple[float, int]:
+    """tau of the exponential tail beyond t_c: for an exponential law the excess over any t_c is
+    again exponential with the same scale (memorylessness), so mean(TTS - t_c | TTS > t_c)
+    estimates it without the early-time part. Returns (tau, runs used)."""
+    x = np.asarray(tts, dtype=float)
+    tail = x[x > t_c] - t_c
+    return (float(tail.mean()) if tail.size else math.inf), int(tail.size)
+
+
 def single_clone_scale(tau: float, n_clones: int) -> float:
     """t0 = tau N_cl (SM): the scale that stays fixed when the clone count changes."""
     return tau * n_clones
@@ -147,6 +156,12 @@ def summarize(tts, censored: int = 0, cap: float | None = None,
                        tts99_empirical=float(np.percentile(tts, 99)))
             d, pv = ks_exponential(tts, tau)
             out.update(ks_distance=d, ks_pvalue=pv)
+            t_c = float(np.percentile(tts, 50))
+            tt, used = tail_tau(tts, t_c)
+            dt_, pvt = ks_exponential(tts[tts > t_c] - t_c, tt)
+            out.update(tail_from=t_c, tail_tau=tt, tail_runs=used, tail_ks_pvalue=pvt)
+            if n_clones:
+                out["t0_tail"] = single_clone_scale(tt, n_clones)
             loc, scale = shifted_exponential(tts)
             d2, pv2 = ks_exponential(tts - loc, scale)
             out.update(shifted_loc=loc, shifted_scale=scale, shifted_ks_distance=d2,

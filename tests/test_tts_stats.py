@@ -98,3 +98,14 @@ def test_shifted_exponential():
     assert scale == pytest.approx(300.0, rel=0.03)
     s = ts.summarize(x)
     assert s["shifted_ks_pvalue"] > 0.01
+
+
+def test_tail_tau_ignores_early_times():
+    """A law that is suppressed at short times but exponential beyond: the tail estimate
+    recovers the scale, the plain mean does not."""
+    rng = np.random.default_rng(5)
+    x = rng.gamma(3.0, 40.0, size=30000)          # slow start
+    x = np.where(x > 150, 150 + rng.exponential(200.0, size=x.size), x)
+    tau, used = ts.tail_tau(x, 400.0)
+    assert tau == pytest.approx(200.0, rel=0.05) and used > 1000
+    assert abs(ts.tau_mean(x) - 200.0) > 20
