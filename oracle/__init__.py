@@ -51,9 +51,9 @@ def _load():
     lib.or_energy.restype = i32
     lib.or_colour.argtypes = [i32, P, i32, P, P]
     lib.or_colour.restype = i32
-    lib.or_run.argtypes = [i32, P, P, P, u64, u32, u32, i64, i64, u32, u32, P, P, P, P, i32]
+    lib.or_run.argtypes = [i32, P, P, P, u64, u32, u32, u32, i64, i64, u32, u32, P, P, P, P, i32]
     lib.or_run.restype = i32
-    lib.or_trace.argtypes = [i32, P, P, P, u64, u32, u32, i64, u32, u32, P, P, P, P]
+    lib.or_trace.argtypes = [i32, P, P, P, u64, u32, u32, u32, i64, u32, u32, P, P, P, P]
     lib.or_trace.restype = i32
     _lib = lib
     return lib
@@ -106,8 +106,9 @@ def colour(tri, cap: int = 32):
 
 def run(tri, J, perm, *, seed: int, instance_id: int, thr: int, n_sweeps: int,
         clone_begin: int = 0, clone_count: int, start_sweep: int = 0, init_spins=None,
-        want_final: bool = False, threads: int = 0):
-    """Run clones [clone_begin, clone_begin+clone_count) for n_sweeps sweeps.
+        want_final: bool = False, threads: int = 0, thr0: int = 0):
+    """Run clones [clone_begin, clone_begin+clone_count) for n_sweeps sweeps (thr0 > 0: k = 0
+    spins flip iff the draw is below thr0; then only the final configuration is tested).
 
     Returns dict(first_hit, energy[, final_spins]) as numpy arrays."""
     tri = _tri(tri)
@@ -121,7 +122,7 @@ def run(tri, J, perm, *, seed: int, instance_id: int, thr: int, n_sweeps: int,
     en = np.zeros(clone_count, dtype=np.int32)
     fin = np.zeros((clone_count, n), dtype=np.int8) if want_final else None
     rc = _load().or_run(n, _ptr(tri), _ptr(J), _ptr(perm), seed & (2**64 - 1), instance_id,
-                        thr, clone_begin, clone_count, start_sweep, n_sweeps, _ptr(init),
+                        thr, thr0, clone_begin, clone_count, start_sweep, n_sweeps, _ptr(init),
                         _ptr(fh), _ptr(en), _ptr(fin), threads)
     if rc != 0:
         raise ValueError("invalid instance")
@@ -132,7 +133,7 @@ def run(tri, J, perm, *, seed: int, instance_id: int, thr: int, n_sweeps: int,
 
 
 def trace(tri, J, perm, spins, *, seed: int, instance_id: int, thr: int, clone: int,
-          n_sweeps: int, start_sweep: int = 0):
+          n_sweeps: int, start_sweep: int = 0, thr0: int = 0):
     """Single-clone trajectory: (final spins, k[n_sweeps][n], flip[n_sweeps][n], energies)."""
     tri = _tri(tri)
     n = tri.shape[0]
@@ -143,7 +144,7 @@ def trace(tri, J, perm, spins, *, seed: int, instance_id: int, thr: int, clone: 
     tf = np.zeros((n_sweeps, n), dtype=np.int8)
     en = np.zeros(n_sweeps + 1, dtype=np.int32)
     rc = _load().or_trace(n, _ptr(tri), _ptr(J), _ptr(perm), seed & (2**64 - 1), instance_id,
-                          thr, clone, start_sweep, n_sweeps, _ptr(s), _ptr(tk), _ptr(tf),
+                          thr, thr0, clone, start_sweep, n_sweeps, _ptr(s), _ptr(tk), _ptr(tf),
                           _ptr(en))
     if rc != 0:
         raise ValueError("invalid instance")

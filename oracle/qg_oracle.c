@@ -18,7 +18,9 @@
  *   or_philox        Philox4x32 with 10 rounds, from its published definition (Salmon, Moraes,
  *                    Dror, Shaw, SC'11, "Parallel random numbers: as easy as 1, 2, 3").
  *   or_run           Section "The quasi-greedy algorithm": a spin in k unsatisfied triplets
- *                    flips with probability w_k, w0 = 0, w1 = thr / 2^16, w2 = w3 = 1;
+ *                    flips with probability w_k, w0 = thr0 / 2^16 (0 for the quasi-greedy rule;
+ *                    w0 = w1^3 is the Metropolis rule the same section mentions),
+ *                    w1 = thr / 2^16, w2 = w3 = 1;
  *                    Section "Basic information about the GPU implementation": one random
  *                    number shared by the 32 clones of a word; Supplementary Material: sets
  *                    processed one after the other, the exact sweep at which a clone reaches the
@@ -31,10 +33,12 @@
  *         bit b of  philox(ctr = (i, 0xFFFFFFFF, g >> 2, instance_id))[g & 3],  bit 1 <=> s = -1;
  *       sweep t, site i, group g: the 16-bit draw
  *         d = (philox(ctr = (i, t, g >> 3, instance_id))[(g & 7) >> 1] >> (16 * (g & 1))) & 0xFFFF
- *       and the spin (k = 1) flips iff d < thr;
+ *       and the spin flips iff d < thr (k = 1) or d < thr0 (k = 0);
  *   - a sweep visits the sites in `perm` order (the colour classes one after another);
  *   - first_hit[c] = smallest t in [start_sweep, start_sweep + n_sweeps] with E(C_t) = -N,
- *     where C_t is the configuration before sweep t, or -1.
+ *     where C_t is the configuration before sweep t, or -1. With thr0 > 0 a ground state can be
+ *     left again, and only the final configuration is tested: first_hit = the end sweep if it
+ *     has E = -N, else -1.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -182,7 +186,7 @@ static int unsatisfied_count(const int32_t *tri, const int8_t *J, const int32_t 
  * (n entries each, in visiting order) receive k and whether the site flipped. */
 static void sweep_one(int32_t n, const int32_t *tri, const int8_t *J, const int32_t *inc,
                       const int32_t *perm, uint64_t seed, uint32_t instance_id, uint32_t thr,
-                      uint32_t t, int64_t clone, int8_t *s, int8_t *trace_k,
+                      uint32_t thr0, uint32_t t, int64_t clone, int8_t *s, int8_t *trace_k,
                       int8_t *trace_flip) {
     for (int32_t pos = 0; pos < n; ++pos) {
         int32_t i = perm[pos];
@@ -193,7 +197,7 @@ static void sweep_one(int32_t n, const int32_t *tri, const int8_t *J, const int3
         else if (k == 1)
             flip = or_draw16(seed, instance_id, i, t, clone) < thr; /* w1 = thr / 2^16 */
         else
-            flip = 0; /* w0 = 0 */
+            flip = thr0 > 0 && or_draw16(seed, instance_id, i, t, clone) < thr0; /* w0 */
         if (flip) s[i] = (int8_t)-s[i];
         if (trace_k) trace_k[pos] = (int8_t)k;
         if (trace_flip) trace_flip[pos] = (int8_t)flip;
@@ -212,7 +216,8 @@ static void sweep_one(int32_t n, const int32_t *tri, const int8_t *J, const int3
  * Returns 0, or -1 on invalid input.
  */
 int32_t or_run(int32_t n, const int32_t *tri, const int8_t *J, const int32_t *perm,
-               uint64_t seed, uint32_t instance_id, uint32_t thr, int64_t clone_begin,
+               uint64_t seed, uint32_t instance_id, uint32_t thr, uint32_t thr0,
+               int64_t clone_begin,
                int64_t clone_count, uint32_t start_sweep, uint32_t n_sweeps,
                const int8_t *init_spins, int32_t *first_hit, int32_t *energy,
                int8_t *final_spins, int32_t n_threads) {
@@ -234,12 +239,13 @@ int32_t or_run(int32_t n, const int32_t *tri, const int8_t *J, const int32_t *pe
                 memcpy(s, init_spins + q * n, (size_t)n);
             else
                 for (int32_t i = 0; i < n; ++i) s[i] = or_initial_spin(seed, instance_id, i, c);
-            int32_t hit = or_energy(n, tri, J, s) == -n ? (int32_t)start_sweep : -1;
+            int32_t hit = thr0 == 0 && or_energy(n, tri, J, s) == -n ? (int32_t)start_sweep : -1;
             for (uint32_t k = 0; k < n_sweeps; ++k) {
                 uint32_t t = start_sweep + k;
-                sweep_one(n, tri, J, inc, perm, seed, instance_id, thr, t, c, s, NULL, NULL);
-                if (hit < 0 && or_energy(n, tri, J, s) == -n) hit = (int32_t)(t + 1);
+                sweep_one(n, tri, J, inc, perm, seed, instance_id, thr, thr0, t, c, s, NULL, NULL);
+                if (thr0 == 0 && hit < 0 && or_energy(n, tri, J, s) == -n) hit = (int32_t)(t + 1);
             }
+            if (thr0 > 0 && or_energy(n, tri, J, s) == -n) hit = (int32_t)(start_sweep + n_sweeps);
             first_hit[q] = hit;
             if (energy) energy[q] = or_energy(n, tri, J, s);
             if (final_spins) memcpy(final_spins + q * n, s, (size_t)n);
@@ -256,14 +262,14 @@ int32_t or_run(int32_t n, const int32_t *tri, const int8_t *J, const int32_t *pe
  * before every sweep plus after the last one (energies: [n_sweeps + 1]).
  */
 int32_t or_trace(int32_t n, const int32_t *tri, const int8_t *J, const int32_t *perm,
-                 uint64_t seed, uint32_t instance_id, uint32_t thr, int64_t clone,
+                 uint64_t seed, uint32_t instance_id, uint32_t thr, uint32_t thr0, int64_t clone,
                  uint32_t start_sweep, uint32_t n_sweeps, int8_t *spins /* in/out [n] */,
                  int8_t *trace_k, int8_t *trace_flip, int32_t *energies) {
     int32_t *inc = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)n);
     if (build_incidence(n, tri, inc) != 0) { free(inc); return -1; }
     energies[0] = or_energy(n, tri, J, spins);
     for (uint32_t k = 0; k < n_sweeps; ++k) {
-        sweep_one(n, tri, J, inc, perm, seed, instance_id, thr, start_sweep + k, clone, spins,
+        sweep_one(n, tri, J, inc, perm, seed, instance_id, thr, thr0, start_sweep + k, clone, spins,
                   trace_k + (size_t)k * n, trace_flip + (size_t)k * n);
         energies[k + 1] = or_energy(n, tri, J, spins);
     }

@@ -2,6 +2,7 @@
 vectors and hand-worked examples. None of these tests uses a GPU or the HIP library."""
 from __future__ import annotations
 
+import math
 import os
 import shutil
 import subprocess
@@ -363,3 +364,64 @@ def test_resume_equals_uninterrupted():
     b = oracle.run(inst.tri, inst.J, perm, n_sweeps=40, start_sweep=30,
                    init_spins=a["final_spins"], **kw)
     assert np.array_equal(full["final_spins"], b["final_spins"])
+
+
+# ------------------------------------------------------------------------- Metropolis variant
+
+def test_metropolis_rule_per_update():
+    """With a second threshold thr0, a spin with k = 0 flips iff the same 16-bit draw is below
+    thr0; the other rules are unchanged (Section "The quasi-greedy algorithm": w0 = w1^3 gives
+    the Metropolis rule)."""
+    inst = planted_instance(64, 199)
+    perm, _ = oracle.colour(inst.tri, 32)
+    clone, seed, iid, T = 77, 4321, 5, 30
+    thr, thr0 = 8869, 4000
+    s0 = np.array([oracle.initial_spin(seed, iid, i, clone) for i in range(64)])
+    _, k, flip, en = oracle.trace(inst.tri, inst.J, perm, s0, seed=seed, instance_id=iid,
+                                  thr=thr, thr0=thr0, clone=clone, n_sweeps=T)
+    seen0 = 0
+    for t in range(T):
+        assert np.all(flip[t][k[t] >= 2] == 1)
+        for pos in np.flatnonzero(k[t] <= 1):
+            d = oracle.draw16(seed, iid, int(perm[pos]), t, clone)
+            want = d < (thr if k[t][pos] == 1 else thr0)
+            assert flip[t][pos] == int(want)
+            seen0 += int(k[t][pos] == 0 and want)
+        dE = int(((6 - 4 * k[t].astype(int)) * flip[t]).sum())
+        assert en[t + 1] - en[t] == dE
+    assert seen0 > 0
+
+
+@pytest.mark.parametrize("T", [1.0, 0.8])
+def test_metropolis_paramagnetic_energy(T):
+    """w1 = exp(-2/T), w0 = w1^3 satisfies detailed balance for flips costing 6 - 4k; above the
+    dynamical temperature the chain equilibrates in the paramagnet, whose energy per spin on a
+    locally tree-like 3-regular hypergraph is -tanh(1/T) (cavity equations with u = h = 0,
+    Section "Analytic prediction"). Thresholds are 16-bit roundings of w1 and w0."""
+    beta = 1.0 / T
+    thr = round(math.exp(-2 * beta) * 65536)
+    thr0 = round(math.exp(-6 * beta) * 65536)
+    inst = planted_instance(2048, 91)
+    perm, _ = oracle.colour(inst.tri, 32)
+    r = oracle.run(inst.tri, inst.J, perm, seed=17, instance_id=0, thr=thr, thr0=thr0,
+                   n_sweeps=300, clone_count=256)
+    e = r["energy"].mean() / 2048
+    assert abs(e + math.tanh(beta)) < 0.006
+    # the quasi-greedy rule at the same w1 never pays for a k = 0 flip and sits lower
+    q = oracle.run(inst.tri, inst.J, perm, seed=17, instance_id=0, thr=thr, n_sweeps=300,
+                   clone_count=64)
+    assert q["energy"].mean() / 2048 < e - 0.003
+
+
+def test_metropolis_first_hit_only_at_end():
+    """With w0 > 0 only the final configuration is tested for E = -N."""
+    inst = planted_instance(64, 5)
+    perm, _ = oracle.colour(inst.tri, 32)
+    init = np.tile(inst.tau, (4, 1))
+    r = oracle.run(inst.tri, inst.J, perm, seed=1, instance_id=0, thr=3604, thr0=1,
+                   n_sweeps=0, clone_count=4, start_sweep=9, init_spins=init)
+    assert r["first_hit"].tolist() == [9] * 4
+    r = oracle.run(inst.tri, inst.J, perm, seed=1, instance_id=0, thr=3604, thr0=30000,
+                   n_sweeps=3, clone_count=4, init_spins=init)
+    assert np.all((r["first_hit"] == 3) == (r["energy"] == -64))
+    assert np.all(r["first_hit"][r["energy"] > -64] == -1)
