@@ -33,6 +33,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 2 wide products and 2 three-input XORs) plus 8 threshold compares serve 8 groups = 256
 # clones. 9/32 + 48/256 = 0.469 lane-ops per update.
 ALGO_OPS_PER_UPDATE = 9 / 32 + (10 * (2 + 2) + 8) / 256
+# With w0 > 0 the rule also takes 9 operations per word (no ground-state test, one more
+# select) and every draw is compared with both thresholds.
+ALGO_OPS_PER_UPDATE_W0 = 9 / 32 + (10 * (2 + 2) + 16) / 256
 # Algorithmic LDS traffic per update: the 7 state bits an update reads (own spin and the two
 # partners in each of its three triplets) and the 1 bit it writes = 1 byte.
 ALGO_LDS_BYTES_PER_UPDATE = 1.0
@@ -57,12 +60,17 @@ def parse():
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     ap.add_argument("--workload", default="batched",
-                    choices=["batched", "steady", "uneven", "serve", "tts"],
+                    choices=["batched", "steady", "uneven", "serve", "tts", "w1scan"],
                     help="batched: the default line; steady: 16 x N=1024 x 2^20 clones, fixed "
                          "sweeps; uneven: 512 instances of uneven N and clone count, batched vs "
                          "served vs one at a time; serve: Poisson stream through the server vs "
                          "one run at a time; tts: the exponential TTS law on many runs of one "
-                         "small instance, tau x N_cl scaling and the short-timeout estimate")
+                         "small instance, tau x N_cl scaling and the short-timeout estimate; "
+                         "w1scan: mean TTS against w1 on one small instance, and the same w1 "
+                         "with w0 = w1^3")
+    ap.add_argument("--accept-thr0", type=int, default=0,
+                    help="batched: w0 threshold (w0 = thr0 / 65536); > 0 runs the w0 rule for "
+                         "the full budget (a ground state is not absorbing, so no early stop)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
@@ -98,14 +106,14 @@ def cpu_baseline(insts, args, target_s):
     # calibrate on one instance
     t0 = time.perf_counter()
     oracle.run(insts[0].tri, insts[0].J, perms[0], seed=1, instance_id=0, thr=3604,
-               n_sweeps=200, clone_count=256, threads=threads)
+               thr0=args.accept_thr0, n_sweeps=200, clone_count=256, threads=threads)
     per_sweep = max((time.perf_counter() - t0) / 200, 1e-6)
     sweeps = int(max(10, min(5000, target_s / (per_sweep * len(insts)))))
     t0 = time.perf_counter()
     updates = 0
     for k, inst in enumerate(insts):
         oracle.run(inst.tri, inst.J, perms[k], seed=k, instance_id=k, thr=3604,
-                   n_sweeps=sweeps, clone_count=256, threads=threads)
+                   thr0=args.accept_thr0, n_sweeps=sweeps, clone_count=256, threads=threads)
         updates += 256 * inst.n * sweeps
     dt = time.perf_counter() - t0
     return {"value": updates / dt / 1e9, "unit": "clone-spin updates/ns", "cores": threads,
@@ -366,6 +374,64 @@ def workload_tts(args, xorsat, torch):
     return out
 
 
+def workload_w1scan(args, xorsat, torch):
+    """Mean TTS against w1 (Section "Numerical results": w1 was chosen at the minimum of a
+    quadratic fit of the mean TTS) on one planted instance, many runs per value; then the same
+    pseudo-temperatures with w0 = w1^3 (detailed balance), scored by the share of runs whose end
+    configuration holds a ground state after as many sweeps as the quasi-greedy median TTS."""
+    from paper_2102_09510_amd import tts_stats as ts
+    from paper_2102_09510_amd.instances import gen_seed, planted_instance
+
+    n, runs, ncl, cap = 100, 512, 1024, 200000
+    w1s = [0.03, 0.04, 0.045, 0.05, 0.055, 0.06, 0.065, 0.07, 0.08]
+    inst = planted_instance(n, gen_seed(7, 0))
+    h = xorsat.Instance(inst.tri, inst.J)
+    rows, times_of = [], {}
+    for w1 in w1s:
+        thr = round(w1 * 65536)
+        cfgs = [xorsat.make_config(n_clones=ncl, seed=0xBEEF + 104729 * r, instance_id=r,
+                                   accept_thr=thr, max_sweeps=cap, stop_on_first=True,
+                                   chunk_sweeps=20) for r in range(runs)]
+        t0 = time.perf_counter()
+        res = xorsat.run_batch([h] * runs, cfgs, want_energy=False)
+        dt = time.perf_counter() - t0
+        tts = np.array([r.tts_sweeps for r in res])
+        solved = tts >= 0
+        times = np.where(solved, tts, cap)
+        times_of[w1] = times
+        tau = ts.tau_censored_mle(times, solved)
+        rows.append({"w1": w1, "accept_thr": thr, "mean_tts": float(times.mean()),
+                     "tau": tau, "p50": float(np.percentile(times, 50)),
+                     "censored": int((~solved).sum()), "seconds": round(dt, 2)})
+        print(f"# w1 {w1}: mean TTS {times.mean():.0f} sweeps, {dt:.1f} s", file=sys.stderr,
+              flush=True)
+    w = np.array([r["w1"] for r in rows])
+    m = np.array([r["mean_tts"] for r in rows])
+    k = int(np.argmin(m))
+    lo, hi = max(0, k - 2), min(len(w), k + 3)
+    c2, c1, _ = np.polyfit(w[lo:hi], m[lo:hi], 2)
+    w_opt = float(-c1 / (2 * c2)) if c2 > 0 else None
+    # w0 = w1^3 at the same pseudo-temperatures, fixed budget
+    budget = int(next(r["p50"] for r in rows if r["w1"] == 0.055))
+    met = []
+    for w1 in w1s:
+        thr, thr0 = round(w1 * 65536), max(1, round(w1 ** 3 * 65536))
+        cfgs = [xorsat.make_config(n_clones=ncl, seed=0xBEEF + 104729 * r, instance_id=r,
+                                   accept_thr=thr, accept_thr0=thr0, max_sweeps=budget,
+                                   stop_on_first=False, chunk_sweeps=100) for r in range(runs)]
+        res = xorsat.run_batch([h] * runs, cfgs, want_energy=False)
+        ok = sum(1 for r in res if r.tts_sweeps >= 0)
+        met.append({"w1": w1, "accept_thr0": thr0, "runs_in_ground_state_at_end": ok,
+                    "quasi_greedy_runs_solved_by_then": int((times_of[w1] <= budget).sum())})
+        print(f"# w1 {w1}, w0 = w1^3: {ok}/{runs} runs end in a ground state", file=sys.stderr,
+              flush=True)
+    return {"metric": "mean TTS (sweeps) against w1",
+            "config": {"workload": f"1 planted instance, N={n}, {ncl} clones, {runs} runs per "
+                                   f"w1, to first ground state (cap {cap} sweeps)"},
+            "quasi_greedy": rows, "quadratic_fit_w1_min": w_opt,
+            "w0_eq_w1_cubed": {"budget_sweeps": budget, "runs": runs, "rows": met}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -391,7 +457,8 @@ def main():
         return
     if args.workload != "batched":
         fn = {"steady": workload_steady, "uneven": workload_uneven,
-              "serve": workload_serve, "tts": workload_tts}[args.workload]
+              "serve": workload_serve, "tts": workload_tts,
+              "w1scan": workload_w1scan}[args.workload]
         print(json.dumps(fn(args, xorsat, torch)), flush=True)
         return
     insts = [planted_instance(args.n, gen_seed(2, k)) for k in range(args.instances)]
@@ -400,7 +467,8 @@ def main():
     def step(s):
         cfgs = [xorsat.make_config(n_clones=args.clones, seed=run_seed(2, k) + s,
                                    instance_id=k, accept_thr=THR_PAPER,
-                                   max_sweeps=args.budget, stop_on_first=True,
+                                   accept_thr0=args.accept_thr0, max_sweeps=args.budget,
+                                   stop_on_first=args.accept_thr0 == 0,
                                    chunk_sweeps=args.chunk)
                 for k in range(args.instances)]
         return xorsat.run_batch(handles, cfgs, want_energy=True)
@@ -436,7 +504,8 @@ def main():
     kern_rate = prof["clone_spin_updates"] / (prof["total_ms"] * 1e6) if prof["total_ms"] else 0
     per_launch_updates = prof["clone_spin_updates"] / max(prof["launches"], 1)
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
-    achieved = ALGO_OPS_PER_UPDATE * per_launch_updates / (avg_ms * 1e-3) / 1e12
+    ops = ALGO_OPS_PER_UPDATE_W0 if args.accept_thr0 else ALGO_OPS_PER_UPDATE
+    achieved = ops * per_launch_updates / (avg_ms * 1e-3) / 1e12
     lds_tbs = ALGO_LDS_BYTES_PER_UPDATE * per_launch_updates / (avg_ms * 1e-3) / 1e12
     line = {
         "metric": "clone-spin updates/ns on 1 MI355X",
@@ -452,9 +521,12 @@ def main():
         "dtype": "u32",
         "data": "synthetic planted instances (seeded configuration model)",
         "config": {"workload": f"{args.instances} planted instances, N={args.n}, "
-                               f"{args.clones} clones each, batched, to first ground state or "
-                               f"{args.budget} sweeps per step",
-                   "chunk_sweeps": args.chunk, "accept_thr": THR_PAPER},
+                               f"{args.clones} clones each, batched, " +
+                               (f"{args.budget} sweeps per step with w0 = "
+                                f"{args.accept_thr0}/65536" if args.accept_thr0 else
+                                f"to first ground state or {args.budget} sweeps per step"),
+                   "chunk_sweeps": args.chunk, "accept_thr": THR_PAPER,
+                   **({"accept_thr0": args.accept_thr0} if args.accept_thr0 else {})},
         "tts_sweeps": {"solved": len(tts), "censored": censored,
                        "p50": float(np.percentile(tts, 50)) if tts else None,
                        "p99": float(np.percentile(tts, 99)) if tts else None},

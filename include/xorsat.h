@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define XS_ABI_VERSION 1
+#define XS_ABI_VERSION 2
 
 typedef int32_t xs_status;
 #define XS_OK 0
@@ -90,8 +90,10 @@ xs_status xs_instance_get_partition(const xs_instance *inst, int32_t *perm, int3
 /*
  * Run configuration. The dynamics (Section "The quasi-greedy algorithm"): a sweep visits the
  * spins set by set in partition order; a spin in k unsatisfied triplets flips with
- * probability w_k, w0 = 0, w2 = w3 = 1, and w1 = accept_thr / 65536 (the paper uses
- * w1 = 0.055, accept_thr = 3604). The k = 1 test compares a 16-bit draw d with accept_thr.
+ * probability w_k, w2 = w3 = 1, w1 = accept_thr / 65536 (the paper uses w1 = 0.055,
+ * accept_thr = 3604) and w0 = accept_thr0 / 65536 (0 for the quasi-greedy rule; w0 = w1^3 is
+ * the Metropolis rule of the pseudo-temperature T = -2 / ln w1 that the same section relates it
+ * to). A k = 1 spin flips iff its 16-bit draw d < accept_thr, a k = 0 spin iff d < accept_thr0.
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed low, seed high):
  *   start bit of spin i, clone c: bit (c & 31) of philox(i, 0xFFFFFFFF, g >> 2, id)[g & 3];
  *   draw of spin i, sweep t, group g = c >> 5:
@@ -102,7 +104,7 @@ typedef struct {
     uint32_t instance_id;  /* part of every random counter; keeps instances independent */
     uint64_t seed;         /* Philox key */
     uint32_t n_clones;     /* > 0, multiple of XS_CLONE_QUANTUM */
-    uint32_t accept_thr;   /* 0 .. 65536 */
+    uint32_t accept_thr;   /* w1 threshold, 0 .. 65536 */
     uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME */
     uint32_t max_sweeps;   /* sweep budget of this call (0 = only check the start state) */
     uint32_t start_sweep;  /* absolute index of the first sweep (for resumed runs) */
@@ -117,6 +119,11 @@ typedef struct {
     uint32_t rec_global;   /* where a workgroup reads the per-spin neighbour records: 1 = global
                               memory (through the caches; frees LDS for clone state), 2 = LDS,
                               0 = chosen by the library. Speed only. */
+    uint32_t accept_thr0;  /* w0 threshold, 0 .. 65536 (0: quasi-greedy). With accept_thr0 > 0 a
+                              ground state is not absorbing: no sweep is tested, first_hit is
+                              end_sweep for a clone whose end configuration has E = -N and -1
+                              otherwise, and XS_STOP_ON_FIRST is rejected (XS_EINVAL). */
+    uint32_t reserved;     /* must be 0 */
 } xs_run_config;
 
 /*

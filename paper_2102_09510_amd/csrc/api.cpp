@@ -200,6 +200,12 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
         return fail(XS_EINVAL, "n_clones %u is not a positive multiple of %d", cfg->n_clones,
                     XS_CLONE_QUANTUM);
     if (cfg->accept_thr > 65536) return fail(XS_EINVAL, "accept_thr %u > 65536", cfg->accept_thr);
+    if (cfg->accept_thr0 > 65536)
+        return fail(XS_EINVAL, "accept_thr0 %u > 65536", cfg->accept_thr0);
+    if (cfg->reserved) return fail(XS_EINVAL, "xs_run_config.reserved must be 0");
+    if (cfg->accept_thr0 && (cfg->flags & XS_STOP_ON_FIRST))
+        return fail(XS_EINVAL, "XS_STOP_ON_FIRST needs accept_thr0 = 0 (with w0 > 0 a ground "
+                               "state is not absorbing and no sweep is tested)");
     if (cfg->flags & ~(XS_STOP_ON_FIRST | XS_RESUME))
         return fail(XS_EINVAL, "unknown flags 0x%x", cfg->flags);
     if ((uint64_t)cfg->start_sweep + cfg->max_sweeps >= 0xFFFFFFFFull)
@@ -311,6 +317,7 @@ void fill_desc(const xs_instance *I, const xs_run_config &c, const DeviceTables 
     d.n_classes = (uint32_t)I->class_off.size() - 1;
     d.inst_id = c.instance_id;
     d.thr = c.accept_thr;
+    d.thr0 = c.accept_thr0;
     d.seed_lo = (uint32_t)c.seed;
     d.seed_hi = (uint32_t)(c.seed >> 32);
     d.flags = c.flags;
@@ -363,10 +370,11 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
             }
         if (!changed) break;
     }
-    // Tiles grouped by (workgroup size, column width, record placement): one launch per group
-    // and chunk.
-    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<uint2>> by_launch;
-    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, size_t> lds_of;
+    // Tiles grouped by (workgroup size, column width, record placement, rule): one launch per
+    // group and chunk.
+    using LaunchKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
+    std::map<LaunchKey, std::vector<uint2>> by_launch;
+    std::map<LaunchKey, size_t> lds_of;
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
         d.log2_tile_blocks = ilog2(d.tile_blocks);
@@ -384,18 +392,19 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
                                                   : (default_rec_global(d.n) ? 1u : 2u);
         d.rec_global = GRc == 1 ? 1u : 0u;
         const uint32_t nb = cfgs[k].n_clones / 256;
-        const auto key = std::make_tuple(T, C, d.rec_global);
+        const uint32_t met = d.thr0 ? 1u : 0u;
+        const auto key = std::make_tuple(T, C, d.rec_global, met);
         auto &v = by_launch[key];
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) v.push_back(make_uint2((uint32_t)k, b0));
         lds_of[key] = std::max(lds_of[key], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes,
-                                                                d.rec_global != 0));
+                                                                d.rec_global != 0, met != 0));
     }
     tiles.clear();
     groups.clear();
     for (auto &kv : by_launch) {
         groups.push_back(TileGroup{std::get<0>(kv.first), std::get<1>(kv.first),
-                                   std::get<2>(kv.first), tiles.size(), kv.second.size(),
-                                   lds_of[kv.first]});
+                                   std::get<2>(kv.first), std::get<3>(kv.first), tiles.size(),
+                                   kv.second.size(), lds_of[kv.first]});
         tiles.insert(tiles.end(), kv.second.begin(), kv.second.end());
     }
     for (const TileGroup &g : groups)
@@ -485,6 +494,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             for (const TileGroup &gr : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + gr.first, (int)gr.count,
                                         (int)gr.threads, (int)gr.col_bytes, gr.rec_global != 0,
+                                        gr.met != 0,
                                         gr.lds, s));
             if (with_events) XS_HIP(hipEventRecord(ev[2 * g + 1], s));
             XS_HIP(xs::launch_decide(d_inst, count, d_active, s));
@@ -712,7 +722,7 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
     }
     std::memset(out, 0, sizeof *out);
     for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
-        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls, true) > 160 * 1024) continue;
+        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls, true, false) > 160 * 1024) continue;
         for (uint32_t T = 128; T <= 1024; T *= 2) {
             if (T < 8 * B || (T == 128 && B > 2)) continue;
             for (uint32_t C = 4; C <= 16; C *= 2)
@@ -720,7 +730,7 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
                     // skip columns that leave most threads without a task in a full class
                     if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
                         continue;
-                    if (xs::chunk_lds_bytes(n, B, ncls, G == 1) > 160 * 1024) continue;
+                    if (xs::chunk_lds_bytes(n, B, ncls, G == 1, false) > 160 * 1024) continue;
                     for (auto &c : cfgs) {
                         c.tile_blocks = B;
                         c.wg_threads = T;

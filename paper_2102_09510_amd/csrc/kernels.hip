@@ -45,6 +45,8 @@ constexpr uint32_t kMaj3 = ((kA & kB) | (kA & kC) | (kB & kC)) & 0xFF;
 constexpr uint32_t kOr3 = (kA | kB | kC) & 0xFF;
 constexpr uint32_t kXorAndNot = ((kA ^ kB) & ~kC) & 0xFF;  // (a ^ b) & ~c
 constexpr uint32_t kXorAnd = (kA ^ (kB & kC)) & 0xFF;      // a ^ (b & c)
+constexpr uint32_t kXorAndN = (kA ^ (kB & ~kC)) & 0xFF;    // a ^ (b & ~c)
+constexpr uint32_t kMux = ((kA & kB) | (~kA & kC)) & 0xFF; // a ? b : c, bitwise
 
 template <uint32_t LUT>
 __device__ __forceinline__ uint32_t lop3(uint32_t a, uint32_t b, uint32_t c) {
@@ -85,6 +87,24 @@ __device__ __forceinline__ uint32_t qg_word(uint32_t x, uint32_t a1, uint32_t b1
     const uint32_t k1 = lop3<kXorAndNot>(x, par, dmaj);  // k == 1
     if (kAcc) acc = lop3<kOr3>(acc, k1, dmaj);       // k >= 1
     return lop3<kXorAnd>(m, k1, accept);
+}
+
+// The same word with w0 > 0 (Section "The quasi-greedy algorithm": w0 = w1^3 gives the
+// detailed-balance Metropolis rule at the pseudo-temperature of w1): a k = 0 spin flips when the
+// group's w0 bit is set. When k <= 1 (dmaj = 0), k = 1 iff x differs from p1 ^ p2 ^ p3, which
+// selects acc1 over acc0; nine three-input operations.
+__device__ __forceinline__ uint32_t met_word(uint32_t x, uint32_t a1, uint32_t b1, uint32_t a2,
+                                             uint32_t b2, uint32_t a3, uint32_t b3, uint32_t j1,
+                                             uint32_t j2, uint32_t j3, uint32_t acc1,
+                                             uint32_t acc0) {
+    const uint32_t p1 = lop3<kXor3>(a1, b1, j1);
+    const uint32_t p2 = lop3<kXor3>(a2, b2, j2);
+    const uint32_t p3 = lop3<kXor3>(a3, b3, j3);
+    const uint32_t m = lop3<kMaj3>(p1, p2, p3);
+    const uint32_t par = lop3<kXor3>(p1, p2, p3);
+    const uint32_t e = x ^ par;      // k odd
+    const uint32_t dmaj = x ^ m;     // k >= 2
+    return lop3<kXorAndN>(m, lop3<kMux>(e, acc1, acc0), dmaj);
 }
 
 
@@ -138,7 +158,7 @@ struct Tile {
     uint32_t flag;       // workgroup flag (uint32)
     uint32_t colbase;    // st + this thread's column
     uint32_t rb_sel, rb_shift;
-    uint32_t thr, key0, key1, iid, ncls;
+    uint32_t thr, thr0, key0, key1, iid, ncls;
     uint32_t cls;        // per class: first position | size << 16 (uint32 each)
 };
 
@@ -174,25 +194,33 @@ __device__ __forceinline__ void col_store(uint32_t addr, const uint32_t (&w)[CW 
     *reinterpret_cast<typename ColVec<CW>::T *>(xs_lds + addr) = v;
 }
 
+// Bit g of the result: draw g of the eight 16-bit draws in o is below thr.
+__device__ __forceinline__ uint32_t draws_below(uint4 o, uint32_t thr) {
+    return below(o.x & 0xFFFFu, thr) | below(o.x >> 16, thr) << 1 |
+           below(o.y & 0xFFFFu, thr) << 2 | below(o.y >> 16, thr) << 3 |
+           below(o.z & 0xFFFFu, thr) << 4 | below(o.z >> 16, thr) << 5 |
+           below(o.w & 0xFFFFu, thr) << 6 | below(o.w >> 16, thr) << 7;
+}
+
 // Acceptance bits of sweep t: one Philox call per (position, block) gives the eight 16-bit draws
-// of the block's eight groups.
-template <int NT, bool GR>
+// of the block's eight groups. MET: a 16-bit entry, the w1 byte and above it the w0 byte of the
+// same draws.
+template <int NT, bool GR, bool MET>
 __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t rb) {
     for (uint32_t q = T.tid; q < T.n * T.B; q += NT) {
         const uint32_t p = q >> T.lB, b = q & (T.B - 1);
         const uint32_t i = (rec_at<GR>(T, p).w >> 16) & 0x1FFFu;
         const uint4 o = philox10(make_uint4(i, t, T.blk0 + b, T.iid), T.key0, T.key1);
-        const uint32_t thr = T.thr;
-        const uint32_t bits = below(o.x & 0xFFFFu, thr) | below(o.x >> 16, thr) << 1 |
-                              below(o.y & 0xFFFFu, thr) << 2 | below(o.y >> 16, thr) << 3 |
-                              below(o.z & 0xFFFFu, thr) << 4 | below(o.z >> 16, thr) << 5 |
-                              below(o.w & 0xFFFFu, thr) << 6 | below(o.w >> 16, thr) << 7;
-        xs_lds[rb + q] = (uint8_t)bits;
+        if constexpr (MET)
+            *reinterpret_cast<uint16_t *>(xs_lds + rb + 2 * q) =
+                (uint16_t)(draws_below(o, T.thr) | draws_below(o, T.thr0) << 8);
+        else
+            xs_lds[rb + q] = (uint8_t)draws_below(o, T.thr);
     }
 }
 
 // One task: the spin whose record is r (position p), this thread's column.
-template <int CW, bool kAcc>
+template <int CW, bool kAcc, bool MET>
 __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, uint32_t rb,
                                             uint32_t (&acc)[CW / 4]) {
     constexpr int G = CW / 4;
@@ -209,18 +237,29 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, 
     const uint32_t j1 = 0u - ((meta >> 13) & 1u);
     const uint32_t j2 = 0u - ((meta >> 14) & 1u);
     const uint32_t j3 = 0u - (meta >> 15);
-    const uint32_t bits = (uint32_t)xs_lds[rb + (p << T.lB) + T.rb_sel] >> T.rb_shift;
+    // rb_shift is a multiple of G, so the column's G bits stay inside their byte
+    if constexpr (MET) {
+        const uint32_t v = *reinterpret_cast<const uint16_t *>(
+            xs_lds + rb + 2 * ((p << T.lB) + T.rb_sel));
+        const uint32_t bits = v >> T.rb_shift, bits0 = v >> (8 + T.rb_shift);
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-        y[g] = qg_word<kAcc>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
-                             0u - ((bits >> g) & 1u), acc[g]);
+        for (int g = 0; g < G; ++g)
+            y[g] = met_word(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
+                            0u - ((bits >> g) & 1u), 0u - ((bits0 >> g) & 1u));
+    } else {
+        const uint32_t bits = (uint32_t)xs_lds[rb + (p << T.lB) + T.rb_sel] >> T.rb_shift;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            y[g] = qg_word<kAcc>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
+                                 0u - ((bits >> g) & 1u), acc[g]);
+    }
     col_store<CW>(self, y);
 }
 
 // The classes of one sweep, a barrier before each (the first one also publishes the sweep's
 // acceptance bits and the previous sweep's last writes). Records and class descriptors are
 // read-only, so each thread fetches its first record of a class before that class's barrier.
-template <int NT, int CW, bool GR, bool kAcc>
+template <int NT, int CW, bool GR, bool kAcc, bool MET = false>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
     uint32_t cd = lds_u32(T.cls);
     for (uint32_t c = 0; c < T.ncls; ++c) {
@@ -231,10 +270,10 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
         if (T.tid < ntask) r0 = rec_at<GR>(T, p0);
         if (c + 1 < T.ncls) cd = lds_u32(T.cls + 4 * (c + 1));
         __syncthreads();
-        if (T.tid < ntask) update_task<CW, kAcc>(T, r0, p0, rb, acc);
+        if (T.tid < ntask) update_task<CW, kAcc, MET>(T, r0, p0, rb, acc);
         for (uint32_t q = T.tid + NT; q < ntask; q += NT) {
             const uint32_t p = cs + (q >> T.lcol);
-            update_task<CW, kAcc>(T, rec_at<GR>(T, p), p, rb, acc);
+            update_task<CW, kAcc, MET>(T, rec_at<GR>(T, p), p, rb, acc);
         }
     }
 }
@@ -321,6 +360,17 @@ __device__ __forceinline__ void load_state(const Tile &T) {
     }
 }
 
+// Write the tile's rows back LDS -> global (caller synchronises first).
+template <int NT>
+__device__ __forceinline__ void store_state(const Tile &T) {
+    uint4 *dst0 = reinterpret_cast<uint4 *>(T.I->state + 4 * (size_t)T.blk0);
+    for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
+        const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
+        (dst0 + ((size_t)i * T.W >> 1))[k] =
+            *reinterpret_cast<const uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k);
+    }
+}
+
 // K sweeps (or fewer at the budget end) of one workgroup tile. The grid holds every tile of
 // every instance of the batch; tiles of finished instances return at once.
 //
@@ -330,7 +380,10 @@ __device__ __forceinline__ void load_state(const Tile &T) {
 // unchanged in global memory: the tile is written back at the end) with a per-sweep test, which
 // gives the exact first sweep; the replay draws the same random numbers, so it reproduces the
 // same trajectory.
-template <int NT, int CW, bool GR>
+//
+// MET (w0 > 0): a ground state can be left again, so no sweep is tested; the final pass tests
+// the end configuration only.
+template <int NT, int CW, bool GR, bool MET>
 __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts,
                                                const uint2 *__restrict__ tiles) {
     constexpr int G = CW / 4;        // groups per column
@@ -359,7 +412,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     T.col = T.tid & (T.ncol - 1);  // fixed per thread: NT is a multiple of ncol
     T.grec = I->grec;
     T.st = GR ? 0u : (uint32_t)lds_rec_bytes(T.n);
-    const uint32_t rbb = (uint32_t)align16((size_t)T.n * T.B);
+    const uint32_t rbb = (uint32_t)align16((size_t)T.n * T.B * (MET ? 2 : 1));
     T.rb0 = T.st + T.n * T.rowb;
     T.rb1 = T.rb0 + rbb;
     T.acc = T.rb1 + rbb;
@@ -369,6 +422,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     T.rb_sel = (T.col << LG) >> 3;
     T.rb_shift = (T.col << LG) & 7;
     T.thr = I->thr;
+    T.thr0 = I->thr0;
     T.key0 = I->seed_lo;
     T.key1 = I->seed_hi;
     T.iid = I->inst_id;
@@ -391,6 +445,18 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
         lds_rec(p) = o;
     }
     load_state<NT>(T);
+    if constexpr (MET) {
+        uint32_t none[G] = {};
+        __syncthreads();  // records, class table and state visible to every thread
+        accept_bits<NT, GR, true>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+        for (uint32_t t = t0; t < t1; ++t) {
+            sweep<NT, CW, GR, false, true>(T, (t & 1) ? T.rb1 : T.rb0, none);
+            if (t + 1 < t1) accept_bits<NT, GR, true>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+        }
+        __syncthreads();
+        store_state<NT>(T);
+        return;
+    }
     // Groups of the tile already in a ground state keep their recorded first hit.
     uint32_t hm = 0;
     if (T.tid < T.ngrp) {
@@ -404,23 +470,23 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     if (I->track) {
         // This instance keeps producing new ground-state clones: test every sweep.
         uint32_t hm_t = hm;
-        accept_bits<NT, GR>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+        accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
             uint32_t acc[G] = {};
             sweep<NT, CW, GR, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
             reduce_acc<CW>(T, acc);
             __syncthreads();
             if (T.tid < T.ngrp) record_hits(T, t, hm_t);
-            if (t + 1 < t1) accept_bits<NT, GR>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+            if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
         hm = hm_t;
         check_state<NT, CW, GR>(T, t1, hm);
     } else {
         uint32_t none[G] = {};  // unused: this loop tracks no ground states
-        accept_bits<NT, GR>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+        accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
             sweep<NT, CW, GR, false>(T, (t & 1) ? T.rb1 : T.rb0, none);
-            if (t + 1 < t1) accept_bits<NT, GR>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+            if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
         if (check_state<NT, CW, GR>(T, t1, hm)) {
             // Replay from the chunk's start state with a per-sweep ground-state test.
@@ -432,25 +498,20 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
             }
             __syncthreads();
             load_state<NT>(T);
-            accept_bits<NT, GR>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+            accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
             for (uint32_t t = t0; t < t1; ++t) {
                 uint32_t acc[G] = {};
                 sweep<NT, CW, GR, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
                 reduce_acc<CW>(T, acc);
                 __syncthreads();
                 if (T.tid < T.ngrp) record_hits(T, t, hm_replay);
-                if (t + 1 < t1) accept_bits<NT, GR>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+                if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
             }
             if (T.tid == 0) atomicOr(const_cast<uint32_t *>(&I->track), 1u);
         }
     }
     __syncthreads();
-    uint4 *dst0 = reinterpret_cast<uint4 *>(I->state + 4 * (size_t)T.blk0);
-    for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
-        const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
-        (dst0 + ((size_t)i * T.W >> 1))[k] =
-            *reinterpret_cast<const uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k);
-    }
+    store_state<NT>(T);
 }
 
 // ------------------------------------------------------------------------------ control
@@ -538,9 +599,10 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 
 }  // namespace
 
-size_t chunk_lds_bytes(uint32_t n, uint32_t B, uint32_t n_classes, bool rec_global) {
+size_t chunk_lds_bytes(uint32_t n, uint32_t B, uint32_t n_classes, bool rec_global, bool met) {
     return (rec_global ? 0 : lds_rec_bytes(n)) + (size_t)n * B * 32 +
-           2 * align16((size_t)n * B) + (size_t)B * 8 * 4 + 16 + 4 * (size_t)n_classes;
+           2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16 +
+           4 * (size_t)n_classes;
 }
 
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
@@ -550,52 +612,62 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NT, int CW, bool GR>
+template <int NT, int CW, bool GR, bool MET>
 hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            size_t lds_bytes, hipStream_t s) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk<NT, CW, GR>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(qg_chunk<NT, CW, GR, MET>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((qg_chunk<NT, CW, GR>), dim3(n_tiles), dim3(NT), lds_bytes, s, d_insts,
-                       d_tiles);
+    hipLaunchKernelGGL((qg_chunk<NT, CW, GR, MET>), dim3(n_tiles), dim3(NT), lds_bytes, s,
+                       d_insts, d_tiles);
     return hipGetLastError();
 }
 
-template <int CW, bool GR>
+template <int CW, bool GR, bool MET>
 hipError_t launch_chunk_cw(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            int threads, size_t lds_bytes, hipStream_t s) {
     switch (threads) {
-        case 64: return launch_chunk_nt<64, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 128: return launch_chunk_nt<128, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 256: return launch_chunk_nt<256, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 512: return launch_chunk_nt<512, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 1024: return launch_chunk_nt<1024, CW, GR>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 64: return launch_chunk_nt<64, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 128: return launch_chunk_nt<128, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 256: return launch_chunk_nt<256, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 512: return launch_chunk_nt<512, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 1024:
+            return launch_chunk_nt<1024, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <bool GR>
+template <bool GR, bool MET>
 hipError_t launch_chunk_gr(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            int threads, int col_bytes, size_t lds_bytes, hipStream_t s) {
     switch (col_bytes) {
-        case 4: return launch_chunk_cw<4, GR>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
-        case 8: return launch_chunk_cw<8, GR>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
-        case 16: return launch_chunk_cw<16, GR>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
+        case 4:
+            return launch_chunk_cw<4, GR, MET>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
+        case 8:
+            return launch_chunk_cw<8, GR, MET>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
+        case 16:
+            return launch_chunk_cw<16, GR, MET>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        int col_bytes, bool rec_global, size_t lds_bytes, hipStream_t s) {
-    return rec_global ? launch_chunk_gr<true>(d_insts, d_tiles, n_tiles, threads, col_bytes,
-                                              lds_bytes, s)
-                      : launch_chunk_gr<false>(d_insts, d_tiles, n_tiles, threads, col_bytes,
-                                               lds_bytes, s);
+                        int col_bytes, bool rec_global, bool met, size_t lds_bytes,
+                        hipStream_t s) {
+    if (met)
+        return rec_global ? launch_chunk_gr<true, true>(d_insts, d_tiles, n_tiles, threads,
+                                                        col_bytes, lds_bytes, s)
+                          : launch_chunk_gr<false, true>(d_insts, d_tiles, n_tiles, threads,
+                                                         col_bytes, lds_bytes, s);
+    return rec_global ? launch_chunk_gr<true, false>(d_insts, d_tiles, n_tiles, threads,
+                                                     col_bytes, lds_bytes, s)
+                      : launch_chunk_gr<false, false>(d_insts, d_tiles, n_tiles, threads,
+                                                      col_bytes, lds_bytes, s);
 }
 
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s) {

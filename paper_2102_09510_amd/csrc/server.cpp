@@ -192,7 +192,8 @@ struct xs_server {
                 }
             for (const xsh::TileGroup &g : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + g.first, (int)g.count, (int)g.threads,
-                                        (int)g.col_bytes, g.rec_global != 0, g.lds, stream));
+                                        (int)g.col_bytes, g.rec_global != 0, g.met != 0, g.lds,
+                                        stream));
             XS_HIP(xs::launch_decide(d_inst, R, d_active, stream));
             XS_HIP(hipMemcpyAsync(h.data(), d_inst, sizeof(xs::InstDev) * R,
                                   hipMemcpyDeviceToHost, stream));

@@ -37,7 +37,7 @@ struct InstDev {
     uint32_t track;       // nonzero once a chunk had to be replayed: later chunks test every sweep
     uint32_t col_bytes;   // task column width of this instance's launches (host side)
     uint32_t rec_global;  // records read from global memory (host side: selects the kernel)
-    uint32_t pad;
+    uint32_t thr0;        // w0 threshold: k = 0 spins flip iff the draw is below it (0: never)
 };
 
 }  // namespace xs
@@ -47,10 +47,13 @@ namespace xs {
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
 // threads: 64, 128, 256, 512 or 1024, at least 8 * tile_blocks of every tile it runs;
 // col_bytes: 4, 8 or 16 bytes of a spin row per task; rec_global: every tile's instance has
-// grec set (records in global memory), else records are staged in LDS.
+// grec set (records in global memory), else records are staged in LDS; met: every tile's
+// instance has thr0 > 0 (w0 rule, no ground-state tracking).
 hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        int col_bytes, bool rec_global, size_t lds_bytes, hipStream_t s);
+                        int col_bytes, bool rec_global, bool met, size_t lds_bytes,
+                        hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
 hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
-size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, uint32_t n_classes, bool rec_global);
+size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, uint32_t n_classes, bool rec_global,
+                       bool met);
 }  // namespace xs

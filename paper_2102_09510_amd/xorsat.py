@@ -47,7 +47,8 @@ class RunConfig(ctypes.Structure):
                 ("max_sweeps", ctypes.c_uint32), ("start_sweep", ctypes.c_uint32),
                 ("chunk_sweeps", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
                 ("wg_threads", ctypes.c_uint32), ("col_bytes", ctypes.c_uint32),
-                ("rec_global", ctypes.c_uint32)]
+                ("rec_global", ctypes.c_uint32), ("accept_thr0", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class RunBuffers(ctypes.Structure):
@@ -235,11 +236,14 @@ class RunOutput:
 def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: int = 3604,
                 max_sweeps: int = 100000, stop_on_first: bool = True, resume: bool = False,
                 start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0,
-                wg_threads: int = 0, col_bytes: int = 0, rec_global: int = 0) -> RunConfig:
+                wg_threads: int = 0, col_bytes: int = 0, rec_global: int = 0,
+                accept_thr0: int = 0) -> RunConfig:
+    """accept_thr0 > 0 selects the rule with w0 = accept_thr0 / 65536 (no ground-state
+    tracking: first_hit marks only clones whose end configuration is a ground state)."""
     flags = (XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0)
     return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
                      accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks,
-                     wg_threads, col_bytes, rec_global)
+                     wg_threads, col_bytes, rec_global, accept_thr0, 0)
 
 
 def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):

@@ -36,12 +36,12 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(xorsat.EXPORTS) == names
     for name in names:
         assert hasattr(lib, name), name
-    assert lib.xs_abi_version() == 1
+    assert lib.xs_abi_version() == 2
     assert lib.xs_status_str(1) == b"XS_EINVAL"
 
 
 def test_struct_layouts():
-    assert ctypes.sizeof(xorsat.RunConfig) == 56  # 56 bytes of fields
+    assert ctypes.sizeof(xorsat.RunConfig) == 64  # 64 bytes of fields
     assert ctypes.sizeof(xorsat.RunBuffers) == 32
     assert ctypes.sizeof(xorsat.RunResult) == 56
     assert ctypes.sizeof(xorsat.InstanceInfo) == 16

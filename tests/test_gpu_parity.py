@@ -41,7 +41,7 @@ def oracle_replay(inst, h, cfg, out, clones, init_spins=None):
     for a, b in zip(starts, ends):
         init = None if init_spins is None else init_spins[a:b]
         r = oracle.run(inst.tri, inst.J, operm, seed=cfg.seed, instance_id=cfg.instance_id,
-                       thr=cfg.accept_thr, n_sweeps=out.sweeps_done,
+                       thr=cfg.accept_thr, thr0=cfg.accept_thr0, n_sweeps=out.sweeps_done,
                        start_sweep=cfg.start_sweep, clone_begin=int(clones[a]),
                        clone_count=int(b - a), init_spins=init, want_final=True)
         for k in res:
@@ -239,3 +239,97 @@ def test_full_size_sampled_clones(n, clones, sweeps):
     sample = np.sort(np.concatenate([32 * g + np.arange(32) for g in groups]))
     sample = np.r_[sample, clones - 1]
     assert_parity(inst, h, cfg, out, clones=sample)
+
+
+# --------------------------------------------------------------------------- w0 > 0 (Metropolis)
+
+def _w_thresholds(T):
+    """w1 = exp(-2/T) and w0 = w1^3 (the detailed-balance rule at temperature T) as 16-bit
+    thresholds."""
+    import math
+    return round(math.exp(-2.0 / T) * 65536), round(math.exp(-6.0 / T) * 65536)
+
+
+@pytest.mark.parametrize("n,clones,B,T,C,G,chunk,sweeps,thr,thr0", [
+    (100, 4096, 2, 0, 0, 0, 7, 40, *_w_thresholds(1.0)),     # ragged classes, 8 tiles
+    (37, 2048, 0, 0, 0, 0, 0, 33, THR_PAPER, 20000),          # odd N, large w0, one chunk
+    (257, 1024, 1, 64, 8, 1, 5, 23, *_w_thresholds(0.69)),    # global records, narrow columns
+    (128, 8192, 4, 256, 4, 2, 16, 50, 65536, 65536),          # every spin flips each visit
+    (4, 256, 1, 0, 0, 0, 1, 9, 30000, 1),                     # smallest case
+])
+def test_metropolis_budget_runs(n, clones, B, T, C, G, chunk, sweeps, thr, thr0):
+    """w0 > 0: every clone's end configuration, energy and end-only ground-state mark equal the
+    oracle's."""
+    _torch()
+    inst = planted_instance(n, 800 + n)
+    h = xorsat.Instance(inst.tri, inst.J)
+    cfg = xorsat.make_config(n_clones=clones, seed=n * 3 + 1, instance_id=5, accept_thr=thr,
+                             accept_thr0=thr0, max_sweeps=sweeps, stop_on_first=False,
+                             chunk_sweeps=chunk, tile_blocks=B, wg_threads=T, col_bytes=C,
+                             rec_global=G)
+    out = xorsat.run(h, cfg)
+    ref = assert_parity(inst, h, cfg, out)
+    assert set(np.unique(ref["first_hit"])) <= {-1, sweeps}
+    tts, winner = oracle.solve_results(ref["first_hit"])
+    assert (out.tts_sweeps, out.winner_clone) == (tts, winner)
+
+
+def test_metropolis_end_ground_states_marked():
+    """A small instance at low w0: many clones end in a ground state; exactly those are marked
+    with the end sweep, and the solved configuration is the lowest such clone's."""
+    _torch()
+    inst = planted_instance(12, 4242)
+    h = xorsat.Instance(inst.tri, inst.J)
+    cfg = xorsat.make_config(n_clones=4096, seed=11, instance_id=0, accept_thr=THR_PAPER,
+                             accept_thr0=11, max_sweeps=200, stop_on_first=False,
+                             chunk_sweeps=50)
+    out = xorsat.run(h, cfg)
+    ref = assert_parity(inst, h, cfg, out)
+    fh = out.first_hit.cpu().numpy()
+    en = out.energy.cpu().numpy()
+    assert np.array_equal(fh == 200, en == -12)
+    assert (fh == 200).sum() > 100
+    winner = int(np.flatnonzero(fh == 200)[0])
+    assert out.tts_sweeps == 200 and out.winner_clone == winner
+    assert np.array_equal(out.solved, ref["final_spins"][winner])
+
+
+def test_metropolis_rejects_stop_on_first():
+    _torch()
+    inst = planted_instance(16, 1)
+    h = xorsat.Instance(inst.tri, inst.J)
+    cfg = xorsat.make_config(n_clones=256, seed=1, accept_thr0=5, max_sweeps=10,
+                             stop_on_first=True)
+    with pytest.raises(xorsat.XsError):
+        xorsat.run(h, cfg)
+
+
+def test_metropolis_tiling_and_batch_neutral():
+    """Launch knobs and batching with quasi-greedy instances change nothing for w0 > 0 runs."""
+    torch = _torch()
+    inst = planted_instance(128, 21)
+    h = xorsat.Instance(inst.tri, inst.J)
+    thr, thr0 = _w_thresholds(0.8)
+    outs = []
+    for B, T, C, G in ((1, 0, 0, 0), (4, 1024, 16, 2), (8, 256, 8, 1), (2, 128, 4, 2)):
+        cfg = xorsat.make_config(n_clones=8192, seed=7, instance_id=2, accept_thr=thr,
+                                 accept_thr0=thr0, max_sweeps=100, stop_on_first=False,
+                                 chunk_sweeps=30, tile_blocks=B, wg_threads=T, col_bytes=C,
+                                 rec_global=G)
+        outs.append(xorsat.run(h, cfg))
+    for o in outs[1:]:
+        assert torch.equal(o.state, outs[0].state)
+        assert torch.equal(o.first_hit, outs[0].first_hit)
+        assert torch.equal(o.energy, outs[0].energy)
+    # mixed batch: quasi-greedy and w0 > 0 runs of the same instance side by side
+    base = dict(n_clones=8192, seed=7, instance_id=2, accept_thr=thr, max_sweeps=100,
+                stop_on_first=False, chunk_sweeps=30)
+    cfgs = [xorsat.make_config(accept_thr0=thr0, **base), xorsat.make_config(**base)]
+    batch = xorsat.run_batch([h, h], cfgs)
+    qg = xorsat.run(h, cfgs[1])
+    assert torch.equal(batch[0].state, outs[0].state)
+    assert torch.equal(batch[0].energy, outs[0].energy)
+    assert torch.equal(batch[1].state, qg.state)
+    assert torch.equal(batch[1].first_hit, qg.first_hit)
+    # the two rules differ (w0 > 0 moves k = 0 spins)
+    assert not torch.equal(batch[0].state, batch[1].state)
