@@ -84,8 +84,8 @@ def measured_traffic(args):
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "qg_chunk_n256x64_hbm_counters.json")
-    if not os.path.exists(path) or (args.instances, args.n, args.clones, args.chunk) != \
-            (64, 256, 65536, 100):
+    if not os.path.exists(path) or (args.instances, args.n, args.clones, args.chunk,
+                                    args.accept_thr0) != (64, 256, 65536, 100, 0):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()

@@ -333,3 +333,26 @@ def test_metropolis_tiling_and_batch_neutral():
     assert torch.equal(batch[1].first_hit, qg.first_hit)
     # the two rules differ (w0 > 0 moves k = 0 spins)
     assert not torch.equal(batch[0].state, batch[1].state)
+
+
+@pytest.mark.parametrize("T", [1.0, 0.8])
+def test_metropolis_full_size_paramagnetic_energy(T):
+    """N = 2048, 2^17 clones, w0 = w1^3 at temperature T: the mean energy per spin after 300
+    sweeps is the paramagnet's -tanh(1/T) (a property at any size), and sampled clones from
+    different tiles match the oracle bit for bit."""
+    import math
+    _torch()
+    n, clones = 2048, 1 << 17
+    inst = planted_instance(n, 31337)
+    h = xorsat.Instance(inst.tri, inst.J)
+    thr, thr0 = _w_thresholds(T)
+    cfg = xorsat.make_config(n_clones=clones, seed=12345, instance_id=9, accept_thr=thr,
+                             accept_thr0=thr0, max_sweeps=300, stop_on_first=False)
+    out = xorsat.run(h, cfg)
+    en = out.energy.cpu().numpy()
+    e = en.mean() / n
+    assert abs(e + math.tanh(1.0 / T)) < 0.004, e
+    rng = np.random.default_rng(int(T * 10))
+    groups = rng.choice(clones // 32, size=3, replace=False)
+    sample = np.sort(np.concatenate([32 * g + np.arange(32) for g in groups]))
+    assert_parity(inst, h, cfg, out, clones=sample)
