@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -60,17 +61,26 @@ def parse():
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     ap.add_argument("--workload", default="batched",
-                    choices=["batched", "steady", "uneven", "serve", "tts", "w1scan"],
+                    choices=["batched", "steady", "uneven", "serve", "tts", "w1scan", "paper"],
                     help="batched: the default line; steady: 16 x N=1024 x 2^20 clones, fixed "
                          "sweeps; uneven: 512 instances of uneven N and clone count, batched vs "
                          "served vs one at a time; serve: Poisson stream through the server vs "
                          "one run at a time; tts: the exponential TTS law on many runs of one "
                          "small instance, tau x N_cl scaling and the short-timeout estimate; "
                          "w1scan: mean TTS against w1 on one small instance, and the same w1 "
-                         "with w0 = w1^3")
+                         "with w0 = w1^3; paper: TTS_99 in seconds at the paper's clone count "
+                         "(327,680) on planted N = 128 instances, one run at a time, and a "
+                         "short-timeout estimate at N = 256")
     ap.add_argument("--accept-thr0", type=int, default=0,
                     help="batched: w0 threshold (w0 = thr0 / 65536); > 0 runs the w0 rule for "
                          "the full budget (a ground state is not absorbing, so no early stop)")
+    ap.add_argument("--scan-n", type=int, default=100, help="w1scan: spins of the instance")
+    ap.add_argument("--paper-instances", type=int, default=100, help="paper: N = 128 instances")
+    ap.add_argument("--paper-runs", type=int, default=16, help="paper: runs per N = 128 instance")
+    ap.add_argument("--paper-timeout-instances", type=int, default=32,
+                    help="paper: N = 256 instances, one capped run each")
+    ap.add_argument("--paper-timeout-sweeps", type=int, default=2000000,
+                    help="paper: sweep cap of the N = 256 runs")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
@@ -116,10 +126,18 @@ def cpu_baseline(insts, args, target_s):
                    thr0=args.accept_thr0, n_sweeps=sweeps, clone_count=256, threads=threads)
         updates += 256 * inst.n * sweeps
     dt = time.perf_counter() - t0
+    # one core: the first instance, 256 clones, a tenth of the sweeps
+    s1 = max(10, sweeps // 10)
+    t1 = time.perf_counter()
+    oracle.run(insts[0].tri, insts[0].J, perms[0], seed=0, instance_id=0, thr=3604,
+               thr0=args.accept_thr0, n_sweeps=s1, clone_count=256, threads=1)
+    one = 256 * insts[0].n * s1 / (time.perf_counter() - t1) / 1e9
     return {"value": updates / dt / 1e9, "unit": "clone-spin updates/ns", "cores": threads,
             "kind": "oracle",
             "sample": f"{len(insts)} instances x 256 clones x {sweeps} sweeps (N={insts[0].n}), "
-                      f"{updates:.3e} updates in {dt:.1f} s"}
+                      f"{updates:.3e} updates in {dt:.1f} s",
+            "single_core_value": one,
+            "single_core_sample": f"1 instance x 256 clones x {s1} sweeps, 1 thread"}
 
 
 def pct(v, q):
@@ -382,8 +400,8 @@ def workload_w1scan(args, xorsat, torch):
     from paper_2102_09510_amd import tts_stats as ts
     from paper_2102_09510_amd.instances import gen_seed, planted_instance
 
-    n, runs, ncl, cap = 100, 512, 1024, 200000
-    w1s = [0.03, 0.04, 0.045, 0.05, 0.055, 0.06, 0.065, 0.07, 0.08]
+    n, runs, ncl, cap = args.scan_n, 512, 1024, 400000
+    w1s = [0.03, 0.04, 0.05, 0.055, 0.06, 0.07, 0.08, 0.09, 0.10, 0.12, 0.14, 0.17, 0.20]
     inst = planted_instance(n, gen_seed(7, 0))
     h = xorsat.Instance(inst.tri, inst.J)
     rows, times_of = [], {}
@@ -432,6 +450,84 @@ def workload_w1scan(args, xorsat, torch):
             "w0_eq_w1_cubed": {"budget_sweeps": budget, "runs": runs, "rows": met}}
 
 
+def workload_paper(args, xorsat, torch):
+    """The paper's headline quantity on synthetic planted instances at its clone count
+    (Section "Numerical results", Table 1: TTS_99 of the median instance, 327,680 clones, w1 =
+    0.055, one run on the GPU at a time). N = 128: every run to its first ground state, tau of an
+    instance = mean wall time of its runs, TTS_99 = ln(100) tau. N = 256: runs capped at a short
+    timeout (Section "Running with a short timeout"); with few successes per instance the
+    instances are pooled into one posterior (inverse-gamma with shape = successes and scale =
+    total capped time)."""
+    from paper_2102_09510_amd import tts_stats as ts
+    from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance
+
+    ncl = 327680
+    out = {"metric": "TTS_99 (s) of the median instance, 327,680 clones, w1 = 0.055",
+           "config": {"workload": "planted instances, one run at a time"}}
+    # N = 128: full runs
+    n, count, runs = 128, args.paper_instances, args.paper_runs
+    taus, taus_sw = [], []
+    t_all = time.perf_counter()
+    for k in range(count):
+        inst = planted_instance(n, gen_seed(8, k))
+        h = xorsat.Instance(inst.tri, inst.J)
+        secs, sweeps = [], []
+        for r in range(runs):
+            cfg = xorsat.make_config(n_clones=ncl, seed=0x5EED + 7919 * r + 104729 * k,
+                                     instance_id=k, accept_thr=THR_PAPER, max_sweeps=10**7,
+                                     stop_on_first=True, chunk_sweeps=100)
+            o = xorsat.run(h, cfg, want_energy=False)
+            assert o.tts_sweeps >= 0
+            secs.append(o.seconds)
+            sweeps.append(o.tts_sweeps)
+        taus.append(float(np.mean(secs)))
+        taus_sw.append(float(np.mean(sweeps)))
+        if k % 10 == 9:
+            print(f"# N=128: {k + 1} instances, {time.perf_counter() - t_all:.1f} s",
+                  file=sys.stderr, flush=True)
+    ln100 = math.log(100.0)
+    out["n128"] = {"instances": count, "runs_per_instance": runs,
+                   "tts99_s_median": ln100 * float(np.median(taus)),
+                   "tts99_s_p10_p90": [ln100 * float(np.percentile(taus, 10)),
+                                       ln100 * float(np.percentile(taus, 90))],
+                   "tau_sweeps_median": float(np.median(taus_sw)),
+                   "paper_tts99_s_v100": 0.0275}
+    # N = 256: short timeout, pooled
+    n, count, cap = 256, args.paper_timeout_instances, args.paper_timeout_sweeps
+    hs = []
+    for k in range(count):
+        inst = planted_instance(n, gen_seed(9, k))
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+    cfgs = [xorsat.make_config(n_clones=ncl, seed=0xFACE + 104729 * k, instance_id=k,
+                               accept_thr=THR_PAPER, max_sweeps=cap, stop_on_first=True,
+                               chunk_sweeps=100) for k in range(count)]
+    print(f"# N=256: {count} runs capped at {cap} sweeps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = []
+    for g in range(0, count, 8):  # groups of 8 runs, so that progress shows
+        res += xorsat.run_batch(hs[g:g + 8], cfgs[g:g + 8], want_energy=False)
+        print(f"# N=256: {len(res)} runs done, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    succ = sum(1 for o in res if o.tts_sweeps >= 0)
+    # seconds per sweep of one run alone at this size
+    o1 = xorsat.run(hs[0], xorsat.make_config(n_clones=ncl, seed=1, instance_id=0,
+                                               accept_thr=THR_PAPER, max_sweeps=2000,
+                                               stop_on_first=False, chunk_sweeps=100),
+                    want_energy=False)
+    s_per_sweep = o1.seconds / 2000
+    n256 = {"runs": count, "cap_sweeps": cap, "successes": succ, "seconds": round(dt, 1),
+            "seconds_per_sweep_one_run": s_per_sweep, "paper_tts99_s_v100": 640.0}
+    if succ:
+        post = ts.TimeoutPosterior(succ, count, cap)
+        q = [post.quantile(0.16), post.quantile(0.5), post.quantile(0.84)]
+        n256.update(tau_sweeps_posterior_median=q[1], tau_sweeps_68=[q[0], q[2]],
+                    tts99_s_pooled=ln100 * q[1] * s_per_sweep,
+                    tts99_s_pooled_68=[ln100 * q[0] * s_per_sweep, ln100 * q[2] * s_per_sweep])
+    out["n256_timeout"] = n256
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -458,7 +554,7 @@ def main():
     if args.workload != "batched":
         fn = {"steady": workload_steady, "uneven": workload_uneven,
               "serve": workload_serve, "tts": workload_tts,
-              "w1scan": workload_w1scan}[args.workload]
+              "w1scan": workload_w1scan, "paper": workload_paper}[args.workload]
         print(json.dumps(fn(args, xorsat, torch)), flush=True)
         return
     insts = [planted_instance(args.n, gen_seed(2, k)) for k in range(args.instances)]

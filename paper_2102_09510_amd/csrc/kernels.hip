@@ -247,11 +247,12 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, 
             y[g] = met_word(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
                             0u - ((bits >> g) & 1u), 0u - ((bits0 >> g) & 1u));
     } else {
-        const uint32_t bits = (uint32_t)xs_lds[rb + (p << T.lB) + T.rb_sel] >> T.rb_shift;
+        const int bits = xs_lds[rb + (p << T.lB) + T.rb_sel];
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int g = 0; g < G; ++g)  // sign-extended bit rb_shift + g: the group's mask
             y[g] = qg_word<kAcc>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
-                                 0u - ((bits >> g) & 1u), acc[g]);
+                                 (uint32_t)__builtin_amdgcn_sbfe(bits, T.rb_shift + g, 1),
+                                 acc[g]);
     }
     col_store<CW>(self, y);
 }
@@ -261,19 +262,25 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, 
 // read-only, so each thread fetches its first record of a class before that class's barrier.
 template <int NT, int CW, bool GR, bool kAcc, bool MET = false>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
-    uint32_t cd = lds_u32(T.cls);
+    // The class descriptor is uniform: moved to a scalar register once read from LDS.
+    uint32_t cd = __builtin_amdgcn_readfirstlane(lds_u32(T.cls));
     for (uint32_t c = 0; c < T.ncls; ++c) {
         const uint32_t cs = cd & 0xFFFFu;
         const uint32_t ntask = (cd >> 16) << T.lcol;
         const uint32_t p0 = cs + (T.tid >> T.lcol);
-        uint4 r0 = make_uint4(0, 0, 0, 0);
+        uint4 r0;  // read only by threads with a task
         if (T.tid < ntask) r0 = rec_at<GR>(T, p0);
-        if (c + 1 < T.ncls) cd = lds_u32(T.cls + 4 * (c + 1));
+        if (c + 1 < T.ncls) cd = __builtin_amdgcn_readfirstlane(lds_u32(T.cls + 4 * (c + 1)));
         __syncthreads();
         if (T.tid < ntask) update_task<CW, kAcc, MET>(T, r0, p0, rb, acc);
-        for (uint32_t q = T.tid + NT; q < ntask; q += NT) {
-            const uint32_t p = cs + (q >> T.lcol);
-            update_task<CW, kAcc, MET>(T, rec_at<GR>(T, p), p, rb, acc);
+        // further rounds of the class (more tasks than threads): a uniform trip count
+        const uint32_t rounds = (ntask - 1) / NT;
+        for (uint32_t k = 1; k <= rounds; ++k) {
+            const uint32_t q = T.tid + k * NT;
+            if (q < ntask) {
+                const uint32_t p = cs + (q >> T.lcol);
+                update_task<CW, kAcc, MET>(T, rec_at<GR>(T, p), p, rb, acc);
+            }
         }
     }
 }
