@@ -123,11 +123,7 @@ typedef struct {
                               ground state is not absorbing: no sweep is tested, first_hit is
                               end_sweep for a clone whose end configuration has E = -N and -1
                               otherwise, and XS_STOP_ON_FIRST is rejected (XS_EINVAL). */
-    uint32_t wave_tiles;   /* how a workgroup's clone blocks are scheduled: 1 = one block per
-                              wave, each wave sweeping its block alone (wg_threads =
-                              64 * tile_blocks, tile_blocks <= 16), 2 = the workgroup sweeps its
-                              blocks together with a barrier per colour class, 0 = chosen by the
-                              library. Speed only. */
+    uint32_t reserved;     /* must be 0 */
 } xs_run_config;
 
 /*
@@ -157,7 +153,6 @@ typedef struct {
     uint32_t wg_threads;         /* workgroup size used (result-neutral) */
     uint32_t col_bytes;          /* task column width used (result-neutral) */
     uint32_t rec_global;         /* 1 if records were read from global memory (result-neutral) */
-    uint32_t wave_tiles;         /* 1 if every wave swept its own block (result-neutral) */
     uint64_t clone_spin_updates; /* n_clones * n * sweeps_done */
     double seconds;              /* wall time of the call */
 } xs_run_result;
@@ -246,21 +241,21 @@ xs_status xs_server_get_stats(const xs_server *srv, xs_server_stats *out);
  * Autotuner of the result-neutral launch knobs (tile_blocks: clones per workgroup, in blocks of
  * 256; wg_threads: threads per workgroup; col_bytes: clones one thread updates per step, which
  * with the class size sets how a colour class is spread over the threads). It times the valid
- * combinations (both wave_tiles schedules) with short budget runs of `count` copies of
+ * combinations with short budget runs of `count` copies of
  * `inst` (fewer if their state would exceed 2 GiB) on `stream`, using HIP events around the
  * sweep launches, and records the fastest combination for workloads of the same N (rounded up to a
  * power of two), clone count and batch size (rounded up to a power of two, at most 64). Later
  * runs whose config leaves both knobs 0 use the recorded pair. Allocates and frees its own
  * device buffers. Results of any run never depend on these knobs.
  */
-#define XS_TUNE_MAX_TRIALS 96
+#define XS_TUNE_MAX_TRIALS 64
 typedef struct {
-    uint32_t tile_blocks, wg_threads, col_bytes, rec_global, wave_tiles;
+    uint32_t tile_blocks, wg_threads, col_bytes, rec_global;
     double updates_per_ns; /* sweep-kernel rate of this trial */
 } xs_tune_trial;
 
 typedef struct {
-    uint32_t tile_blocks, wg_threads, col_bytes, rec_global, wave_tiles; /* the fastest choice */
+    uint32_t tile_blocks, wg_threads, col_bytes, rec_global; /* the fastest choice */
     double updates_per_ns;
     int32_t n_trials;
     xs_tune_trial trials[XS_TUNE_MAX_TRIALS];
@@ -268,9 +263,8 @@ typedef struct {
 
 xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count, void *stream,
                       xs_tune_result *out);
-/* Write / read the recorded choices as text ("n_bucket clones count_bucket B T CW GR WV rate"
- * lines, GR = 1 for records in global memory, 2 for LDS; WV = 1 for wave tiles, 2 for
- * workgroup tiles).
+/* Write / read the recorded choices as text ("n_bucket clones count_bucket B T CW GR rate"
+ * lines, GR = 1 for records in global memory, 2 for LDS).
  * Loading adds to (and overrides) the table in memory. */
 xs_status xs_tune_save(const char *path);
 xs_status xs_tune_load(const char *path);

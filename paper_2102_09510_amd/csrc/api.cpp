@@ -202,14 +202,7 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
     if (cfg->accept_thr > 65536) return fail(XS_EINVAL, "accept_thr %u > 65536", cfg->accept_thr);
     if (cfg->accept_thr0 > 65536)
         return fail(XS_EINVAL, "accept_thr0 %u > 65536", cfg->accept_thr0);
-    if (cfg->wave_tiles > 2)
-        return fail(XS_EINVAL, "wave_tiles %u must be 0, 1 or 2", cfg->wave_tiles);
-    if (cfg->wave_tiles == 1) {
-        if (cfg->tile_blocks > 16)
-            return fail(XS_EINVAL, "wave_tiles = 1 needs tile_blocks <= 16");
-        if (cfg->tile_blocks && cfg->wg_threads && cfg->wg_threads != 64 * cfg->tile_blocks)
-            return fail(XS_EINVAL, "wave_tiles = 1 needs wg_threads = 64 * tile_blocks");
-    }
+    if (cfg->reserved) return fail(XS_EINVAL, "xs_run_config.reserved must be 0");
     if (cfg->accept_thr0 && (cfg->flags & XS_STOP_ON_FIRST))
         return fail(XS_EINVAL, "XS_STOP_ON_FIRST needs accept_thr0 = 0 (with w0 > 0 a ground "
                                "state is not absorbing and no sweep is tested)");
@@ -259,12 +252,6 @@ uint32_t default_col_bytes(uint32_t B) { return B >= 4 ? 16u : 8u; }
 // workgroup's LDS (n >= 512: 8 KB or more); measured neutral at n = 256, faster above.
 uint32_t default_rec_global(uint32_t n) { return n >= 512 ? 1u : 0u; }
 
-// Default block schedule: workgroup tiles (changed only by measurement).
-uint32_t default_wave_tiles(uint32_t n) {
-    (void)n;
-    return 2u;
-}
-
 // Options of one driver call beyond the public configuration.
 struct RunOpts {
     bool graph = true;             // replay the chunk loop as a captured hipGraph
@@ -280,7 +267,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    uint32_t tile_blocks, wg_threads, col_bytes, rec_global, wave_tiles;
+    uint32_t tile_blocks, wg_threads, col_bytes, rec_global;
     double rate;
 };
 std::mutex g_tune_mu;
@@ -350,9 +337,8 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         xs::InstDev &d = h[k];
         const uint32_t nb = c.n_clones / 256;
         uint32_t B = c.tile_blocks ? c.tile_blocks : max_tile_blocks(d.n, nb, 1024);
-        uint32_t tuned_T = 0, tuned_C = 0, tuned_G = 0, tuned_V = 0;
-        if (!c.tile_blocks && !c.wg_threads && !c.col_bytes && !c.rec_global &&
-            !c.wave_tiles) {
+        uint32_t tuned_T = 0, tuned_C = 0, tuned_G = 0;
+        if (!c.tile_blocks && !c.wg_threads && !c.col_bytes && !c.rec_global) {
             std::lock_guard<std::mutex> lock(g_tune_mu);
             auto it = g_tune.find(tune_key(d.n, c.n_clones, count));
             if (it != g_tune.end() && nb % it->second.tile_blocks == 0 &&
@@ -361,14 +347,12 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
                 tuned_T = it->second.wg_threads;
                 tuned_C = it->second.col_bytes;
                 tuned_G = it->second.rec_global;
-                tuned_V = it->second.wave_tiles;
             }
         }
         d.tile_blocks = B;
         d.wg_threads = tuned_T;  // 0 unless tuned
         d.col_bytes = tuned_C;
         d.rec_global = tuned_G;  // 0 = not tuned, 1 = global, 2 = LDS
-        d.wave = tuned_V;        // 0 = not tuned, 1 = wave tiles, 2 = workgroup tiles
     }
     // Shrink automatic tiles while the batch has too few workgroups.
     auto count_tiles = [&]() {
@@ -380,8 +364,7 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         if (count_tiles() >= kTargetTiles) break;
         bool changed = false;
         for (int k = 0; k < count; ++k)
-            if (!cfgs[k].tile_blocks && !h[k].wg_threads &&
-                !(cfgs[k].wave_tiles == 1 && cfgs[k].wg_threads) && h[k].tile_blocks > 1) {
+            if (!cfgs[k].tile_blocks && !h[k].wg_threads && h[k].tile_blocks > 1) {
                 h[k].tile_blocks /= 2;
                 changed = true;
             }
@@ -389,30 +372,13 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
     }
     // Tiles grouped by (workgroup size, column width, record placement, rule): one launch per
     // group and chunk.
-    using LaunchKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, uint32_t>;
+    using LaunchKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
     std::map<LaunchKey, std::vector<uint2>> by_launch;
     std::map<LaunchKey, size_t> lds_of;
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
-        const uint32_t V = cfgs[k].wave_tiles ? cfgs[k].wave_tiles
-                           : d.wave            ? d.wave
-                                               : default_wave_tiles(d.n);
-        d.wave = V == 1 ? 1u : 0u;
-        if (d.wave) {
-            // one block per wave: the thread count follows the tile (at most 16 waves)
-            if (cfgs[k].wg_threads && !cfgs[k].tile_blocks) {
-                const uint32_t B = cfgs[k].wg_threads / 64;
-                if ((cfgs[k].n_clones / 256) % B || d.n * B > 2048)
-                    return fail(XS_EINVAL, "wave_tiles = 1 with wg_threads %u: %u blocks per "
-                                           "workgroup do not tile this run",
-                                cfgs[k].wg_threads, B);
-                d.tile_blocks = B;
-            }
-            d.tile_blocks = std::min(d.tile_blocks, 16u);
-        }
         d.log2_tile_blocks = ilog2(d.tile_blocks);
-        uint32_t T = d.wave                ? 64 * d.tile_blocks
-                     : cfgs[k].wg_threads ? cfgs[k].wg_threads
+        uint32_t T = cfgs[k].wg_threads ? cfgs[k].wg_threads
                      : d.wg_threads       ? d.wg_threads
                                           : default_threads(d.tile_blocks);
         T = std::max(T, 8 * d.tile_blocks);
@@ -427,7 +393,7 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         d.rec_global = GRc == 1 ? 1u : 0u;
         const uint32_t nb = cfgs[k].n_clones / 256;
         const uint32_t met = d.thr0 ? 1u : 0u;
-        const auto key = std::make_tuple(T, C, d.rec_global, met, d.wave);
+        const auto key = std::make_tuple(T, C, d.rec_global, met);
         auto &v = by_launch[key];
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) v.push_back(make_uint2((uint32_t)k, b0));
         lds_of[key] = std::max(lds_of[key], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes,
@@ -437,9 +403,8 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
     groups.clear();
     for (auto &kv : by_launch) {
         groups.push_back(TileGroup{std::get<0>(kv.first), std::get<1>(kv.first),
-                                   std::get<2>(kv.first), std::get<3>(kv.first),
-                                   std::get<4>(kv.first), tiles.size(), kv.second.size(),
-                                   lds_of[kv.first]});
+                                   std::get<2>(kv.first), std::get<3>(kv.first), tiles.size(),
+                                   kv.second.size(), lds_of[kv.first]});
         tiles.insert(tiles.end(), kv.second.begin(), kv.second.end());
     }
     for (const TileGroup &g : groups)
@@ -529,7 +494,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             for (const TileGroup &gr : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + gr.first, (int)gr.count,
                                         (int)gr.threads, (int)gr.col_bytes, gr.rec_global != 0,
-                                        gr.met != 0, gr.wave != 0,
+                                        gr.met != 0,
                                         gr.lds, s));
             if (with_events) XS_HIP(hipEventRecord(ev[2 * g + 1], s));
             XS_HIP(xs::launch_decide(d_inst, count, d_active, s));
@@ -608,7 +573,6 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         r.wg_threads = d.wg_threads;
         r.col_bytes = d.col_bytes;
         r.rec_global = d.rec_global;
-        r.wave_tiles = d.wave;
         r.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * r.sweeps_done;
         r.seconds = secs;
         if (bufs[k].solved && d.winner != INT32_MAX)
@@ -757,65 +721,51 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
         bufs[k].solved = nullptr;
     }
     std::memset(out, 0, sizeof *out);
-    auto trial = [&](uint32_t B, uint32_t T, uint32_t C, uint32_t G, uint32_t V) -> xs_status {
-        if (out->n_trials >= XS_TUNE_MAX_TRIALS) return XS_OK;
-        for (auto &c : cfgs) {
-            c.tile_blocks = B;
-            c.wg_threads = T;
-            c.col_bytes = C;
-            c.rec_global = G;
-            c.wave_tiles = V;
-        }
-        RunOpts opt;
-        double ms = 0.0;
-        opt.kernel_ms = &ms;
-        xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
-                                 res.data(), opt);  // warm
-        if (st != XS_OK) return st;
-        ms = 0.0;
-        st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream, res.data(), opt);
-        if (st != XS_OK) return st;
-        uint64_t upd = 0;
-        for (auto &r : res) upd += r.clone_spin_updates;
-        const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
-        out->trials[out->n_trials++] = xs_tune_trial{B, T, C, G, V, rate};
-        if (rate > out->updates_per_ns) {
-            out->updates_per_ns = rate;
-            out->tile_blocks = B;
-            out->wg_threads = T;
-            out->col_bytes = C;
-            out->rec_global = G;
-            out->wave_tiles = V;
-        }
-        return XS_OK;
-    };
     for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
-        if (nb % B || n * B > 2048 ||
-            xs::chunk_lds_bytes(n, B, ncls, true, false) > 160 * 1024)
-            continue;
-        for (uint32_t C = 4; C <= 16; C *= 2)
-            for (uint32_t G = (n >= 512 ? 1u : 2u); G <= 2; ++G) {
-                if (xs::chunk_lds_bytes(n, B, ncls, G == 1, false) > 160 * 1024) continue;
-                // workgroup tiles: skip columns that leave most threads without a task in a
-                // full class
-                for (uint32_t T = 128; T <= 1024; T *= 2) {
-                    if (T < 8 * B || (T == 128 && B > 2) || 32u * (8u * B / (C / 4)) < T / 4)
+        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls, true, false) > 160 * 1024) continue;
+        for (uint32_t T = 128; T <= 1024; T *= 2) {
+            if (T < 8 * B || (T == 128 && B > 2)) continue;
+            for (uint32_t C = 4; C <= 16; C *= 2)
+                for (uint32_t G = (n >= 512 ? 1u : 2u); G <= 2; ++G) {
+                    // skip columns that leave most threads without a task in a full class
+                    if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
                         continue;
-                    xs_status st = trial(B, T, C, G, 2);
+                    if (xs::chunk_lds_bytes(n, B, ncls, G == 1, false) > 160 * 1024) continue;
+                    for (auto &c : cfgs) {
+                        c.tile_blocks = B;
+                        c.wg_threads = T;
+                        c.col_bytes = C;
+                        c.rec_global = G;
+                    }
+                    RunOpts opt;
+                    double ms = 0.0;
+                    opt.kernel_ms = &ms;
+                    xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(),
+                                             stream, res.data(), opt);  // warm
                     if (st != XS_OK) return st;
-                }
-                // wave tiles: one block per wave
-                if (B <= 16) {
-                    xs_status st = trial(B, 64 * B, C, G, 1);
+                    ms = 0.0;
+                    st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
+                                   res.data(), opt);
                     if (st != XS_OK) return st;
+                    uint64_t upd = 0;
+                    for (auto &r : res) upd += r.clone_spin_updates;
+                    const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
+                    out->trials[out->n_trials++] = xs_tune_trial{B, T, C, G, rate};
+                    if (rate > out->updates_per_ns) {
+                        out->updates_per_ns = rate;
+                        out->tile_blocks = B;
+                        out->wg_threads = T;
+                        out->col_bytes = C;
+                        out->rec_global = G;
+                    }
                 }
-            }
+        }
     }
     if (!out->n_trials) return fail(XS_EINVAL, "no valid launch configuration");
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[tune_key(n, n_clones, count)] = TuneVal{out->tile_blocks, out->wg_threads,
                                                    out->col_bytes, out->rec_global,
-                                                   out->wave_tiles, out->updates_per_ns};
+                                                   out->updates_per_ns};
     return XS_OK;
 }
 
@@ -825,12 +775,11 @@ xs_status xs_tune_save(const char *path) {
     if (!f) return fail(XS_EINVAL, "cannot open %s for writing", path);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     std::fprintf(f, "# n_bucket clones count_bucket tile_blocks wg_threads col_bytes "
-                    "rec_global wave_tiles updates_per_ns\n");
+                    "rec_global updates_per_ns\n");
     for (auto &kv : g_tune)
-        std::fprintf(f, "%u %u %u %u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
+        std::fprintf(f, "%u %u %u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
                      kv.first.count_bucket, kv.second.tile_blocks, kv.second.wg_threads,
-                     kv.second.col_bytes, kv.second.rec_global, kv.second.wave_tiles,
-                     kv.second.rate);
+                     kv.second.col_bytes, kv.second.rec_global, kv.second.rate);
     std::fclose(f);
     return XS_OK;
 }
@@ -843,16 +792,16 @@ xs_status xs_tune_load(const char *path) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        unsigned nb_, cl, cb, B, T, C, G, V;
+        unsigned nb_, cl, cb, B, T, C, G;
         double rate;
-        if (std::sscanf(line, "%u %u %u %u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &C, &G,
-                        &V, &rate) != 9)
+        if (std::sscanf(line, "%u %u %u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &C, &G,
+                        &rate) != 8)
             continue;
         if (!B || (B & (B - 1)) || B > (unsigned)xs::kMaxTileBlocks || !T || (T & (T - 1)) ||
             T < 64 || T > 1024 || T < 8 * B || (C != 4 && C != 8 && C != 16) ||
-            (G != 1 && G != 2) || (V != 1 && V != 2) || (V == 1 && T != 64 * B))
+            (G != 1 && G != 2))
             continue;
-        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, C, G, V, rate};
+        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, C, G, rate};
     }
     std::fclose(f);
     return XS_OK;

@@ -151,7 +151,7 @@ extern __shared__ __align__(16) uint8_t xs_lds[];
 struct Tile {
     const InstDev *I;
     const uint4 *grec;   // records in global memory (GR kernels), offsets for this tile's rows
-    uint32_t n, W, B, lB, rowb, ncol, lcol, n16, l16, ngrp, blk0, tid, col, lane;
+    uint32_t n, W, B, lB, rowb, ncol, lcol, n16, l16, ngrp, blk0, tid, col;
     uint32_t st;         // state rows (records start at 0)
     uint32_t rb0, rb1;   // acceptance bytes, double-buffered by sweep parity
     uint32_t acc;        // per-group accumulators [8*B] (uint32)
@@ -521,274 +521,6 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     store_state<NT>(T);
 }
 
-// ------------------------------------------------------------------------------ chunk, wave tiles
-
-// Wave-private tiles: the workgroup's B = NT / 64 blocks are dealt out one per wave, and a wave
-// updates only the columns of its own block. The classes of a sweep are then ordered inside the
-// wave alone: LDS operations of one wave complete in issue order, so the only synchronisation
-// between classes is this compiler-level fence, and no workgroup barrier is executed after the
-// records are staged. In the Tile, lcol/ncol count the columns of one wave's block and `lane`
-// indexes tasks.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Acceptance entries of sweep t for the wave's block (block index rb_sel of the tile).
-template <bool GR, bool MET>
-__device__ __forceinline__ void accept_bits_wave(const Tile &T, uint32_t t, uint32_t rb) {
-    for (uint32_t p = T.lane; p < T.n; p += 64) {
-        const uint32_t i = (rec_at<GR>(T, p).w >> 16) & 0x1FFFu;
-        const uint4 o = philox10(make_uint4(i, t, T.blk0 + T.rb_sel, T.iid), T.key0, T.key1);
-        const uint32_t q = (p << T.lB) + T.rb_sel;
-        if constexpr (MET)
-            *reinterpret_cast<uint16_t *>(xs_lds + rb + 2 * q) =
-                (uint16_t)(draws_below(o, T.thr) | draws_below(o, T.thr0) << 8);
-        else
-            xs_lds[rb + q] = (uint8_t)draws_below(o, T.thr);
-    }
-}
-
-// One sweep of the wave's block: the classes in order, tasks over the wave's lanes. The next
-// class's descriptor and first record (read-only) are fetched while the current class runs.
-template <int CW, bool GR, bool kAcc, bool MET>
-__device__ __forceinline__ void sweep_wave(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
-    uint32_t cd = __builtin_amdgcn_readfirstlane(lds_u32(T.cls));
-    uint32_t p0 = (cd & 0xFFFFu) + (T.lane >> T.lcol);
-    uint4 r0;  // read only by lanes with a task
-    if (T.lane < ((cd >> 16) << T.lcol)) r0 = rec_at<GR>(T, p0);
-    for (uint32_t c = 0; c < T.ncls; ++c) {
-        const uint32_t cs = cd & 0xFFFFu;
-        const uint32_t ntask = (cd >> 16) << T.lcol;
-        const uint4 r = r0;
-        const uint32_t p = p0;
-        if (c + 1 < T.ncls) {
-            cd = __builtin_amdgcn_readfirstlane(lds_u32(T.cls + 4 * (c + 1)));
-            p0 = (cd & 0xFFFFu) + (T.lane >> T.lcol);
-            if (T.lane < ((cd >> 16) << T.lcol)) r0 = rec_at<GR>(T, p0);
-        }
-        if (T.lane < ntask) update_task<CW, kAcc, MET>(T, r, p, rb, acc);
-        const uint32_t rounds = (ntask - 1) >> 6;
-        for (uint32_t k = 1; k <= rounds; ++k) {
-            const uint32_t q = T.lane + 64 * k;
-            if (q < ntask) {
-                const uint32_t pq = cs + (q >> T.lcol);
-                update_task<CW, kAcc, MET>(T, rec_at<GR>(T, pq), pq, rb, acc);
-            }
-        }
-        wave_sync();
-    }
-}
-
-// k >= 1 over every spin of the wave's block in its current state (no update).
-template <int CW, bool GR>
-__device__ __forceinline__ void unsat_any_wave(const Tile &T, uint32_t (&acc)[CW / 4]) {
-    constexpr int G = CW / 4;
-    for (uint32_t q = T.lane; q < T.n << T.lcol; q += 64) {
-        const uint4 r = rec_at<GR>(T, q >> T.lcol);
-        uint32_t x[G], a1[G], b1[G], a2[G], b2[G], a3[G], b3[G];
-        col_load<CW>(T.colbase + (r.x & 0xFFFFu), x);
-        col_load<CW>(T.colbase + (r.x >> 16), a1);
-        col_load<CW>(T.colbase + (r.y & 0xFFFFu), b1);
-        col_load<CW>(T.colbase + (r.y >> 16), a2);
-        col_load<CW>(T.colbase + (r.z & 0xFFFFu), b2);
-        col_load<CW>(T.colbase + (r.z >> 16), a3);
-        col_load<CW>(T.colbase + (r.w & 0xFFFFu), b3);
-        const uint32_t meta = r.w >> 16;
-        const uint32_t j1 = 0u - ((meta >> 13) & 1u);
-        const uint32_t j2 = 0u - ((meta >> 14) & 1u);
-        const uint32_t j3 = 0u - (meta >> 15);
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-            qg_word<true>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3, 0u, acc[g]);
-    }
-}
-
-// OR the lanes' accumulators per column (lanes lane, lane + ncol, ... share a column), then
-// lanes below ncol record first hits at sweep t for their G groups: a zero bit of a group's OR
-// marks a clone in a ground state. hm[g] holds the group's clones with a hit already. Returns
-// nonzero in every lane if some clone of the block got a new hit.
-template <int CW>
-__device__ __forceinline__ uint32_t wave_hits(const Tile &T, uint32_t t, uint32_t (&acc)[CW / 4],
-                                              uint32_t (&hm)[CW / 4]) {
-    constexpr int G = CW / 4;
-    for (uint32_t m = T.ncol; m < 64; m <<= 1)
-        for (int g = 0; g < G; ++g) acc[g] |= __shfl_xor(acc[g], (int)m);
-    uint32_t any = 0;
-    if (T.lane < T.ncol) {
-        for (int g = 0; g < G; ++g) {
-            uint32_t fresh = ~acc[g] & ~hm[g];
-            if (fresh) {
-                const uint32_t grp = (T.blk0 + T.rb_sel) * 8 + T.rb_shift + g;
-                int32_t *fh = T.I->first_hit + ((size_t)grp << 5);
-                hm[g] |= fresh;
-                any = 1;
-                while (fresh) {
-                    fh[__builtin_ctz(fresh)] = (int32_t)t;
-                    fresh &= fresh - 1;
-                }
-            }
-        }
-        if (any) atomicOr(const_cast<uint32_t *>(&T.I->hit), 1u);
-    }
-    return __ballot(any) != 0;
-}
-
-template <int CW, bool GR>
-__device__ __forceinline__ uint32_t check_state_wave(const Tile &T, uint32_t t,
-                                                     uint32_t (&hm)[CW / 4]) {
-    uint32_t acc[CW / 4] = {};
-    wave_sync();
-    unsat_any_wave<CW, GR>(T, acc);
-    return wave_hits<CW>(T, t, acc, hm);
-}
-
-// The wave's block rows, global <-> LDS (32 bytes per spin row).
-__device__ __forceinline__ void load_state_wave(const Tile &T) {
-    const uint4 *src0 =
-        reinterpret_cast<const uint4 *>(T.I->state + 4 * (size_t)(T.blk0 + T.rb_sel));
-    for (uint32_t q = T.lane; q < 2 * T.n; q += 64) {
-        const uint32_t i = q >> 1, k = q & 1;
-        *reinterpret_cast<uint4 *>(xs_lds + T.st + i * T.rowb + 32 * T.rb_sel + 16 * k) =
-            (src0 + ((size_t)i * T.W >> 1))[k];
-    }
-}
-__device__ __forceinline__ void store_state_wave(const Tile &T) {
-    uint4 *dst0 = reinterpret_cast<uint4 *>(T.I->state + 4 * (size_t)(T.blk0 + T.rb_sel));
-    for (uint32_t q = T.lane; q < 2 * T.n; q += 64) {
-        const uint32_t i = q >> 1, k = q & 1;
-        (dst0 + ((size_t)i * T.W >> 1))[k] = *reinterpret_cast<const uint4 *>(
-            xs_lds + T.st + i * T.rowb + 32 * T.rb_sel + 16 * k);
-    }
-}
-
-// Hit masks of the lane's groups from first_hit: a clone counts as hit if fh is in [0, below).
-template <int CW>
-__device__ __forceinline__ void wave_hit_masks(const Tile &T, uint32_t below,
-                                               uint32_t (&hm)[CW / 4]) {
-    for (int g = 0; g < CW / 4; ++g) {
-        hm[g] = 0;
-        if (T.lane < T.ncol) {
-            const uint32_t grp = (T.blk0 + T.rb_sel) * 8 + T.rb_shift + g;
-            const int32_t *fh = T.I->first_hit + ((size_t)grp << 5);
-            for (int b = 0; b < 32; ++b)
-                hm[g] |= (fh[b] >= 0 && (uint32_t)fh[b] < below ? 1u : 0u) << b;
-        }
-    }
-}
-
-// The same chunk semantics as qg_chunk (start check, fast loop with end check and replay,
-// tracking mode, w0 rule), per wave.
-template <int NT, int CW, bool GR, bool MET>
-__global__ __launch_bounds__(NT) void qg_chunk_wave(const InstDev *__restrict__ insts,
-                                                    const uint2 *__restrict__ tiles) {
-    constexpr int G = CW / 4;
-    constexpr int LG = G == 4 ? 2 : G == 2 ? 1 : 0;
-    const uint2 tile = tiles[blockIdx.x];
-    const InstDev *I = insts + tile.x;
-    if (I->done) return;
-    const uint32_t t0 = I->t_cur;
-    const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
-    if (t0 >= t1) return;
-
-    if (I->tile_blocks * 64 != NT) return;  // the host launches NT = 64 * tile_blocks only
-    Tile T;
-    T.I = I;
-    T.n = I->n;
-    T.W = I->n_words;
-    T.B = I->tile_blocks;
-    T.lB = I->log2_tile_blocks;
-    T.rowb = T.B << 5;
-    T.tid = threadIdx.x;
-    T.lane = T.tid & 63;
-    T.lcol = 3 - LG;  // columns of one block
-    T.ncol = 1u << T.lcol;
-    T.col = (T.tid >> 6) * T.ncol + (T.lane & (T.ncol - 1));
-    T.blk0 = tile.y;
-    T.grec = I->grec;
-    T.st = GR ? 0u : (uint32_t)lds_rec_bytes(T.n);
-    const uint32_t rbb = (uint32_t)align16((size_t)T.n * T.B * (MET ? 2 : 1));
-    T.rb0 = T.st + T.n * T.rowb;
-    T.rb1 = T.rb0 + rbb;
-    T.cls = T.rb1 + rbb;
-    T.colbase = T.st + T.col * CW;
-    T.rb_sel = (T.col << LG) >> 3;   // = the wave's block
-    T.rb_shift = (T.col << LG) & 7;  // first group of the lane's column in its block
-    T.thr = I->thr;
-    T.thr0 = I->thr0;
-    T.key0 = I->seed_lo;
-    T.key1 = I->seed_hi;
-    T.iid = I->inst_id;
-    T.ncls = I->n_classes;
-    for (uint32_t c = T.tid; c < T.ncls; c += NT) {
-        const uint32_t a = (uint32_t)I->class_off[c], b = (uint32_t)I->class_off[c + 1];
-        lds_u32(T.cls + 4 * c) = a | ((b - a) << 16);
-    }
-    for (uint32_t p = T.tid; !GR && p < T.n; p += NT) {
-        const uint4 r = I->rec[p];
-        const uint32_t rowb = T.rowb;
-        const uint32_t i = r.x & 0xFFFFu;
-        uint4 o;
-        o.x = (i * rowb) | (((r.x >> 16) * rowb) << 16);
-        o.y = ((r.y & 0xFFFFu) * rowb) | (((r.y >> 16) * rowb) << 16);
-        o.z = ((r.z & 0xFFFFu) * rowb) | (((r.z >> 16) * rowb) << 16);
-        o.w = ((r.w & 0xFFFFu) * rowb) | ((i | ((r.w >> 16) << 13)) << 16);
-        lds_rec(p) = o;
-    }
-    load_state_wave(T);
-    __syncthreads();  // records and class table shared by the waves; from here on waves are independent
-
-    if constexpr (MET) {
-        uint32_t none[G] = {};
-        for (uint32_t t = t0; t < t1; ++t) {
-            accept_bits_wave<GR, true>(T, t, T.rb0);
-            wave_sync();
-            sweep_wave<CW, GR, false, true>(T, T.rb0, none);
-        }
-        store_state_wave(T);
-        return;
-    }
-    uint32_t hm[G];
-    wave_hit_masks<CW>(T, 0xFFFFFFFFu, hm);
-    if (t0 == I->t_start) check_state_wave<CW, GR>(T, t0, hm);  // the run's start configuration
-
-    if (I->track) {
-        for (uint32_t t = t0; t < t1; ++t) {
-            uint32_t acc[G] = {};
-            accept_bits_wave<GR, false>(T, t, T.rb0);
-            wave_sync();
-            sweep_wave<CW, GR, true, false>(T, T.rb0, acc);
-            wave_hits<CW>(T, t, acc, hm);
-        }
-        check_state_wave<CW, GR>(T, t1, hm);
-    } else {
-        uint32_t none[G] = {};
-        for (uint32_t t = t0; t < t1; ++t) {
-            accept_bits_wave<GR, false>(T, t, T.rb0);
-            wave_sync();
-            sweep_wave<CW, GR, false, false>(T, T.rb0, none);
-        }
-        if (check_state_wave<CW, GR>(T, t1, hm)) {
-            // Replay the wave's block from the chunk's start state with a per-sweep test.
-            uint32_t hm_replay[G];
-            wave_hit_masks<CW>(T, t1, hm_replay);
-            wave_sync();
-            load_state_wave(T);
-            for (uint32_t t = t0; t < t1; ++t) {
-                uint32_t acc[G] = {};
-                accept_bits_wave<GR, false>(T, t, T.rb0);
-                wave_sync();
-                sweep_wave<CW, GR, true, false>(T, T.rb0, acc);
-                wave_hits<CW>(T, t, acc, hm_replay);
-            }
-            if (T.lane == 0) atomicOr(const_cast<uint32_t *>(&I->track), 1u);
-        }
-    }
-    wave_sync();
-    store_state_wave(T);
-}
-
 // ------------------------------------------------------------------------------ control
 
 // After a chunk: advance every unfinished instance, end it at the budget or (stop-on-first)
@@ -887,85 +619,62 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NT, int CW, bool GR, bool MET, bool WV>
+template <int NT, int CW, bool GR, bool MET>
 hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            size_t lds_bytes, hipStream_t s) {
-    const void *fn = WV ? reinterpret_cast<const void *>(qg_chunk_wave<NT, CW, GR, MET>)
-                        : reinterpret_cast<const void *>(qg_chunk<NT, CW, GR, MET>);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e =
-            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(qg_chunk<NT, CW, GR, MET>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    if constexpr (WV)
-        hipLaunchKernelGGL((qg_chunk_wave<NT, CW, GR, MET>), dim3(n_tiles), dim3(NT), lds_bytes,
-                           s, d_insts, d_tiles);
-    else
-        hipLaunchKernelGGL((qg_chunk<NT, CW, GR, MET>), dim3(n_tiles), dim3(NT), lds_bytes, s,
-                           d_insts, d_tiles);
+    hipLaunchKernelGGL((qg_chunk<NT, CW, GR, MET>), dim3(n_tiles), dim3(NT), lds_bytes, s,
+                       d_insts, d_tiles);
     return hipGetLastError();
 }
 
-template <int CW, bool GR, bool MET, bool WV>
+template <int CW, bool GR, bool MET>
 hipError_t launch_chunk_cw(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            int threads, size_t lds_bytes, hipStream_t s) {
     switch (threads) {
-        case 64:
-            return launch_chunk_nt<64, CW, GR, MET, WV>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 128:
-            return launch_chunk_nt<128, CW, GR, MET, WV>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 256:
-            return launch_chunk_nt<256, CW, GR, MET, WV>(d_insts, d_tiles, n_tiles, lds_bytes, s);
-        case 512:
-            return launch_chunk_nt<512, CW, GR, MET, WV>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 64: return launch_chunk_nt<64, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 128: return launch_chunk_nt<128, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 256: return launch_chunk_nt<256, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
+        case 512: return launch_chunk_nt<512, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
         case 1024:
-            return launch_chunk_nt<1024, CW, GR, MET, WV>(d_insts, d_tiles, n_tiles, lds_bytes,
-                                                          s);
+            return launch_chunk_nt<1024, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <bool GR, bool MET, bool WV>
+template <bool GR, bool MET>
 hipError_t launch_chunk_gr(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            int threads, int col_bytes, size_t lds_bytes, hipStream_t s) {
     switch (col_bytes) {
         case 4:
-            return launch_chunk_cw<4, GR, MET, WV>(d_insts, d_tiles, n_tiles, threads, lds_bytes,
-                                                   s);
+            return launch_chunk_cw<4, GR, MET>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
         case 8:
-            return launch_chunk_cw<8, GR, MET, WV>(d_insts, d_tiles, n_tiles, threads, lds_bytes,
-                                                   s);
+            return launch_chunk_cw<8, GR, MET>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
         case 16:
-            return launch_chunk_cw<16, GR, MET, WV>(d_insts, d_tiles, n_tiles, threads,
-                                                    lds_bytes, s);
+            return launch_chunk_cw<16, GR, MET>(d_insts, d_tiles, n_tiles, threads, lds_bytes, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <bool MET, bool WV>
-hipError_t launch_chunk_met(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
-                            int threads, int col_bytes, bool rec_global, size_t lds_bytes,
-                            hipStream_t s) {
-    return rec_global ? launch_chunk_gr<true, MET, WV>(d_insts, d_tiles, n_tiles, threads,
-                                                       col_bytes, lds_bytes, s)
-                      : launch_chunk_gr<false, MET, WV>(d_insts, d_tiles, n_tiles, threads,
-                                                        col_bytes, lds_bytes, s);
-}
-
 hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        int col_bytes, bool rec_global, bool met, bool wave, size_t lds_bytes,
+                        int col_bytes, bool rec_global, bool met, size_t lds_bytes,
                         hipStream_t s) {
-    if (wave)
-        return met ? launch_chunk_met<true, true>(d_insts, d_tiles, n_tiles, threads, col_bytes,
-                                                  rec_global, lds_bytes, s)
-                   : launch_chunk_met<false, true>(d_insts, d_tiles, n_tiles, threads, col_bytes,
-                                                   rec_global, lds_bytes, s);
-    return met ? launch_chunk_met<true, false>(d_insts, d_tiles, n_tiles, threads, col_bytes,
-                                               rec_global, lds_bytes, s)
-               : launch_chunk_met<false, false>(d_insts, d_tiles, n_tiles, threads, col_bytes,
-                                                rec_global, lds_bytes, s);
+    if (met)
+        return rec_global ? launch_chunk_gr<true, true>(d_insts, d_tiles, n_tiles, threads,
+                                                        col_bytes, lds_bytes, s)
+                          : launch_chunk_gr<false, true>(d_insts, d_tiles, n_tiles, threads,
+                                                         col_bytes, lds_bytes, s);
+    return rec_global ? launch_chunk_gr<true, false>(d_insts, d_tiles, n_tiles, threads,
+                                                     col_bytes, lds_bytes, s)
+                      : launch_chunk_gr<false, false>(d_insts, d_tiles, n_tiles, threads,
+                                                      col_bytes, lds_bytes, s);
 }
 
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s) {

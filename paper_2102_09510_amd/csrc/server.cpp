@@ -145,13 +145,10 @@ struct xs_server {
                 ++k;
                 continue;
             }
-            xs_run_result res{};
-            res.tts_sweeps = -1;
-            res.winner_clone = -1;
-            res.end_sweep = r->desc.t_cur;
-            res.sweeps_done = r->desc.t_cur - r->desc.t_start;
-            res.clone_spin_updates =
-                (uint64_t)r->desc.n_words * 64 * r->desc.n * (r->desc.t_cur - r->desc.t_start);
+            xs_run_result res{-1, -1, r->desc.t_cur, r->desc.t_cur - r->desc.t_start, 0, 0, 0, 0,
+                              (uint64_t)r->desc.n_words * 64 * r->desc.n *
+                                  (r->desc.t_cur - r->desc.t_start),
+                              0};
             release(r);
             complete(r, XS_ECANCELED, res);
             delete r;
@@ -195,8 +192,8 @@ struct xs_server {
                 }
             for (const xsh::TileGroup &g : groups)
                 XS_HIP(xs::launch_chunk(d_inst, d_tiles + g.first, (int)g.count, (int)g.threads,
-                                        (int)g.col_bytes, g.rec_global != 0, g.met != 0,
-                                        g.wave != 0, g.lds, stream));
+                                        (int)g.col_bytes, g.rec_global != 0, g.met != 0, g.lds,
+                                        stream));
             XS_HIP(xs::launch_decide(d_inst, R, d_active, stream));
             XS_HIP(hipMemcpyAsync(h.data(), d_inst, sizeof(xs::InstDev) * R,
                                   hipMemcpyDeviceToHost, stream));
@@ -233,7 +230,6 @@ struct xs_server {
                 res.wg_threads = d.wg_threads;
                 res.col_bytes = d.col_bytes;
                 res.rec_global = d.rec_global;
-                res.wave_tiles = d.wave;
                 res.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * res.sweeps_done;
                 const size_t n = d.n, nc = (size_t)d.n_words * 64;
                 if (r->outs.state)

@@ -59,7 +59,7 @@ void fill_desc(const xs_instance *I, const xs_run_config &c, const DeviceTables 
 
 // One chunk launch per workgroup size over a list of tiles.
 struct TileGroup {
-    uint32_t threads, col_bytes, rec_global, met, wave;
+    uint32_t threads, col_bytes, rec_global, met;
     size_t first, count, lds;
 };
 // Point every descriptor that reads its records from global memory at its instance's table for

@@ -38,8 +38,6 @@ struct InstDev {
     uint32_t col_bytes;   // task column width of this instance's launches (host side)
     uint32_t rec_global;  // records read from global memory (host side: selects the kernel)
     uint32_t thr0;        // w0 threshold: k = 0 spins flip iff the draw is below it (0: never)
-    uint32_t wave;        // wave-private tiles (host side: selects the kernel)
-    uint32_t pad;
 };
 
 }  // namespace xs
@@ -50,10 +48,9 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, hipStream_t
 // threads: 64, 128, 256, 512 or 1024, at least 8 * tile_blocks of every tile it runs;
 // col_bytes: 4, 8 or 16 bytes of a spin row per task; rec_global: every tile's instance has
 // grec set (records in global memory), else records are staged in LDS; met: every tile's
-// instance has thr0 > 0 (w0 rule, no ground-state tracking); wave: wave-private tiles, every
-// tile's instance has tile_blocks == threads / 64.
+// instance has thr0 > 0 (w0 rule, no ground-state tracking).
 hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
-                        int col_bytes, bool rec_global, bool met, bool wave, size_t lds_bytes,
+                        int col_bytes, bool rec_global, bool met, size_t lds_bytes,
                         hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
 hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);

@@ -31,7 +31,7 @@ EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_crea
            "xs_autotune", "xs_tune_save", "xs_tune_load", "xs_tune_clear",
            "xs_server_create", "xs_server_destroy", "xs_server_submit", "xs_server_step",
            "xs_server_poll", "xs_server_cancel", "xs_server_get_stats"]
-XS_TUNE_MAX_TRIALS = 96
+XS_TUNE_MAX_TRIALS = 64
 
 
 class XsError(RuntimeError):
@@ -48,7 +48,7 @@ class RunConfig(ctypes.Structure):
                 ("chunk_sweeps", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
                 ("wg_threads", ctypes.c_uint32), ("col_bytes", ctypes.c_uint32),
                 ("rec_global", ctypes.c_uint32), ("accept_thr0", ctypes.c_uint32),
-                ("wave_tiles", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32)]
 
 
 class RunBuffers(ctypes.Structure):
@@ -61,7 +61,6 @@ class RunResult(ctypes.Structure):
                 ("end_sweep", ctypes.c_uint32), ("sweeps_done", ctypes.c_uint32),
                 ("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
                 ("col_bytes", ctypes.c_uint32), ("rec_global", ctypes.c_uint32),
-                ("wave_tiles", ctypes.c_uint32),
                 ("clone_spin_updates", ctypes.c_uint64), ("seconds", ctypes.c_double)]
 
 
@@ -73,13 +72,12 @@ class KernelStats(ctypes.Structure):
 class TuneTrial(ctypes.Structure):
     _fields_ = [("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
                 ("col_bytes", ctypes.c_uint32), ("rec_global", ctypes.c_uint32),
-                ("wave_tiles", ctypes.c_uint32), ("updates_per_ns", ctypes.c_double)]
+                ("updates_per_ns", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
                 ("col_bytes", ctypes.c_uint32), ("rec_global", ctypes.c_uint32),
-                ("wave_tiles", ctypes.c_uint32),
                 ("updates_per_ns", ctypes.c_double), ("n_trials", ctypes.c_int32),
                 ("trials", TuneTrial * XS_TUNE_MAX_TRIALS)]
 
@@ -227,7 +225,6 @@ class RunOutput:
     wg_threads: int
     col_bytes: int
     rec_global: int
-    wave_tiles: int
     clone_spin_updates: int
     seconds: float
     state: object        # torch int64 [n][n_clones/64] on the device
@@ -240,13 +237,13 @@ def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: i
                 max_sweeps: int = 100000, stop_on_first: bool = True, resume: bool = False,
                 start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0,
                 wg_threads: int = 0, col_bytes: int = 0, rec_global: int = 0,
-                accept_thr0: int = 0, wave_tiles: int = 0) -> RunConfig:
+                accept_thr0: int = 0) -> RunConfig:
     """accept_thr0 > 0 selects the rule with w0 = accept_thr0 / 65536 (no ground-state
     tracking: first_hit marks only clones whose end configuration is a ground state)."""
     flags = (XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0)
     return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
                      accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks,
-                     wg_threads, col_bytes, rec_global, accept_thr0, wave_tiles)
+                     wg_threads, col_bytes, rec_global, accept_thr0, 0)
 
 
 def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
@@ -268,8 +265,8 @@ def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
 def _output(res: RunResult, state, first_hit, energy, solved) -> RunOutput:
     return RunOutput(int(res.tts_sweeps), int(res.winner_clone), int(res.end_sweep),
                      int(res.sweeps_done), int(res.tile_blocks), int(res.wg_threads),
-                     int(res.col_bytes), int(res.rec_global), int(res.wave_tiles),
-                     int(res.clone_spin_updates), float(res.seconds), state, first_hit, energy,
+                     int(res.col_bytes), int(res.rec_global), int(res.clone_spin_updates),
+                     float(res.seconds), state, first_hit, energy,
                      solved if res.winner_clone >= 0 else None)
 
 
@@ -316,17 +313,16 @@ def profile_read(reset: bool = False) -> dict:
 
 
 def autotune(inst: Instance, n_clones: int, count: int = 1) -> dict:
-    """Time every valid launch-knob combination (tile_blocks, wg_threads, col_bytes,
-    rec_global, wave_tiles) for `count` instances like `inst` and record the fastest for later
-    runs that leave all knobs at 0."""
+    """Time every valid (tile_blocks, wg_threads) pair for `count` instances like `inst` and
+    record the fastest for later runs that leave both knobs at 0."""
     res = TuneResult()
     _check(load().xs_autotune(inst.handle, n_clones, count, _stream(), ctypes.byref(res)))
     trials = [(res.trials[k].tile_blocks, res.trials[k].wg_threads, res.trials[k].col_bytes,
-               res.trials[k].rec_global, res.trials[k].wave_tiles, res.trials[k].updates_per_ns)
+               res.trials[k].rec_global, res.trials[k].updates_per_ns)
               for k in range(res.n_trials)]
     return dict(tile_blocks=res.tile_blocks, wg_threads=res.wg_threads,
                 col_bytes=res.col_bytes, rec_global=res.rec_global,
-                wave_tiles=res.wave_tiles, updates_per_ns=res.updates_per_ns, trials=trials)
+                updates_per_ns=res.updates_per_ns, trials=trials)
 
 
 def tune_save(path: str):

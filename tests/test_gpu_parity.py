@@ -66,14 +66,13 @@ def assert_parity(inst, h, cfg, out, clones=None, init_spins=None):
 
 
 def run_and_check_full(n, seed, n_clones, *, max_sweeps, stop=True, chunk=0, tile_blocks=0,
-                       thr=THR_PAPER, cap=32, iid=3, wave=0, col_bytes=0, rec_global=0):
+                       thr=THR_PAPER, cap=32, iid=3):
     _torch()
     inst = planted_instance(n, seed)
     h = xorsat.Instance(inst.tri, inst.J, colour_cap=cap)
     cfg = xorsat.make_config(n_clones=n_clones, seed=seed * 7 + 1, instance_id=iid,
                              accept_thr=thr, max_sweeps=max_sweeps, stop_on_first=stop,
-                             chunk_sweeps=chunk, tile_blocks=tile_blocks, wave_tiles=wave,
-                             col_bytes=col_bytes, rec_global=rec_global)
+                             chunk_sweeps=chunk, tile_blocks=tile_blocks)
     out = xorsat.run(h, cfg)
     ref = assert_parity(inst, h, cfg, out)
     tts, winner = oracle.solve_results(ref["first_hit"])
@@ -84,27 +83,12 @@ def run_and_check_full(n, seed, n_clones, *, max_sweeps, stop=True, chunk=0, til
     return inst, h, cfg, out
 
 
-@pytest.mark.parametrize("wave", [2, 1])
-def test_small_instance_full_parity_to_first_ground_state(wave):
+def test_small_instance_full_parity_to_first_ground_state():
     """N = 64, 1024 clones, stop at the first ground state (the single-instance workload):
-    every clone, every output, TTS and winner; both block schedules."""
-    inst, h, cfg, out = run_and_check_full(64, 1000001, 1024, max_sweeps=100000, wave=wave)
+    every clone, every output, TTS and winner."""
+    inst, h, cfg, out = run_and_check_full(64, 1000001, 1024, max_sweeps=100000)
     assert out.tts_sweeps >= 0
-    assert out.wave_tiles == (wave == 1)
     assert out.end_sweep % 100 == 0 or out.end_sweep == 100000
-
-
-@pytest.mark.parametrize("n,clones,B,C,G,chunk,sweeps,stop", [
-    (100, 4096, 2, 8, 2, 7, 40, False),    # ragged classes, 8 tiles
-    (48, 2048, 1, 4, 1, 13, 3000, False),  # budget run with many ground states (replays)
-    (37, 1024, 4, 16, 2, 5, 5000, True),   # odd N, stop at the first ground state
-    (257, 2048, 4, 16, 1, 9, 20, False),   # N just above 256, four waves
-])
-def test_wave_tiles_every_clone(n, clones, B, C, G, chunk, sweeps, stop):
-    """One block per wave: every clone against the oracle, including chunks with new ground
-    states (end-of-chunk test and replay) and the tracking mode that follows."""
-    run_and_check_full(n, 600 + n, clones, max_sweeps=sweeps, stop=stop, chunk=chunk,
-                       tile_blocks=B, wave=1, col_bytes=C, rec_global=G)
 
 
 @pytest.mark.parametrize("n,clones,B,chunk,sweeps", [
@@ -135,25 +119,14 @@ def test_tiling_is_result_neutral():
     inst = planted_instance(128, 9)
     h = xorsat.Instance(inst.tri, inst.J)
     outs = []
-    for B, T, C, G, V in ((1, 0, 0, 0, 2), (2, 0, 0, 0, 2), (4, 0, 0, 0, 2), (8, 0, 0, 0, 2),
-                          (16, 0, 0, 0, 2), (1, 64, 16, 2, 2), (2, 128, 16, 1, 2),
-                          (4, 1024, 16, 2, 2), (8, 256, 16, 1, 2), (16, 256, 16, 2, 2),
-                          (1, 256, 4, 1, 2), (1, 64, 8, 2, 2), (2, 256, 4, 1, 2),
-                          (4, 256, 8, 1, 2), (16, 128, 4, 1, 2), (8, 512, 8, 2, 2),
-                          # one block per wave
-                          (1, 64, 16, 2, 1), (2, 128, 8, 1, 1), (4, 256, 16, 2, 1),
-                          (8, 512, 4, 1, 1), (16, 1024, 16, 2, 1), (4, 0, 8, 2, 1),
-                          (0, 0, 0, 0, 1)):
+    for B, T, C, G in ((1, 0, 0, 0), (2, 0, 0, 0), (4, 0, 0, 0), (8, 0, 0, 0), (16, 0, 0, 0),
+                       (1, 64, 16, 2), (2, 128, 16, 1), (4, 1024, 16, 2), (8, 256, 16, 1),
+                       (16, 256, 16, 2), (1, 256, 4, 1), (1, 64, 8, 2), (2, 256, 4, 1),
+                       (4, 256, 8, 1), (16, 128, 4, 1), (8, 512, 8, 2)):
         cfg = xorsat.make_config(n_clones=8192, seed=99, instance_id=1, max_sweeps=300,
                                  stop_on_first=False, tile_blocks=B, chunk_sweeps=64,
-                                 wg_threads=T, col_bytes=C, rec_global=G, wave_tiles=V)
+                                 wg_threads=T, col_bytes=C, rec_global=G)
         out = xorsat.run(h, cfg)
-        assert out.wave_tiles == (V == 1)
-        if V == 1:
-            assert out.wg_threads == 64 * out.tile_blocks
-        if not B:
-            outs.append(out)
-            continue
         if G:
             assert out.rec_global == (G == 1)
         assert out.tile_blocks == B and out.wg_threads == (T or out.wg_threads)
@@ -277,16 +250,14 @@ def _w_thresholds(T):
     return round(math.exp(-2.0 / T) * 65536), round(math.exp(-6.0 / T) * 65536)
 
 
-@pytest.mark.parametrize("n,clones,B,T,C,G,chunk,sweeps,thr,thr0,V", [
-    (100, 4096, 2, 0, 0, 0, 7, 40, *_w_thresholds(1.0), 0),     # ragged classes, 8 tiles
-    (37, 2048, 0, 0, 0, 0, 0, 33, THR_PAPER, 20000, 0),          # odd N, large w0, one chunk
-    (257, 1024, 1, 64, 8, 1, 5, 23, *_w_thresholds(0.69), 0),    # global records, narrow cols
-    (128, 8192, 4, 256, 4, 2, 16, 50, 65536, 65536, 0),          # every spin flips each visit
-    (4, 256, 1, 0, 0, 0, 1, 9, 30000, 1, 0),                     # smallest case
-    (100, 4096, 4, 256, 16, 2, 7, 40, *_w_thresholds(1.0), 1),   # one block per wave
-    (257, 2048, 2, 128, 4, 1, 5, 23, *_w_thresholds(0.69), 1),
+@pytest.mark.parametrize("n,clones,B,T,C,G,chunk,sweeps,thr,thr0", [
+    (100, 4096, 2, 0, 0, 0, 7, 40, *_w_thresholds(1.0)),     # ragged classes, 8 tiles
+    (37, 2048, 0, 0, 0, 0, 0, 33, THR_PAPER, 20000),          # odd N, large w0, one chunk
+    (257, 1024, 1, 64, 8, 1, 5, 23, *_w_thresholds(0.69)),    # global records, narrow columns
+    (128, 8192, 4, 256, 4, 2, 16, 50, 65536, 65536),          # every spin flips each visit
+    (4, 256, 1, 0, 0, 0, 1, 9, 30000, 1),                     # smallest case
 ])
-def test_metropolis_budget_runs(n, clones, B, T, C, G, chunk, sweeps, thr, thr0, V):
+def test_metropolis_budget_runs(n, clones, B, T, C, G, chunk, sweeps, thr, thr0):
     """w0 > 0: every clone's end configuration, energy and end-only ground-state mark equal the
     oracle's."""
     _torch()
@@ -295,7 +266,7 @@ def test_metropolis_budget_runs(n, clones, B, T, C, G, chunk, sweeps, thr, thr0,
     cfg = xorsat.make_config(n_clones=clones, seed=n * 3 + 1, instance_id=5, accept_thr=thr,
                              accept_thr0=thr0, max_sweeps=sweeps, stop_on_first=False,
                              chunk_sweeps=chunk, tile_blocks=B, wg_threads=T, col_bytes=C,
-                             rec_global=G, wave_tiles=V)
+                             rec_global=G)
     out = xorsat.run(h, cfg)
     ref = assert_parity(inst, h, cfg, out)
     assert set(np.unique(ref["first_hit"])) <= {-1, sweeps}

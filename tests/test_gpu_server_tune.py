@@ -127,19 +127,16 @@ def test_autotune_is_result_neutral():
     try:
         res = xorsat.autotune(h, 8192, count=4)
         assert res["updates_per_ns"] > 0 and len(res["trials"]) >= 4
-        assert (res["tile_blocks"], res["wg_threads"], res["col_bytes"], res["rec_global"],
-                res["wave_tiles"]) in [(b, t, c, g, v) for b, t, c, g, v, _ in res["trials"]]
-        assert {v for *_, v, _ in res["trials"]} == {1, 2}  # both schedules were timed
+        assert (res["tile_blocks"], res["wg_threads"], res["col_bytes"], res["rec_global"]) in \
+            [(b, t, c, g) for b, t, c, g, _ in res["trials"]]
         cfgs = [xorsat.make_config(n_clones=8192, seed=5 + k, instance_id=k, max_sweeps=120,
                                    stop_on_first=False, chunk_sweeps=40) for k in range(4)]
         tuned = xorsat.run_batch([h] * 4, cfgs)
         assert all((o.tile_blocks, o.wg_threads, o.col_bytes) ==
                    (res["tile_blocks"], res["wg_threads"], res["col_bytes"]) for o in tuned)
         assert all(o.rec_global == (res["rec_global"] == 1) for o in tuned)
-        assert all(o.wave_tiles == (res["wave_tiles"] == 1) for o in tuned)
         for k, c in enumerate(cfgs):
             c.tile_blocks, c.wg_threads, c.col_bytes, c.rec_global = 1, 64, 16, 2
-            c.wave_tiles = 2
         plain = xorsat.run_batch([h] * 4, cfgs)
         for a, b in zip(tuned, plain):
             assert torch.equal(a.state, b.state)
