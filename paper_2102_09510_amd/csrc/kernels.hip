@@ -144,6 +144,15 @@ __global__ __launch_bounds__(256) void qg_init(InstDev *I) {
 // keeps them all as ds_* instructions.
 extern __shared__ __align__(16) uint8_t xs_lds[];
 
+// Address space of read-only global data that uniform accesses load through the scalar cache.
+#define CONSTANT __attribute__((address_space(4)))
+// LDS address space: an integer LDS address used as a pointer, so that a uniform base folds
+// into scalar arithmetic.
+#define LDS_AS __attribute__((address_space(3)))
+__device__ __forceinline__ uint32_t lds_base() {
+    return (uint32_t)(uintptr_t)(LDS_AS uint8_t *)xs_lds;
+}
+
 // Per-workgroup view of one tile. LDS locations are byte offsets into xs_lds. A task is one
 // spin of the current class and one column of CW bytes of the tile's rows (CW / 4 groups of 32
 // clones); `col` is this thread's column, fixed because the workgroup size is a multiple of the
@@ -159,7 +168,10 @@ struct Tile {
     uint32_t colbase;    // st + this thread's column
     uint32_t rb_sel, rb_shift;
     uint32_t thr, thr0, key0, key1, iid, ncls;
-    uint32_t cls;        // per class: first position | size << 16 (uint32 each)
+    uint32_t tpos;       // this thread's first task position in a class (tid >> lcol)
+    uint32_t rbo;        // its acceptance entry index relative to the class start
+    const int32_t *class_off;
+    uint32_t lds0;       // absolute LDS address of xs_lds
 };
 
 __device__ __forceinline__ uint4 &lds_rec(uint32_t p) {
@@ -219,9 +231,10 @@ __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t 
     }
 }
 
-// One task: the spin whose record is r (position p), this thread's column.
+// One task: the spin whose record is r, this thread's column; ra is the absolute LDS address of
+// the acceptance entry of the spin's position and the column's block.
 template <int CW, bool kAcc, bool MET>
-__device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, uint32_t rb,
+__device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
                                             uint32_t (&acc)[CW / 4]) {
     constexpr int G = CW / 4;
     const uint32_t self = T.colbase + (r.x & 0xFFFFu);
@@ -239,15 +252,14 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, 
     const uint32_t j3 = 0u - (meta >> 15);
     // rb_shift is a multiple of G, so the column's G bits stay inside their byte
     if constexpr (MET) {
-        const uint32_t v = *reinterpret_cast<const uint16_t *>(
-            xs_lds + rb + 2 * ((p << T.lB) + T.rb_sel));
+        const uint32_t v = *(const LDS_AS uint16_t *)(uintptr_t)ra;
         const uint32_t bits = v >> T.rb_shift, bits0 = v >> (8 + T.rb_shift);
 #pragma unroll
         for (int g = 0; g < G; ++g)
             y[g] = met_word(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
                             0u - ((bits >> g) & 1u), 0u - ((bits0 >> g) & 1u));
     } else {
-        const int bits = xs_lds[rb + (p << T.lB) + T.rb_sel];
+        const int bits = *(const LDS_AS uint8_t *)(uintptr_t)ra;
 #pragma unroll
         for (int g = 0; g < G; ++g)  // sign-extended bit rb_shift + g: the group's mask
             y[g] = qg_word<kAcc>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3,
@@ -262,26 +274,27 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t p, 
 // read-only, so each thread fetches its first record of a class before that class's barrier.
 template <int NT, int CW, bool GR, bool kAcc, bool MET = false>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
-    // The class descriptor is uniform: moved to a scalar register once read from LDS.
-    uint32_t cd = __builtin_amdgcn_readfirstlane(lds_u32(T.cls));
+    constexpr uint32_t E = MET ? 2 : 1;  // bytes per acceptance entry
+    // Class bounds are uniform and read-only: scalar loads of the class table.
+    const CONSTANT int32_t *co = (const CONSTANT int32_t *)T.class_off;
+    const uint32_t step = NT >> T.lcol;  // positions between a thread's tasks of one class
+    uint32_t cs = 0, ce = (uint32_t)co[1];
     for (uint32_t c = 0; c < T.ncls; ++c) {
-        const uint32_t cs = cd & 0xFFFFu;
-        const uint32_t ntask = (cd >> 16) << T.lcol;
-        const uint32_t p0 = cs + (T.tid >> T.lcol);
+        const uint32_t ntask = (ce - cs) << T.lcol;
         uint4 r0;  // read only by threads with a task
-        if (T.tid < ntask) r0 = rec_at<GR>(T, p0);
-        if (c + 1 < T.ncls) cd = __builtin_amdgcn_readfirstlane(lds_u32(T.cls + 4 * (c + 1)));
+        if (T.tid < ntask) r0 = rec_at<GR>(T, cs + T.tpos);
+        const uint32_t ce_next = c + 1 < T.ncls ? (uint32_t)co[c + 2] : ce;
         __syncthreads();
-        if (T.tid < ntask) update_task<CW, kAcc, MET>(T, r0, p0, rb, acc);
+        const uint32_t ra = (T.lds0 + rb + E * (cs << T.lB)) + E * T.rbo;
+        if (T.tid < ntask) update_task<CW, kAcc, MET>(T, r0, ra, acc);
         // further rounds of the class (more tasks than threads): a uniform trip count
         const uint32_t rounds = (ntask - 1) / NT;
-        for (uint32_t k = 1; k <= rounds; ++k) {
-            const uint32_t q = T.tid + k * NT;
-            if (q < ntask) {
-                const uint32_t p = cs + (q >> T.lcol);
-                update_task<CW, kAcc, MET>(T, rec_at<GR>(T, p), p, rb, acc);
-            }
-        }
+        for (uint32_t k = 1; k <= rounds; ++k)
+            if (T.tid + k * NT < ntask)
+                update_task<CW, kAcc, MET>(T, rec_at<GR>(T, cs + T.tpos + k * step),
+                                           ra + E * ((k * step) << T.lB), acc);
+        cs = ce;
+        ce = ce_next;
     }
 }
 
@@ -424,20 +437,19 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     T.rb1 = T.rb0 + rbb;
     T.acc = T.rb1 + rbb;
     T.flag = T.acc + 4 * T.ngrp;
-    T.cls = T.flag + 16;
     T.colbase = T.st + T.col * CW;
     T.rb_sel = (T.col << LG) >> 3;
     T.rb_shift = (T.col << LG) & 7;
+    T.tpos = T.tid >> T.lcol;
+    T.rbo = (T.tpos << T.lB) + T.rb_sel;
+    T.class_off = I->class_off;
+    T.lds0 = lds_base();
     T.thr = I->thr;
     T.thr0 = I->thr0;
     T.key0 = I->seed_lo;
     T.key1 = I->seed_hi;
     T.iid = I->inst_id;
     T.ncls = I->n_classes;
-    for (uint32_t c = T.tid; c < T.ncls; c += NT) {
-        const uint32_t a = (uint32_t)I->class_off[c], b = (uint32_t)I->class_off[c + 1];
-        lds_u32(T.cls + 4 * c) = a | ((b - a) << 16);
-    }
 
     // Records: spin indices -> byte offsets of the rows in this tile (GR: done by the host).
     for (uint32_t p = T.tid; !GR && p < T.n; p += NT) {
@@ -607,9 +619,9 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 }  // namespace
 
 size_t chunk_lds_bytes(uint32_t n, uint32_t B, uint32_t n_classes, bool rec_global, bool met) {
+    (void)n_classes;  // the class table is read from global memory
     return (rec_global ? 0 : lds_rec_bytes(n)) + (size_t)n * B * 32 +
-           2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16 +
-           4 * (size_t)n_classes;
+           2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16;
 }
 
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
