@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     ap.add_argument("--workload", default="batched",
-                    choices=["batched", "steady", "uneven", "serve", "tts", "w1scan", "paper"],
+                    choices=["batched", "steady", "uneven", "serve", "tts", "w1scan", "paper",
+                             "single"],
                     help="batched: the default line; steady: 16 x N=1024 x 2^20 clones, fixed "
                          "sweeps; uneven: 512 instances of uneven N and clone count, batched vs "
                          "served vs one at a time; serve: Poisson stream through the server vs "
@@ -70,7 +71,9 @@ def parse():
                          "w1scan: mean TTS against w1 on one small instance, and the same w1 "
                          "with w0 = w1^3; paper: TTS_99 in seconds at the paper's clone count "
                          "(327,680) on planted N = 128 instances, one run at a time, and a "
-                         "short-timeout estimate at N = 256")
+                         "short-timeout estimate at N = 256; single: the N = 64, 1,024-clone "
+                         "instance run to its first ground state with many seeds, one run at a "
+                         "time vs all runs batched, and the oracle on the same runs")
     ap.add_argument("--accept-thr0", type=int, default=0,
                     help="batched: w0 threshold (w0 = thr0 / 65536); > 0 runs the w0 rule for "
                          "the full budget (a ground state is not absorbing, so no early stop)")
@@ -528,6 +531,64 @@ def workload_paper(args, xorsat, torch):
     return out
 
 
+def workload_single(args, xorsat, torch):
+    """One planted N = 64 instance, 1,024 clones, first ground state or 10^5 sweeps, R seeds:
+    TTS in sweeps (p50/p99), wall time per run one at a time, the R runs batched in one call,
+    and the CPU oracle timed on the first runs (its TTS must equal the GPU's)."""
+    from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance, run_seed
+
+    n, ncl, runs = 64, 1024, 200
+    inst = planted_instance(n, gen_seed(1, 0))
+    h = xorsat.Instance(inst.tri, inst.J)
+
+    def cfg(r):
+        return xorsat.make_config(n_clones=ncl, seed=run_seed(1, 0) + r, instance_id=0,
+                                  accept_thr=THR_PAPER, max_sweeps=100000, stop_on_first=True,
+                                  chunk_sweeps=args.chunk)
+
+    xorsat.run(h, cfg(0))  # warm
+    torch.cuda.synchronize()
+    one, secs = [], []
+    for r in range(runs):
+        t1 = time.perf_counter()
+        o = xorsat.run(h, cfg(r), want_energy=False)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t1)
+        one.append(o.tts_sweeps)
+    t0 = time.perf_counter()
+    batch = xorsat.run_batch([h] * runs, [cfg(r) for r in range(runs)], want_energy=False)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    assert [o.tts_sweeps for o in batch] == one
+    tts = np.array(one)
+    return {"metric": "TTS (sweeps, seconds) of single runs, N=64, 1024 clones",
+            "config": {"workload": f"1 planted instance, N={n}, {ncl} clones, {runs} seeds, "
+                                   "first ground state or 1e5 sweeps"},
+            "solved": int((tts >= 0).sum()),
+            "tts_sweeps_p50": pct(tts[tts >= 0], 50), "tts_sweeps_p99": pct(tts[tts >= 0], 99),
+            "one_at_a_time_s_p50": pct(secs, 50), "one_at_a_time_s_p99": pct(secs, 99),
+            "batched_all_runs_s": round(t_batch, 4),
+            "cpu_baseline": cpu_baseline_single(inst, [cfg(r) for r in range(20)],
+                                                [o.sweeps_done for o in batch[:20]], one[:20])}
+
+
+def cpu_baseline_single(inst, cfgs, sweeps, tts):
+    """The oracle on the first single runs in full (every clone up to the GPU's end sweep),
+    timed; its TTS must equal the GPU's."""
+    import oracle
+
+    threads = os.cpu_count() or 1
+    perm, _ = oracle.colour(inst.tri, 32)
+    t0 = time.perf_counter()
+    for c, s, want in zip(cfgs, sweeps, tts):
+        ref = oracle.run(inst.tri, inst.J, perm, seed=c.seed, instance_id=c.instance_id,
+                         thr=c.accept_thr, n_sweeps=s, clone_count=c.n_clones, threads=threads)
+        assert oracle.solve_results(ref["first_hit"])[0] == want
+    dt = time.perf_counter() - t0
+    return {"value": round(dt / len(cfgs), 4), "unit": "s per run", "cores": threads,
+            "kind": "oracle", "sample": f"{len(cfgs)} runs in full, TTS equal to the GPU's"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -554,7 +615,8 @@ def main():
     if args.workload != "batched":
         fn = {"steady": workload_steady, "uneven": workload_uneven,
               "serve": workload_serve, "tts": workload_tts,
-              "w1scan": workload_w1scan, "paper": workload_paper}[args.workload]
+              "w1scan": workload_w1scan, "paper": workload_paper,
+              "single": workload_single}[args.workload]
         print(json.dumps(fn(args, xorsat, torch)), flush=True)
         return
     insts = [planted_instance(args.n, gen_seed(2, k)) for k in range(args.instances)]

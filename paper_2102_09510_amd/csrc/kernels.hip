@@ -69,6 +69,26 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
+// The same bijection for the sweep draws, whose counter is (i, t, z, id) with t and id uniform
+// over the workgroup and z fixed per thread: the caller passes z's first-round product pz and
+// the uniform terms t ^ k0 and id ^ k1 of the first round, so only i varies per call.
+__device__ __forceinline__ uint4 philox10_draw(uint32_t i, uint64_t pz, uint32_t t_k0,
+                                               uint32_t id_k1, uint32_t k0, uint32_t k1) {
+    const uint64_t pi = (uint64_t)0xD2511F53u * i;
+    uint4 c = make_uint4((uint32_t)(pz >> 32) ^ t_k0, (uint32_t)pz,
+                         (uint32_t)(pi >> 32) ^ id_k1, (uint32_t)pi);
+#pragma unroll
+    for (int r = 1; r < 10; ++r) {
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4(lop3<kXor3>((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                       lop3<kXor3>((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
+    }
+    return c;
+}
+
 __device__ __forceinline__ uint32_t below(uint32_t v, uint32_t thr) { return v < thr ? 1u : 0u; }
 
 // One 32-clone word of one spin: eight three-input operations, a ninth when ground states are
@@ -216,13 +236,16 @@ __device__ __forceinline__ uint32_t draws_below(uint4 o, uint32_t thr) {
 
 // Acceptance bits of sweep t: one Philox call per (position, block) gives the eight 16-bit draws
 // of the block's eight groups. MET: a 16-bit entry, the w1 byte and above it the w0 byte of the
-// same draws.
+// same draws. A thread keeps one block (NT is a multiple of B) and strides over positions.
 template <int NT, bool GR, bool MET>
 __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t rb) {
-    for (uint32_t q = T.tid; q < T.n * T.B; q += NT) {
-        const uint32_t p = q >> T.lB, b = q & (T.B - 1);
+    const uint32_t b = T.tid & (T.B - 1);
+    const uint64_t pz = (uint64_t)0xCD9E8D57u * (T.blk0 + b);
+    const uint32_t t_k0 = t ^ T.key0, id_k1 = T.iid ^ T.key1;
+    for (uint32_t p = T.tid >> T.lB; p < T.n; p += NT >> T.lB) {
+        const uint32_t q = (p << T.lB) + b;
         const uint32_t i = (rec_at<GR>(T, p).w >> 16) & 0x1FFFu;
-        const uint4 o = philox10(make_uint4(i, t, T.blk0 + b, T.iid), T.key0, T.key1);
+        const uint4 o = philox10_draw(i, pz, t_k0, id_k1, T.key0, T.key1);
         if constexpr (MET)
             *reinterpret_cast<uint16_t *>(xs_lds + rb + 2 * q) =
                 (uint16_t)(draws_below(o, T.thr) | draws_below(o, T.thr0) << 8);
