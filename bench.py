@@ -78,6 +78,11 @@ def parse():
                     help="batched: w0 threshold (w0 = thr0 / 65536); > 0 runs the w0 rule for "
                          "the full budget (a ground state is not absorbing, so no early stop)")
     ap.add_argument("--scan-n", type=int, default=100, help="w1scan: spins of the instance")
+    ap.add_argument("--scan-w1", type=str, default="",
+                    help="w1scan: comma-separated w1 values (default: 13 values, 0.03..0.20)")
+    ap.add_argument("--cap", type=int, default=32,
+                    help="largest colour class of the partition (the paper's 32); it fixes the "
+                         "update order, so it changes trajectories, not the dynamics")
     ap.add_argument("--paper-instances", type=int, default=100, help="paper: N = 128 instances")
     ap.add_argument("--paper-runs", type=int, default=16, help="paper: runs per N = 128 instance")
     ap.add_argument("--paper-timeout-instances", type=int, default=32,
@@ -115,7 +120,7 @@ def cpu_baseline(insts, args, target_s):
     import oracle
 
     threads = os.cpu_count() or 1
-    perms = [oracle.colour(i.tri, 32)[0] for i in insts]
+    perms = [oracle.colour(i.tri, args.cap)[0] for i in insts]
     # calibrate on one instance
     t0 = time.perf_counter()
     oracle.run(insts[0].tri, insts[0].J, perms[0], seed=1, instance_id=0, thr=3604,
@@ -154,7 +159,7 @@ def workload_steady(args, xorsat, torch):
     count, n, clones = 16, 1024, 1 << 20
     sweeps = args.budget if args.budget != 50000 else 10000
     insts = [planted_instance(n, gen_seed(3, k)) for k in range(count)]
-    hs = [xorsat.Instance(i.tri, i.J) for i in insts]
+    hs = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
     cfgs = [xorsat.make_config(n_clones=clones, seed=run_seed(3, k), instance_id=k,
                                accept_thr=THR_PAPER, max_sweeps=sweeps, stop_on_first=False,
                                chunk_sweeps=args.chunk) for k in range(count)]
@@ -189,7 +194,7 @@ def workload_uneven(args, xorsat, torch):
 
     sizes = uneven_sizes(512)
     insts = [planted_instance(n, gen_seed(4, k)) for k, (n, _) in enumerate(sizes)]
-    hs = [xorsat.Instance(i.tri, i.J) for i in insts]
+    hs = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
     budget = args.budget if args.budget != 50000 else 10000
 
     def cfg(k):
@@ -275,7 +280,7 @@ def workload_serve(args, xorsat, torch):
     hs = []
     for k, (_, n) in enumerate(arrivals):
         inst = planted_instance(n, gen_seed(5, k))
-        hs.append(xorsat.Instance(inst.tri, inst.J))
+        hs.append(xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap))
 
     def cfg(k):
         return xorsat.make_config(n_clones=16384, seed=run_seed(5, k), instance_id=k,
@@ -361,7 +366,7 @@ def workload_tts(args, xorsat, torch):
 
     n, runs = 80, 512
     inst = planted_instance(n, gen_seed(6, 0))
-    h = xorsat.Instance(inst.tri, inst.J)
+    h = xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap)
     out = {"metric": "TTS distribution of many-clone runs (sweeps)",
            "config": {"workload": f"1 planted instance, N={n}, {runs} runs per clone count, "
                                   "to first ground state"}}
@@ -404,9 +409,10 @@ def workload_w1scan(args, xorsat, torch):
     from paper_2102_09510_amd.instances import gen_seed, planted_instance
 
     n, runs, ncl, cap = args.scan_n, 512, 1024, 400000
-    w1s = [0.03, 0.04, 0.05, 0.055, 0.06, 0.07, 0.08, 0.09, 0.10, 0.12, 0.14, 0.17, 0.20]
+    w1s = ([float(v) for v in args.scan_w1.split(",")] if args.scan_w1 else
+           [0.03, 0.04, 0.05, 0.055, 0.06, 0.07, 0.08, 0.09, 0.10, 0.12, 0.14, 0.17, 0.20])
     inst = planted_instance(n, gen_seed(7, 0))
-    h = xorsat.Instance(inst.tri, inst.J)
+    h = xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap)
     rows, times_of = [], {}
     for w1 in w1s:
         thr = round(w1 * 65536)
@@ -430,10 +436,12 @@ def workload_w1scan(args, xorsat, torch):
     m = np.array([r["mean_tts"] for r in rows])
     k = int(np.argmin(m))
     lo, hi = max(0, k - 2), min(len(w), k + 3)
-    c2, c1, _ = np.polyfit(w[lo:hi], m[lo:hi], 2)
-    w_opt = float(-c1 / (2 * c2)) if c2 > 0 else None
+    w_opt = None
+    if hi - lo >= 3:
+        c2, c1, _ = np.polyfit(w[lo:hi], m[lo:hi], 2)
+        w_opt = float(-c1 / (2 * c2)) if c2 > 0 else None
     # w0 = w1^3 at the same pseudo-temperatures, fixed budget
-    budget = int(next(r["p50"] for r in rows if r["w1"] == 0.055))
+    budget = int(next((r["p50"] for r in rows if r["w1"] == 0.055), rows[0]["p50"]))
     met = []
     for w1 in w1s:
         thr, thr0 = round(w1 * 65536), max(1, round(w1 ** 3 * 65536))
@@ -473,7 +481,7 @@ def workload_paper(args, xorsat, torch):
     t_all = time.perf_counter()
     for k in range(count):
         inst = planted_instance(n, gen_seed(8, k))
-        h = xorsat.Instance(inst.tri, inst.J)
+        h = xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap)
         secs, sweeps = [], []
         for r in range(runs):
             cfg = xorsat.make_config(n_clones=ncl, seed=0x5EED + 7919 * r + 104729 * k,
@@ -500,7 +508,7 @@ def workload_paper(args, xorsat, torch):
     hs = []
     for k in range(count):
         inst = planted_instance(n, gen_seed(9, k))
-        hs.append(xorsat.Instance(inst.tri, inst.J))
+        hs.append(xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap))
     cfgs = [xorsat.make_config(n_clones=ncl, seed=0xFACE + 104729 * k, instance_id=k,
                                accept_thr=THR_PAPER, max_sweeps=cap, stop_on_first=True,
                                chunk_sweeps=100) for k in range(count)]
@@ -539,7 +547,7 @@ def workload_single(args, xorsat, torch):
 
     n, ncl, runs = 64, 1024, 200
     inst = planted_instance(n, gen_seed(1, 0))
-    h = xorsat.Instance(inst.tri, inst.J)
+    h = xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap)
 
     def cfg(r):
         return xorsat.make_config(n_clones=ncl, seed=run_seed(1, 0) + r, instance_id=0,
@@ -568,17 +576,17 @@ def workload_single(args, xorsat, torch):
             "tts_sweeps_p50": pct(tts[tts >= 0], 50), "tts_sweeps_p99": pct(tts[tts >= 0], 99),
             "one_at_a_time_s_p50": pct(secs, 50), "one_at_a_time_s_p99": pct(secs, 99),
             "batched_all_runs_s": round(t_batch, 4),
-            "cpu_baseline": cpu_baseline_single(inst, [cfg(r) for r in range(20)],
+            "cpu_baseline": cpu_baseline_single(inst, args.cap, [cfg(r) for r in range(20)],
                                                 [o.sweeps_done for o in batch[:20]], one[:20])}
 
 
-def cpu_baseline_single(inst, cfgs, sweeps, tts):
+def cpu_baseline_single(inst, cap, cfgs, sweeps, tts):
     """The oracle on the first single runs in full (every clone up to the GPU's end sweep),
     timed; its TTS must equal the GPU's."""
     import oracle
 
     threads = os.cpu_count() or 1
-    perm, _ = oracle.colour(inst.tri, 32)
+    perm, _ = oracle.colour(inst.tri, cap)
     t0 = time.perf_counter()
     for c, s, want in zip(cfgs, sweeps, tts):
         ref = oracle.run(inst.tri, inst.J, perm, seed=c.seed, instance_id=c.instance_id,
@@ -617,10 +625,12 @@ def main():
               "serve": workload_serve, "tts": workload_tts,
               "w1scan": workload_w1scan, "paper": workload_paper,
               "single": workload_single}[args.workload]
-        print(json.dumps(fn(args, xorsat, torch)), flush=True)
+        out = fn(args, xorsat, torch)
+        out.setdefault("config", {})["colour_cap"] = args.cap
+        print(json.dumps(out), flush=True)
         return
     insts = [planted_instance(args.n, gen_seed(2, k)) for k in range(args.instances)]
-    handles = [xorsat.Instance(i.tri, i.J) for i in insts]
+    handles = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
 
     def step(s):
         cfgs = [xorsat.make_config(n_clones=args.clones, seed=run_seed(2, k) + s,
@@ -683,7 +693,7 @@ def main():
                                (f"{args.budget} sweeps per step with w0 = "
                                 f"{args.accept_thr0}/65536" if args.accept_thr0 else
                                 f"to first ground state or {args.budget} sweeps per step"),
-                   "chunk_sweeps": args.chunk, "accept_thr": THR_PAPER,
+                   "chunk_sweeps": args.chunk, "accept_thr": THR_PAPER, "colour_cap": args.cap,
                    **({"accept_thr0": args.accept_thr0} if args.accept_thr0 else {})},
         "tts_sweeps": {"solved": len(tts), "censored": censored,
                        "p50": float(np.percentile(tts, 50)) if tts else None,

@@ -80,6 +80,10 @@ typedef struct {
     int32_t n_classes;  /* independent sets in the partition */
     int32_t colour_cap; /* largest allowed set */
     int32_t max_class;  /* largest actual set */
+    int32_t n_levels;   /* parallel steps of a sweep on the device (<= n_classes): each spin one
+                           step after the latest earlier spin in update order that shares a
+                           triplet with it, which reproduces the sequential sweep exactly */
+    int32_t max_level;  /* most spins in one step */
 } xs_instance_info;
 
 xs_status xs_instance_get_info(const xs_instance *inst, xs_instance_info *info);

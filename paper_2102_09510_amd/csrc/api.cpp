@@ -82,20 +82,56 @@ void partition(xs_instance &I) {
     }
 }
 
-// Records in update order: spin, then for each of its three triplets (ascending triplet index)
-// the two other spins, then the three coupling bits (bit q: triplet q has J = -1).
-void build_records(xs_instance &I) {
+// Execution schedule of the update order. The update of a spin reads its own value and those of
+// the spins it shares a triplet with, and writes only its own, so two updates commute unless
+// their spins share a triplet. Each spin is placed in a step after every earlier spin (in update
+// order) it shares a triplet with -- the first such step with room when steps hold at most
+// `cap` spins (cap 0: no limit) -- so running the steps one after another, the spins of a step
+// in parallel, keeps the order of every pair that does not commute and gives exactly the
+// sequential sweep. Steps are independent sets. Uncapped, there are at most as many steps as
+// classes (a member of class c has no conflicting predecessor in c, so by induction its step is
+// at most c) and far fewer when the class cap, not a shared triplet, closed the classes; the
+// cap fits the steps to the threads of a launch.
+xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap) {
     const int n = I.n;
-    std::vector<int32_t> inc(3 * n), deg(n, 0);
+    std::vector<int32_t> inc(3 * (size_t)n), deg(n, 0), pos(n), step(n, 0), fill;
     for (int t = 0; t < n; ++t)
         for (int q = 0; q < 3; ++q) {
             const int v = I.tri[3 * t + q];
             inc[3 * v + deg[v]++] = t;
         }
-    I.rec.assign(8 * (size_t)n, 0);
+    for (int p = 0; p < n; ++p) pos[I.perm[p]] = p;
     for (int p = 0; p < n; ++p) {
-        const int i = I.perm[p];
-        uint16_t *r = &I.rec[8 * (size_t)p];
+        const int v = I.perm[p];
+        int s = 0;
+        for (int q = 0; q < 3; ++q) {
+            const int t = inc[3 * v + q];
+            for (int z = 0; z < 3; ++z) {
+                const int u = I.tri[3 * t + z];
+                if (u != v && pos[u] < p) s = std::max(s, step[u] + 1);
+            }
+        }
+        while (cap && s < (int)fill.size() && fill[s] >= (int)cap) ++s;
+        if (s >= (int)fill.size()) fill.resize(s + 1, 0);
+        ++fill[s];
+        step[v] = s;
+    }
+    xsh::HostSched hs;
+    const int steps = (int)fill.size();
+    hs.off.assign(steps + 1, 0);
+    for (int l = 0; l < steps; ++l) {
+        hs.max_step = std::max(hs.max_step, fill[l]);
+        hs.off[l + 1] = hs.off[l] + fill[l];
+    }
+    std::vector<int32_t> next(hs.off.begin(), hs.off.end() - 1);
+    hs.order.assign(n, 0);
+    for (int p = 0; p < n; ++p) hs.order[next[step[I.perm[p]]]++] = I.perm[p];
+    // Records in schedule order: spin, then for each of its three triplets (ascending triplet
+    // index) the two other spins, then the three coupling bits (bit q: triplet q has J = -1).
+    hs.rec.assign(8 * (size_t)n, 0);
+    for (int p = 0; p < n; ++p) {
+        const int i = hs.order[p];
+        uint16_t *r = &hs.rec[8 * (size_t)p];
         r[0] = (uint16_t)i;
         uint16_t jbits = 0;
         for (int q = 0; q < 3; ++q) {
@@ -109,6 +145,12 @@ void build_records(xs_instance &I) {
         }
         r[7] = jbits;
     }
+    return hs;
+}
+
+// Triplets as the final pass reads them: a, b, c, and j = 1 for J = -1.
+void build_triplets(xs_instance &I) {
+    const int n = I.n;
     I.tri16.assign(4 * (size_t)n, 0);
     for (int t = 0; t < n; ++t) {
         for (int q = 0; q < 3; ++q) I.tri16[4 * t + q] = (uint16_t)I.tri[3 * t + q];
@@ -125,35 +167,49 @@ xs_status ensure_tables(xs_instance *I, int device, DeviceTables *out) {
     }
     DeviceTables t;
     const size_t n = (size_t)I->n;
-    XS_HIP(hipMalloc(&t.rec, 16 * n));
-    XS_HIP(hipMalloc(&t.class_off, sizeof(int32_t) * I->class_off.size()));
     XS_HIP(hipMalloc(&t.tri, 8 * n));
-    XS_HIP(hipMemcpy(t.rec, I->rec.data(), 16 * n, hipMemcpyHostToDevice));
-    XS_HIP(hipMemcpy(t.class_off, I->class_off.data(), sizeof(int32_t) * I->class_off.size(),
-                     hipMemcpyHostToDevice));
     XS_HIP(hipMemcpy(t.tri, I->tri16.data(), 8 * n, hipMemcpyHostToDevice));
     I->dev[device] = t;
     *out = t;
     return XS_OK;
 }
 
-xs_status attach_global_records(std::vector<xs::InstDev> &h, const xs_instance *const *insts,
-                                int count, int device) {
+// Steps of a launch hold one task round: wg_threads / (columns per row) spins.
+uint32_t step_cap(const xs::InstDev &d) {
+    return d.wg_threads * d.col_bytes / (32u * d.tile_blocks);
+}
+
+xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *insts, int count,
+                        int device) {
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
-        if (!d.rec_global) {
-            d.grec = nullptr;
-            continue;
-        }
         xs_instance *I = const_cast<xs_instance *>(insts[k]);
+        const uint32_t cap = step_cap(d);
         std::lock_guard<std::mutex> lock(I->mu);
-        auto &tabs = I->dev[device];
-        auto it = tabs.grec.find(d.tile_blocks);
-        if (it == tabs.grec.end()) {
+        auto hit = I->sched.find(cap);
+        if (hit == I->sched.end()) hit = I->sched.emplace(cap, make_schedule(*I, cap)).first;
+        const xsh::HostSched &hs = hit->second;
+        xsh::DevSched &ds = I->dev[device].sched[cap];
+        if (!ds.rec) {
+            const size_t n = (size_t)I->n;
+            XS_HIP(hipMalloc(&ds.rec, 16 * n));
+            XS_HIP(hipMalloc(&ds.off, sizeof(int32_t) * hs.off.size()));
+            XS_HIP(hipMemcpy(ds.rec, hs.rec.data(), 16 * n, hipMemcpyHostToDevice));
+            XS_HIP(hipMemcpy(ds.off, hs.off.data(), sizeof(int32_t) * hs.off.size(),
+                             hipMemcpyHostToDevice));
+            ds.steps = (uint32_t)hs.off.size() - 1;
+        }
+        d.rec = ds.rec;
+        d.class_off = ds.off;
+        d.n_classes = ds.steps;
+        d.grec = nullptr;
+        if (!d.rec_global) continue;
+        auto it = ds.grec.find(d.tile_blocks);
+        if (it == ds.grec.end()) {
             const uint32_t rowb = 32u * d.tile_blocks;
             std::vector<uint32_t> g(4 * (size_t)I->n);
             for (int p = 0; p < I->n; ++p) {
-                const uint16_t *r = &I->rec[8 * (size_t)p];
+                const uint16_t *r = &hs.rec[8 * (size_t)p];
                 const uint32_t i = r[0];
                 g[4 * p + 0] = (i * rowb) | ((r[1] * rowb) << 16);
                 g[4 * p + 1] = (r[2] * rowb) | ((r[3] * rowb) << 16);
@@ -163,7 +219,7 @@ xs_status attach_global_records(std::vector<xs::InstDev> &h, const xs_instance *
             uint4 *dp = nullptr;
             XS_HIP(hipMalloc(&dp, 16 * (size_t)I->n));
             XS_HIP(hipMemcpy(dp, g.data(), 16 * (size_t)I->n, hipMemcpyHostToDevice));
-            it = tabs.grec.emplace(d.tile_blocks, dp).first;
+            it = ds.grec.emplace(d.tile_blocks, dp).first;
         }
         d.grec = it->second;
     }
@@ -241,12 +297,16 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
 }
 
 // Default workgroup size for a tile of B blocks: one thread per (spin, 16-byte column) task of a
-// full 32-spin class, within [256, 1024].
-uint32_t default_threads(uint32_t B) { return std::min(1024u, std::max(256u, 64u * B)); }
+// full 32-spin class, within [256, 1024]; one-block tiles of more than 1024 spins take 512, so
+// that a sweep step (wg_threads / columns spins) stays near the spins per dependency level.
+uint32_t default_threads(uint32_t B, uint32_t n) {
+    if (B == 1 && n > 1024) return 512u;
+    return std::min(1024u, std::max(256u, 64u * B));
+}
 
-// Default task column: narrower columns for small tiles, so that a 32-spin class still spreads
-// over the workgroup (a one-block tile has 64 tasks of 16 bytes, 128 of 8 bytes).
-uint32_t default_col_bytes(uint32_t B) { return B >= 4 ? 16u : 8u; }
+// Default task column: 16 bytes, and 8 for one-block tiles, so that a step still spreads over
+// the workgroup (a one-block tile has 64 tasks of 16 bytes per 32 spins, 128 of 8 bytes).
+uint32_t default_col_bytes(uint32_t B) { return B >= 2 ? 16u : 8u; }
 
 // Default record placement: global memory once the records take a sizeable share of the
 // workgroup's LDS (n >= 512: 8 KB or more); measured neutral at n = 256, faster above.
@@ -306,15 +366,12 @@ struct ChunkGraph {
 void fill_desc(const xs_instance *I, const xs_run_config &c, const DeviceTables &t,
                uint64_t *state, int32_t *first_hit, int32_t *energy, xs::InstDev &d) {
     std::memset(&d, 0, sizeof d);
-    d.rec = t.rec;
-    d.class_off = t.class_off;
-    d.tri = t.tri;
+    d.tri = t.tri;  // records and step offsets: attach_tables, once the launch is chosen
     d.state = state;
     d.first_hit = first_hit;
     d.energy = energy;
     d.n = (uint32_t)I->n;
     d.n_words = c.n_clones / 64;
-    d.n_classes = (uint32_t)I->class_off.size() - 1;
     d.inst_id = c.instance_id;
     d.thr = c.accept_thr;
     d.thr0 = c.accept_thr0;
@@ -380,7 +437,7 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         d.log2_tile_blocks = ilog2(d.tile_blocks);
         uint32_t T = cfgs[k].wg_threads ? cfgs[k].wg_threads
                      : d.wg_threads       ? d.wg_threads
-                                          : default_threads(d.tile_blocks);
+                                          : default_threads(d.tile_blocks, d.n);
         T = std::max(T, 8 * d.tile_blocks);
         d.wg_threads = T;
         const uint32_t C = cfgs[k].col_bytes ? cfgs[k].col_bytes
@@ -436,7 +493,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     {
         xs_status st = tile_instances(h, cfgs, count, tiles, groups);
         if (st != XS_OK) return st;
-        st = attach_global_records(h, insts, count, device);
+        st = attach_tables(h, insts, count, device);
         if (st != XS_OK) return st;
     }
     // Per-call device scratch: descriptors, tiles, the running-instance counter and the
@@ -642,7 +699,8 @@ xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int
     I->tri.assign(tri, tri + 3 * (size_t)m);
     I->J.assign(J, J + m);
     partition(*I);
-    build_records(*I);
+    build_triplets(*I);
+    I->sched.emplace(0u, make_schedule(*I, 0));  // uncapped steps, reported by get_info
     *out = I;
     return XS_OK;
 }
@@ -653,10 +711,12 @@ void xs_instance_destroy(xs_instance *I) {
     (void)hipGetDevice(&cur);
     for (auto &kv : I->dev) {
         (void)hipSetDevice(kv.first);
-        (void)hipFree(kv.second.rec);
-        (void)hipFree(kv.second.class_off);
         (void)hipFree(kv.second.tri);
-        for (auto &g : kv.second.grec) (void)hipFree(g.second);
+        for (auto &s : kv.second.sched) {
+            (void)hipFree(s.second.rec);
+            (void)hipFree(s.second.off);
+            for (auto &g : s.second.grec) (void)hipFree(g.second);
+        }
     }
     if (cur >= 0 && !I->dev.empty()) (void)hipSetDevice(cur);
     delete I;
@@ -668,6 +728,9 @@ xs_status xs_instance_get_info(const xs_instance *I, xs_instance_info *info) {
     info->n_classes = (int32_t)I->class_off.size() - 1;
     info->colour_cap = I->cap;
     info->max_class = I->max_class;
+    const xsh::HostSched &lv = I->sched.at(0u);
+    info->n_levels = (int32_t)lv.off.size() - 1;
+    info->max_level = lv.max_step;
     return XS_OK;
 }
 

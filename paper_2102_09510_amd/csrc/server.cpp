@@ -172,7 +172,7 @@ struct xs_server {
             if (st != XS_OK) return st;
             std::vector<const xs_instance *> insts(R);
             for (int k = 0; k < R; ++k) insts[k] = resident[k]->inst;
-            st = xsh::attach_global_records(h, insts.data(), R, device);
+            st = xsh::attach_tables(h, insts.data(), R, device);
             if (st != XS_OK) return st;
             const size_t off_tiles = align256(sizeof(xs::InstDev) * R);
             const size_t off_active = off_tiles + align256(sizeof(uint2) * tiles.size());

@@ -12,11 +12,25 @@
 
 namespace xsh {
 
-struct DeviceTables {
+// One execution schedule of the sweep on a device: records in schedule order and step offsets.
+struct DevSched {
+    uint4 *rec = nullptr;              // [n] records (spin indices)
+    int32_t *off = nullptr;            // [steps + 1]
+    uint32_t steps = 0;
     std::map<uint32_t, uint4 *> grec;  // records as row offsets, per tile_blocks
-    uint4 *rec = nullptr;
-    int32_t *class_off = nullptr;
+};
+
+struct DeviceTables {
     uint2 *tri = nullptr;
+    std::map<uint32_t, DevSched> sched;  // per step cap
+};
+
+// The host side of a schedule: the update order regrouped into parallel steps.
+struct HostSched {
+    std::vector<int32_t> order;  // spins in schedule order
+    std::vector<int32_t> off;    // [steps + 1]
+    std::vector<uint16_t> rec;   // [n][8] records in schedule order
+    int32_t max_step = 0;
 };
 
 
@@ -29,7 +43,7 @@ struct xs_instance {
     std::vector<int8_t> J;           // [n]
     std::vector<int32_t> perm;       // update order
     std::vector<int32_t> class_off;  // [n_classes + 1]
-    std::vector<uint16_t> rec;       // [n][8] in update order
+    std::map<uint32_t, xsh::HostSched> sched;  // per step cap (0: uncapped levels)
     std::vector<uint16_t> tri16;     // [n][4]: a, b, c, j
     int32_t max_class = 0;
     std::mutex mu;
@@ -62,10 +76,11 @@ struct TileGroup {
     uint32_t threads, col_bytes, rec_global, met;
     size_t first, count, lds;
 };
-// Point every descriptor that reads its records from global memory at its instance's table for
-// its tiling (uploaded on first use).
-xs_status attach_global_records(std::vector<xs::InstDev> &h, const xs_instance *const *insts,
-                                int count, int device);
+// After tiling: point every descriptor at its instance's schedule for the launch's step width
+// (records, step offsets, and the global-memory records of its tiling if it reads records from
+// global memory), built and uploaded on first use.
+xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *insts, int count,
+                        int device);
 // Choose tiling for descriptors h[0..count) (explicit config knobs, then the tuned table, then
 // the default rule), fill tile_blocks / log2 / wg_threads, and build the tile list and groups.
 xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs, int count,

@@ -106,7 +106,8 @@ class ServerStats(ctypes.Structure):
 
 class InstanceInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_classes", ctypes.c_int32),
-                ("colour_cap", ctypes.c_int32), ("max_class", ctypes.c_int32)]
+                ("colour_cap", ctypes.c_int32), ("max_class", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("max_level", ctypes.c_int32)]
 
 
 _lib = None
@@ -192,6 +193,8 @@ class Instance:
         self.n_classes = info.n_classes
         self.colour_cap = info.colour_cap
         self.max_class = info.max_class
+        self.n_levels = info.n_levels
+        self.max_level = info.max_level
 
     @property
     def handle(self):

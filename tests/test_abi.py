@@ -44,7 +44,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(xorsat.RunConfig) == 64  # 64 bytes of fields
     assert ctypes.sizeof(xorsat.RunBuffers) == 32
     assert ctypes.sizeof(xorsat.RunResult) == 56
-    assert ctypes.sizeof(xorsat.InstanceInfo) == 16
+    assert ctypes.sizeof(xorsat.InstanceInfo) == 24
     assert ctypes.sizeof(xorsat.ServerConfig) == 16
     assert ctypes.sizeof(xorsat.ServerOutputs) == 32
     assert ctypes.sizeof(xorsat.ServerCompletion) == 80
@@ -63,6 +63,20 @@ def test_partition_matches_oracle(lib, n, cap):
     assert np.array_equal(off, ooff)
     assert h.n_classes == len(ooff) - 1
     assert h.max_class == int(np.diff(ooff).max())
+    # dependency levels of the update order: one level after the latest earlier spin that
+    # shares a triplet
+    pos = np.empty(n, dtype=np.int64)
+    pos[operm] = np.arange(n)
+    partners = [[] for _ in range(n)]
+    for t in inst.tri.tolist():
+        for v in t:
+            partners[v] += [u for u in t if u != v]
+    level = np.zeros(n, dtype=np.int64)
+    for v in operm:
+        level[v] = max((level[u] + 1 for u in partners[v] if pos[u] < pos[v]), default=0)
+    sizes = np.bincount(level)
+    assert h.n_levels == len(sizes) <= h.n_classes
+    assert h.max_level == int(sizes.max())
     h.close()
 
 
