@@ -241,9 +241,9 @@ uint32_t max_tile_blocks(uint32_t n, uint32_t n_blocks, uint32_t max_nb) {
     return B;
 }
 
-// Default tiling: each workgroup keeps at most 32 KB of clone state (four workgroups per CU
-// fit the 160 KB of LDS next to their tables), then tiles are halved across the batch while it
-// has fewer than kTargetTiles workgroups, so that small batches still spread over the CUs.
+// Default tiling: default_tile_blocks per instance, then tiles are halved across the batch
+// while it has fewer than kTargetTiles workgroups, so that small batches still spread over the
+// CUs.
 constexpr size_t kTargetTiles = 1024;
 
 xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b,
@@ -296,12 +296,21 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
     return XS_OK;
 }
 
-// Default workgroup size for a tile of B blocks: one thread per (spin, 16-byte column) task of a
-// full 32-spin class, within [256, 1024]; one-block tiles of more than 1024 spins take 512, so
-// that a sweep step (wg_threads / columns spins) stays near the spins per dependency level.
+// Default workgroup size for a tile of B blocks: about one thread per task of a typical sweep
+// step (tasks = spins of the step x columns of the row), as measured: 256 up to four blocks,
+// 512 from eight, and 512 for one-block tiles of more than 1024 spins, whose steps are large.
 uint32_t default_threads(uint32_t B, uint32_t n) {
     if (B == 1 && n > 1024) return 512u;
-    return std::min(1024u, std::max(256u, 64u * B));
+    return B >= 8 ? 512u : 256u;
+}
+
+// Default tile: the largest with n * B <= 1024 (at most 32 KB of clone state, four workgroups
+// per CU), raised to eight blocks (256-byte rows: a 16-lane LDS access stays on one row, free
+// of bank conflicts) where n * 8 <= 2048 still leaves two workgroups per CU.
+uint32_t default_tile_blocks(uint32_t n, uint32_t nb) {
+    uint32_t B = max_tile_blocks(n, nb, 1024);
+    if (B < 8 && n * 8 <= 2048 && nb % 8 == 0) B = 8;
+    return B;
 }
 
 // Default task column: 16 bytes, and 8 for one-block tiles, so that a step still spreads over
@@ -393,7 +402,7 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         const xs_run_config &c = cfgs[k];
         xs::InstDev &d = h[k];
         const uint32_t nb = c.n_clones / 256;
-        uint32_t B = c.tile_blocks ? c.tile_blocks : max_tile_blocks(d.n, nb, 1024);
+        uint32_t B = c.tile_blocks ? c.tile_blocks : default_tile_blocks(d.n, nb);
         uint32_t tuned_T = 0, tuned_C = 0, tuned_G = 0;
         if (!c.tile_blocks && !c.wg_threads && !c.col_bytes && !c.rec_global) {
             std::lock_guard<std::mutex> lock(g_tune_mu);
