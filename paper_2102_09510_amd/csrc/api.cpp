@@ -200,8 +200,8 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
             ds.steps = (uint32_t)hs.off.size() - 1;
         }
         d.rec = ds.rec;
-        d.class_off = ds.off;
-        d.n_classes = ds.steps;
+        d.step_off = ds.off;
+        d.n_steps = ds.steps;
         d.grec = nullptr;
         if (!d.rec_global) continue;
         auto it = ds.grec.find(d.tile_blocks);
@@ -462,7 +462,7 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
         const auto key = std::make_tuple(T, C, d.rec_global, met);
         auto &v = by_launch[key];
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) v.push_back(make_uint2((uint32_t)k, b0));
-        lds_of[key] = std::max(lds_of[key], xs::chunk_lds_bytes(d.n, d.tile_blocks, d.n_classes,
+        lds_of[key] = std::max(lds_of[key], xs::chunk_lds_bytes(d.n, d.tile_blocks,
                                                                 d.rec_global != 0, met != 0));
     }
     tiles.clear();
@@ -758,7 +758,6 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
                     XS_CLONE_QUANTUM);
     hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
     const uint32_t n = (uint32_t)inst->n, nb = n_clones / 256;
-    const uint32_t ncls = (uint32_t)inst->class_off.size() - 1;
     const size_t state_bytes = (size_t)n * n_clones / 8;
     const int copies = (int)std::max<size_t>(1, std::min<size_t>((size_t)count,
                                                                  (size_t(2) << 30) / state_bytes));
@@ -794,15 +793,15 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
     }
     std::memset(out, 0, sizeof *out);
     for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
-        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, ncls, true, false) > 160 * 1024) continue;
+        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, true, false) > 160 * 1024) continue;
         for (uint32_t T = 128; T <= 1024; T *= 2) {
             if (T < 8 * B || (T == 128 && B > 2)) continue;
             for (uint32_t C = 4; C <= 16; C *= 2)
                 for (uint32_t G = (n >= 512 ? 1u : 2u); G <= 2; ++G) {
-                    // skip columns that leave most threads without a task in a full class
+                    // skip columns that leave most threads without a task in a full step
                     if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
                         continue;
-                    if (xs::chunk_lds_bytes(n, B, ncls, G == 1, false) > 160 * 1024) continue;
+                    if (xs::chunk_lds_bytes(n, B, G == 1, false) > 160 * 1024) continue;
                     for (auto &c : cfgs) {
                         c.tile_blocks = B;
                         c.wg_threads = T;

@@ -3,13 +3,15 @@
 // Paper: Bernaschi et al., arXiv 2102.09510. Section "The quasi-greedy algorithm" gives the
 // rule (w0 = 0, w1, w2 = w3 = 1); Section "Basic information about the GPU implementation" the
 // multispin coding (one random number per 32-clone word); the Supplementary Material the
-// independent-set schedule, the LDS-resident state and the many sweeps per launch.
+// independent-set schedule, the LDS-resident state and the many sweeps per launch. The host
+// hands the kernels the update order as steps: independent sets whose in-order execution is
+// the sequential sweep (spins sharing a triplet keep their order).
 //
 // Data layout
 //   global state   uint64 [n][W] spin-major, W = n_clones / 64 (bit = clone).
 //   tile           B consecutive 256-clone blocks of one instance (4*B words per spin row),
 //                  owned by one workgroup for a whole chunk of sweeps.
-//   LDS            rec  [n]      16-byte records in update order, u16 fields: byte offsets of
+//   LDS            rec  [n]      16-byte records in step order, u16 fields: byte offsets of
 //                               the spin's own row and of the two other spins of each of its
 //                               three triplets, then meta = i | jbits << 13;
 //                  state [n][32*B] the tile's rows;
@@ -17,7 +19,7 @@
 //                               (position, block): bit k belongs to group k of the block;
 //                  acc   [8*B]   per-group OR of "some triplet of the visited spin is
 //                               unsatisfied" over the current sweep.
-//   task           one spin of the current class x 16 bytes of its row (2 words, 4 groups,
+//   task           one spin of the current step x 16 bytes of its row (2 words, 4 groups,
 //                  128 clones). Consecutive threads take consecutive 16-byte columns of the
 //                  same row, so a wave reads contiguous LDS runs.
 //
@@ -174,7 +176,7 @@ __device__ __forceinline__ uint32_t lds_base() {
 }
 
 // Per-workgroup view of one tile. LDS locations are byte offsets into xs_lds. A task is one
-// spin of the current class and one column of CW bytes of the tile's rows (CW / 4 groups of 32
+// spin of the current step and one column of CW bytes of the tile's rows (CW / 4 groups of 32
 // clones); `col` is this thread's column, fixed because the workgroup size is a multiple of the
 // column count.
 struct Tile {
@@ -187,10 +189,10 @@ struct Tile {
     uint32_t flag;       // workgroup flag (uint32)
     uint32_t colbase;    // st + this thread's column
     uint32_t rb_sel, rb_shift;
-    uint32_t thr, thr0, key0, key1, iid, ncls;
-    uint32_t tpos;       // this thread's first task position in a class (tid >> lcol)
-    uint32_t rbo;        // its acceptance entry index relative to the class start
-    const int32_t *class_off;
+    uint32_t thr, thr0, key0, key1, iid, nsteps;
+    uint32_t tpos;       // this thread's first task position in a step (tid >> lcol)
+    uint32_t rbo;        // its acceptance entry index relative to the step start
+    const int32_t *step_off;
     uint32_t lds0;       // absolute LDS address of xs_lds
 };
 
@@ -292,30 +294,30 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
     col_store<CW>(self, y);
 }
 
-// The classes of one sweep, a barrier before each (the first one also publishes the sweep's
-// acceptance bits and the previous sweep's last writes). Records and class descriptors are
-// read-only, so each thread fetches its first record of a class before that class's barrier.
+// The steps of one sweep, a barrier before each (the first one also publishes the sweep's
+// acceptance bits and the previous sweep's last writes). Records and step bounds are
+// read-only, so each thread fetches its first record of a step before that step's barrier.
 template <int NT, int CW, bool GR, bool kAcc, bool MET = false>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
     constexpr uint32_t E = MET ? 2 : 1;  // bytes per acceptance entry
-    // Class bounds are uniform and read-only: scalar loads of the class table.
-    const CONSTANT int32_t *co = (const CONSTANT int32_t *)T.class_off;
-    const uint32_t step = NT >> T.lcol;  // positions between a thread's tasks of one class
-    uint32_t cs = 0, ce = (uint32_t)co[1];
-    for (uint32_t c = 0; c < T.ncls; ++c) {
+    // Step bounds are uniform and read-only: scalar loads of the step table.
+    const CONSTANT int32_t *so = (const CONSTANT int32_t *)T.step_off;
+    const uint32_t stride = NT >> T.lcol;  // positions between a thread's tasks of one step
+    uint32_t cs = 0, ce = (uint32_t)so[1];
+    for (uint32_t c = 0; c < T.nsteps; ++c) {
         const uint32_t ntask = (ce - cs) << T.lcol;
         uint4 r0;  // read only by threads with a task
         if (T.tid < ntask) r0 = rec_at<GR>(T, cs + T.tpos);
-        const uint32_t ce_next = c + 1 < T.ncls ? (uint32_t)co[c + 2] : ce;
+        const uint32_t ce_next = c + 1 < T.nsteps ? (uint32_t)so[c + 2] : ce;
         __syncthreads();
         const uint32_t ra = (T.lds0 + rb + E * (cs << T.lB)) + E * T.rbo;
         if (T.tid < ntask) update_task<CW, kAcc, MET>(T, r0, ra, acc);
-        // further rounds of the class (more tasks than threads): a uniform trip count
+        // further rounds of the step (more tasks than threads): a uniform trip count
         const uint32_t rounds = (ntask - 1) / NT;
         for (uint32_t k = 1; k <= rounds; ++k)
             if (T.tid + k * NT < ntask)
-                update_task<CW, kAcc, MET>(T, rec_at<GR>(T, cs + T.tpos + k * step),
-                                           ra + E * ((k * step) << T.lB), acc);
+                update_task<CW, kAcc, MET>(T, rec_at<GR>(T, cs + T.tpos + k * stride),
+                                           ra + E * ((k * stride) << T.lB), acc);
         cs = ce;
         ce = ce_next;
     }
@@ -465,14 +467,14 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     T.rb_shift = (T.col << LG) & 7;
     T.tpos = T.tid >> T.lcol;
     T.rbo = (T.tpos << T.lB) + T.rb_sel;
-    T.class_off = I->class_off;
+    T.step_off = I->step_off;
     T.lds0 = lds_base();
     T.thr = I->thr;
     T.thr0 = I->thr0;
     T.key0 = I->seed_lo;
     T.key1 = I->seed_hi;
     T.iid = I->inst_id;
-    T.ncls = I->n_classes;
+    T.nsteps = I->n_steps;
 
     // Records: spin indices -> byte offsets of the rows in this tile (GR: done by the host).
     for (uint32_t p = T.tid; !GR && p < T.n; p += NT) {
@@ -489,7 +491,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
     load_state<NT>(T);
     if constexpr (MET) {
         uint32_t none[G] = {};
-        __syncthreads();  // records, class table and state visible to every thread
+        __syncthreads();  // records and state visible to every thread
         accept_bits<NT, GR, true>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
             sweep<NT, CW, GR, false, true>(T, (t & 1) ? T.rb1 : T.rb0, none);
@@ -641,8 +643,7 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 
 }  // namespace
 
-size_t chunk_lds_bytes(uint32_t n, uint32_t B, uint32_t n_classes, bool rec_global, bool met) {
-    (void)n_classes;  // the class table is read from global memory
+size_t chunk_lds_bytes(uint32_t n, uint32_t B, bool rec_global, bool met) {
     return (rec_global ? 0 : lds_rec_bytes(n)) + (size_t)n * B * 32 +
            2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16;
 }

@@ -14,8 +14,8 @@ constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
 // the constant part, the kernels update the control part.
 struct InstDev {
     // tables (device pointers owned by the instance)
-    const uint4 *rec;        // [n] 16-byte records in update order: u16 {i, a1, b1, a2, b2, a3, b3, jbits}
-    const int32_t *class_off; // [n_classes + 1]
+    const uint4 *rec;        // [n] 16-byte records in step order: u16 {i, a1, b1, a2, b2, a3, b3, jbits}
+    const int32_t *step_off; // [n_steps + 1] schedule steps (independent sets, run in order)
     const uint2 *tri;        // [n] triplets: x = a | b << 16, y = c | j << 16 (j = 1 <=> J = -1)
     const uint4 *grec;       // [n] records with row offsets for this tiling (global-record kernels)
     // caller buffers
@@ -24,7 +24,7 @@ struct InstDev {
     int32_t *energy;         // [n_clones] or null
     int8_t *solved;          // [n] device staging for the winner's spins
     // constants
-    uint32_t n, n_words, n_classes, tile_blocks, log2_tile_blocks;
+    uint32_t n, n_words, n_steps, tile_blocks, log2_tile_blocks;
     uint32_t inst_id, thr, seed_lo, seed_hi;
     uint32_t flags, t_start, t_stop, chunk;
     // control (mutable)
@@ -54,6 +54,5 @@ hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tile
                         hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
 hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
-size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, uint32_t n_classes, bool rec_global,
-                       bool met);
+size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, bool rec_global, bool met);
 }  // namespace xs
