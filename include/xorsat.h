@@ -90,6 +90,13 @@ xs_status xs_instance_get_info(const xs_instance *inst, xs_instance_info *info);
 /* The update order: perm[n] (spins set by set) and class_off[n_classes + 1] (set k holds
  * positions class_off[k] .. class_off[k+1]-1). Host arrays owned by the caller. */
 xs_status xs_instance_get_partition(const xs_instance *inst, int32_t *perm, int32_t *class_off);
+/* The execution schedule the kernels use for launches whose steps hold at most step_cap spins
+ * (0: no limit): order[n] (spins step by step) and step_off[*n_steps + 1]. Each spin sits in a
+ * later step than every spin before it in the update order that shares a triplet with it, so
+ * running the steps in order reproduces the sequential sweep exactly. step_off needs room for
+ * n + 1 entries. Host arrays owned by the caller. */
+xs_status xs_instance_get_schedule(const xs_instance *inst, uint32_t step_cap, int32_t *order,
+                                   int32_t *step_off, int32_t *n_steps);
 
 /*
  * Run configuration. The dynamics (Section "The quasi-greedy algorithm"): a sweep visits the

@@ -750,6 +750,20 @@ xs_status xs_instance_get_partition(const xs_instance *I, int32_t *perm, int32_t
     return XS_OK;
 }
 
+xs_status xs_instance_get_schedule(const xs_instance *I, uint32_t step_cap, int32_t *order,
+                                   int32_t *step_off, int32_t *n_steps) {
+    if (!I || !order || !step_off || !n_steps) return fail(XS_EINVAL, "null argument");
+    xs_instance *M = const_cast<xs_instance *>(I);
+    std::lock_guard<std::mutex> lock(M->mu);
+    auto it = M->sched.find(step_cap);
+    if (it == M->sched.end()) it = M->sched.emplace(step_cap, make_schedule(*M, step_cap)).first;
+    const xsh::HostSched &hs = it->second;
+    std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
+    std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());
+    *n_steps = (int32_t)hs.off.size() - 1;
+    return XS_OK;
+}
+
 xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count, void *stream_v,
                       xs_tune_result *out) {
     if (!inst || !out || count <= 0) return fail(XS_EINVAL, "null argument or count <= 0");

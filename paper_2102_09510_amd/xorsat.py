@@ -27,6 +27,7 @@ XS_CLONE_QUANTUM = 256
 # Every function the header declares, for the export check.
 EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_create",
            "xs_instance_destroy", "xs_instance_get_info", "xs_instance_get_partition",
+           "xs_instance_get_schedule",
            "xs_run", "xs_run_batch", "xs_profile_enable", "xs_profile_read",
            "xs_autotune", "xs_tune_save", "xs_tune_load", "xs_tune_clear",
            "xs_server_create", "xs_server_destroy", "xs_server_submit", "xs_server_step",
@@ -135,6 +136,8 @@ def load():
     lib.xs_instance_get_info.restype = i32
     lib.xs_instance_get_partition.argtypes = [P, P, P]
     lib.xs_instance_get_partition.restype = i32
+    lib.xs_instance_get_schedule.argtypes = [P, ctypes.c_uint32, P, P, P]
+    lib.xs_instance_get_schedule.restype = i32
     lib.xs_run.argtypes = [P, ctypes.POINTER(RunConfig), ctypes.POINTER(RunBuffers), P,
                            ctypes.POINTER(RunResult)]
     lib.xs_run.restype = i32
@@ -205,6 +208,15 @@ class Instance:
         off = np.zeros(self.n_classes + 1, dtype=np.int32)
         _check(load().xs_instance_get_partition(self._h, perm.ctypes.data, off.ctypes.data))
         return perm, off
+
+    def schedule(self, step_cap: int = 0):
+        """The kernels' execution order for steps of at most step_cap spins: (order, step_off)."""
+        order = np.zeros(self.n, dtype=np.int32)
+        off = np.zeros(self.n + 1, dtype=np.int32)
+        steps = ctypes.c_int32()
+        _check(load().xs_instance_get_schedule(self._h, step_cap, order.ctypes.data,
+                                               off.ctypes.data, ctypes.byref(steps)))
+        return order, off[: steps.value + 1].copy()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
