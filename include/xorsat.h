@@ -207,6 +207,9 @@ typedef struct {
     uint32_t struct_size;
     uint32_t max_resident;     /* requests resident at once (0 = no limit besides memory) */
     uint64_t hbm_budget_bytes; /* device bytes the resident requests may hold */
+    uint32_t max_pending;      /* queued, not yet admitted requests (0 = no limit); a submit
+                                  beyond it returns XS_EAGAIN (back-pressure) */
+    uint32_t reserved;         /* must be 0 */
 } xs_server_config;
 
 /* Host buffers filled when a request completes; each may be NULL. */
@@ -235,7 +238,8 @@ xs_status xs_server_create(const xs_server_config *cfg, void *stream, xs_server 
 /* Releases every request's device memory; pending and resident requests are dropped. */
 void xs_server_destroy(xs_server *srv);
 /* Queue a request; the configuration and output pointers are copied, the instance is not.
- * XS_EINVAL for an invalid configuration. */
+ * XS_EINVAL for an invalid configuration, XS_EAGAIN (nothing queued) while max_pending requests
+ * wait for admission. */
 xs_status xs_server_submit(xs_server *srv, const xs_instance *inst, const xs_run_config *cfg,
                            const xs_server_outputs *outs, uint64_t *ticket);
 /* One scheduling step (see above). n_active receives resident + pending requests after it. */
@@ -256,7 +260,7 @@ xs_status xs_server_get_stats(const xs_server *srv, xs_server_stats *out);
  * `inst` (fewer if their state would exceed 2 GiB) on `stream`, using HIP events around the
  * sweep launches, and records the fastest combination for workloads of the same N (rounded up to a
  * power of two), clone count and batch size (rounded up to a power of two, at most 64). Later
- * runs whose config leaves both knobs 0 use the recorded pair. Allocates and frees its own
+ * runs whose config leaves every knob 0 use the recorded choice. Allocates and frees its own
  * device buffers. Results of any run never depend on these knobs.
  */
 #define XS_TUNE_MAX_TRIALS 64

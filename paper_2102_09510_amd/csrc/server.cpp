@@ -267,6 +267,7 @@ xs_status xs_server_create(const xs_server_config *cfg, void *stream, xs_server 
     if (cfg->struct_size < sizeof(xs_server_config))
         return fail(XS_EINVAL, "xs_server_config.struct_size too small");
     if (cfg->hbm_budget_bytes == 0) return fail(XS_EINVAL, "hbm_budget_bytes is 0");
+    if (cfg->reserved) return fail(XS_EINVAL, "xs_server_config.reserved must be 0");
     xs_server *S = new (std::nothrow) xs_server;
     if (!S) return fail(XS_ENOMEM, "host allocation failed");
     S->cfg = *cfg;
@@ -293,6 +294,8 @@ xs_status xs_server_submit(xs_server *srv, const xs_instance *inst, const xs_run
     xs_status st = xsh::validate_run(inst, cfg, &none, false);
     if (st != XS_OK) return st;
     if (cfg->flags & XS_RESUME) return fail(XS_EINVAL, "XS_RESUME is not supported by the server");
+    if (srv->cfg.max_pending && srv->pending.size() >= srv->cfg.max_pending)
+        return fail(XS_EAGAIN, "%zu requests already wait for admission", srv->pending.size());
     Request *r = new (std::nothrow) Request;
     if (!r) return fail(XS_ENOMEM, "host allocation failed");
     r->ticket = srv->next_ticket++;

@@ -85,7 +85,8 @@ class TuneResult(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_resident", ctypes.c_uint32),
-                ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("hbm_budget_bytes", ctypes.c_uint64), ("max_pending", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class ServerOutputs(ctypes.Structure):
@@ -370,8 +371,9 @@ class Server:
     """Continuous-batching server (xs_server_*). Host numpy buffers receive each request's
     outputs when it completes."""
 
-    def __init__(self, hbm_budget_bytes: int, max_resident: int = 0):
-        cfg = ServerConfig(ctypes.sizeof(ServerConfig), max_resident, hbm_budget_bytes)
+    def __init__(self, hbm_budget_bytes: int, max_resident: int = 0, max_pending: int = 0):
+        cfg = ServerConfig(ctypes.sizeof(ServerConfig), max_resident, hbm_budget_bytes,
+                           max_pending, 0)
         h = ctypes.c_void_p()
         _check(load().xs_server_create(ctypes.byref(cfg), _stream(), ctypes.byref(h)))
         self._h = h

@@ -45,7 +45,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(xorsat.RunBuffers) == 32
     assert ctypes.sizeof(xorsat.RunResult) == 56
     assert ctypes.sizeof(xorsat.InstanceInfo) == 24
-    assert ctypes.sizeof(xorsat.ServerConfig) == 16
+    assert ctypes.sizeof(xorsat.ServerConfig) == 24
     assert ctypes.sizeof(xorsat.ServerOutputs) == 32
     assert ctypes.sizeof(xorsat.ServerCompletion) == 80
     assert ctypes.sizeof(xorsat.ServerStats) == 64

@@ -120,6 +120,34 @@ def test_server_admission_by_footprint_and_cancel():
     srv.close()
 
 
+def test_server_back_pressure():
+    """With max_pending set, a submit beyond the queue limit is refused with XS_EAGAIN and
+    accepted again once a step has admitted the waiting requests."""
+    _torch()
+    made = [_make(k, s) for k, s in enumerate(REQS[:3])]
+    srv = xorsat.Server(hbm_budget_bytes=1 << 30, max_pending=2)
+    t = [srv.submit(h, cfg) for _, h, cfg in made[:2]]
+    with pytest.raises(xorsat.XsError) as e:
+        srv.submit(made[2][1], made[2][2])
+    assert e.value.status == xorsat.XS_STATUS_CODES["XS_EAGAIN"]
+    srv.step()  # admits both
+    t.append(srv.submit(made[2][1], made[2][2]))
+    done = []
+    for _ in range(10000):
+        active = srv.step()
+        done += srv.poll()
+        if active == 0:
+            break
+    done += srv.poll()
+    by = {c.ticket: c for c in done}
+    for k, tk in enumerate(t):
+        _, fh, en = _alone(made[k][1], made[k][2])[1:]
+        assert by[tk].status == 0
+        assert np.array_equal(by[tk].outputs["first_hit"], fh)
+        assert np.array_equal(by[tk].outputs["energy"], en)
+    srv.close()
+
+
 def test_autotune_is_result_neutral():
     torch = _torch()
     inst = planted_instance(128, 17)
