@@ -32,6 +32,8 @@
 // (k >= 1) over all visited spins is zero iff C_t has E = -N. If C_t has an unsatisfied triplet,
 // the first visited spin of any unsatisfied triplet still sees it (every spin before it had
 // k = 0 and kept its value), so the OR is one; if C_t is a ground state nothing moves.
+#include <atomic>
+
 #include "xs_internal.h"
 
 #include "../../include/xorsat.h"
@@ -658,13 +660,18 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
 template <int NT, int CW, bool GR, bool MET>
 hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            size_t lds_bytes, hipStream_t s) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(qg_chunk<NT, CW, GR, MET>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    // The 160 KB dynamic-LDS limit is set once per device (bit d of the mask; setting it twice
+    // from racing threads is harmless).
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = uint64_t(1) << (dev & 63);
+    if (!(attr_set.load(std::memory_order_acquire) & bit)) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_chunk<NT, CW, GR, MET>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.fetch_or(bit, std::memory_order_release);
     }
     hipLaunchKernelGGL((qg_chunk<NT, CW, GR, MET>), dim3(n_tiles), dim3(NT), lds_bytes, s,
                        d_insts, d_tiles);
