@@ -85,6 +85,8 @@ def parse():
                          "update order, so it changes trajectories, not the dynamics")
     ap.add_argument("--paper-instances", type=int, default=100, help="paper: N = 128 instances")
     ap.add_argument("--paper-runs", type=int, default=16, help="paper: runs per N = 128 instance")
+    ap.add_argument("--paper-clones", type=int, default=327680,
+                    help="paper: clones per run (the paper's 327,680 by default)")
     ap.add_argument("--paper-timeout-instances", type=int, default=32,
                     help="paper: N = 256 instances, one capped run each")
     ap.add_argument("--paper-timeout-sweeps", type=int, default=2000000,
@@ -462,9 +464,9 @@ def workload_w1scan(args, xorsat, torch):
 
 
 def workload_paper(args, xorsat, torch):
-    """The paper's headline quantity on synthetic planted instances at its clone count
-    (Section "Numerical results", Table 1: TTS_99 of the median instance, 327,680 clones, w1 =
-    0.055, one run on the GPU at a time). N = 128: every run to its first ground state, tau of an
+    """The paper's headline quantity on synthetic planted instances (Section "Numerical
+    results", Table 1: TTS_99 of the median instance, 327,680 clones, w1 = 0.055, one run on the
+    GPU at a time), at the paper's clone count unless --paper-clones says otherwise. N = 128: every run to its first ground state, tau of an
     instance = mean wall time of its runs, TTS_99 = ln(100) tau. N = 256: runs capped at a short
     timeout (Section "Running with a short timeout"); with few successes per instance the
     instances are pooled into one posterior (inverse-gamma with shape = successes and scale =
@@ -472,8 +474,8 @@ def workload_paper(args, xorsat, torch):
     from paper_2102_09510_amd import tts_stats as ts
     from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance
 
-    ncl = 327680
-    out = {"metric": "TTS_99 (s) of the median instance, 327,680 clones, w1 = 0.055",
+    ncl = args.paper_clones
+    out = {"metric": f"TTS_99 (s) of the median instance, {ncl} clones, w1 = 0.055",
            "config": {"workload": "planted instances, one run at a time"}}
     # N = 128: full runs
     n, count, runs = 128, args.paper_instances, args.paper_runs
