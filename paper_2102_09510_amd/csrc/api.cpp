@@ -158,7 +158,7 @@ void build_triplets(xs_instance &I) {
     }
 }
 
-xs_status ensure_tables(xs_instance *I, int device, DeviceTables *out) {
+xs_status ensure_tables(const xs_instance *I, int device, DeviceTables *out) {
     std::lock_guard<std::mutex> lock(I->mu);
     auto it = I->dev.find(device);
     if (it != I->dev.end()) {
@@ -183,7 +183,7 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
                         int device) {
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
-        xs_instance *I = const_cast<xs_instance *>(insts[k]);
+        const xs_instance *I = insts[k];
         const uint32_t cap = step_cap(d);
         std::lock_guard<std::mutex> lock(I->mu);
         auto hit = I->sched.find(cap);
@@ -494,7 +494,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         xs_status st = validate_run(insts[k], &cfgs[k], &bufs[k], true);
         if (st != XS_OK) return st;
         DeviceTables t;
-        st = ensure_tables(const_cast<xs_instance *>(insts[k]), device, &t);
+        st = ensure_tables(insts[k], device, &t);
         if (st != XS_OK) return st;
         fill_desc(insts[k], cfgs[k], t, bufs[k].state, bufs[k].first_hit, bufs[k].energy, h[k]);
     }
@@ -737,6 +737,7 @@ xs_status xs_instance_get_info(const xs_instance *I, xs_instance_info *info) {
     info->n_classes = (int32_t)I->class_off.size() - 1;
     info->colour_cap = I->cap;
     info->max_class = I->max_class;
+    std::lock_guard<std::mutex> lock(I->mu);
     const xsh::HostSched &lv = I->sched.at(0u);
     info->n_levels = (int32_t)lv.off.size() - 1;
     info->max_level = lv.max_step;
@@ -753,10 +754,9 @@ xs_status xs_instance_get_partition(const xs_instance *I, int32_t *perm, int32_t
 xs_status xs_instance_get_schedule(const xs_instance *I, uint32_t step_cap, int32_t *order,
                                    int32_t *step_off, int32_t *n_steps) {
     if (!I || !order || !step_off || !n_steps) return fail(XS_EINVAL, "null argument");
-    xs_instance *M = const_cast<xs_instance *>(I);
-    std::lock_guard<std::mutex> lock(M->mu);
-    auto it = M->sched.find(step_cap);
-    if (it == M->sched.end()) it = M->sched.emplace(step_cap, make_schedule(*M, step_cap)).first;
+    std::lock_guard<std::mutex> lock(I->mu);
+    auto it = I->sched.find(step_cap);
+    if (it == I->sched.end()) it = I->sched.emplace(step_cap, make_schedule(*I, step_cap)).first;
     const xsh::HostSched &hs = it->second;
     std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
     std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());

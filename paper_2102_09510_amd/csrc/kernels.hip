@@ -182,7 +182,7 @@ __device__ __forceinline__ uint32_t lds_base() {
 // clones); `col` is this thread's column, fixed because the workgroup size is a multiple of the
 // column count.
 struct Tile {
-    const InstDev *I;
+    InstDev *I;
     const uint4 *grec;   // records in global memory (GR kernels), offsets for this tile's rows
     uint32_t n, W, B, lB, rowb, ncol, lcol, n16, l16, ngrp, blk0, tid, col;
     uint32_t st;         // state rows (records start at 0)
@@ -376,7 +376,7 @@ __device__ __forceinline__ uint32_t record_hits(const Tile &T, uint32_t t, uint3
             fh[__builtin_ctz(fresh)] = (int32_t)t;
             fresh &= fresh - 1;
         }
-        atomicOr(const_cast<uint32_t *>(&T.I->hit), 1u);
+        atomicOr(&T.I->hit, 1u);
     }
     return out;
 }
@@ -431,12 +431,12 @@ __device__ __forceinline__ void store_state(const Tile &T) {
 // MET (w0 > 0): a ground state can be left again, so no sweep is tested; the final pass tests
 // the end configuration only.
 template <int NT, int CW, bool GR, bool MET>
-__global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts,
+__global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
                                                const uint2 *__restrict__ tiles) {
     constexpr int G = CW / 4;        // groups per column
     constexpr int LG = G == 4 ? 2 : G == 2 ? 1 : 0;
     const uint2 tile = tiles[blockIdx.x];
-    const InstDev *I = insts + tile.x;
+    InstDev *I = insts + tile.x;
     if (I->done) return;
     const uint32_t t0 = I->t_cur;
     const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(const InstDev *__restrict__ insts
                 if (T.tid < T.ngrp) record_hits(T, t, hm_replay);
                 if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
             }
-            if (T.tid == 0) atomicOr(const_cast<uint32_t *>(&I->track), 1u);
+            if (T.tid == 0) atomicOr(&I->track, 1u);
         }
     }
     __syncthreads();
@@ -650,15 +650,15 @@ size_t chunk_lds_bytes(uint32_t n, uint32_t B, bool rec_global, bool met) {
            2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16;
 }
 
-hipError_t launch_init(const InstDev *d_inst, const InstDev &h, hipStream_t s) {
+hipError_t launch_init(InstDev *d_inst, const InstDev &h, hipStream_t s) {
     const uint64_t total = (uint64_t)h.n * ((h.n_words >> 1) + 1);
     const uint32_t blocks = (uint32_t)((total + 255) / 256);
-    hipLaunchKernelGGL(qg_init, dim3(blocks), dim3(256), 0, s, const_cast<InstDev *>(d_inst));
+    hipLaunchKernelGGL(qg_init, dim3(blocks), dim3(256), 0, s, d_inst);
     return hipGetLastError();
 }
 
 template <int NT, int CW, bool GR, bool MET>
-hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+hipError_t launch_chunk_nt(InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            size_t lds_bytes, hipStream_t s) {
     // The 160 KB dynamic-LDS limit is set once per device (bit d of the mask; setting it twice
     // from racing threads is harmless).
@@ -679,7 +679,7 @@ hipError_t launch_chunk_nt(const InstDev *d_insts, const uint2 *d_tiles, int n_t
 }
 
 template <int CW, bool GR, bool MET>
-hipError_t launch_chunk_cw(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+hipError_t launch_chunk_cw(InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            int threads, size_t lds_bytes, hipStream_t s) {
     switch (threads) {
         case 64: return launch_chunk_nt<64, CW, GR, MET>(d_insts, d_tiles, n_tiles, lds_bytes, s);
@@ -693,7 +693,7 @@ hipError_t launch_chunk_cw(const InstDev *d_insts, const uint2 *d_tiles, int n_t
 }
 
 template <bool GR, bool MET>
-hipError_t launch_chunk_gr(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
+hipError_t launch_chunk_gr(InstDev *d_insts, const uint2 *d_tiles, int n_tiles,
                            int threads, int col_bytes, size_t lds_bytes, hipStream_t s) {
     switch (col_bytes) {
         case 4:
@@ -706,7 +706,7 @@ hipError_t launch_chunk_gr(const InstDev *d_insts, const uint2 *d_tiles, int n_t
     }
 }
 
-hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
+hipError_t launch_chunk(InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
                         int col_bytes, bool rec_global, bool met, size_t lds_bytes,
                         hipStream_t s) {
     if (met)

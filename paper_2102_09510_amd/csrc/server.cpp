@@ -101,7 +101,7 @@ struct xs_server {
                 continue;
             }
             xsh::DeviceTables t;
-            xs_status st = xsh::ensure_tables(const_cast<xs_instance *>(r->inst), device, &t);
+            xs_status st = xsh::ensure_tables(r->inst, device, &t);
             if (st != XS_OK) return st;
             XS_HIP(hipMalloc(&r->mem, r->bytes));
             const size_t n = (size_t)r->inst->n, nc = r->cfg.n_clones;

@@ -43,11 +43,12 @@ struct xs_instance {
     std::vector<int8_t> J;           // [n]
     std::vector<int32_t> perm;       // update order
     std::vector<int32_t> class_off;  // [n_classes + 1]
-    std::map<uint32_t, xsh::HostSched> sched;  // per step cap (0: uncapped levels)
+    // Caches filled on first use (under mu), so they may change behind a const instance.
+    mutable std::map<uint32_t, xsh::HostSched> sched;  // per step cap (0: uncapped levels)
     std::vector<uint16_t> tri16;     // [n][4]: a, b, c, j
     int32_t max_class = 0;
-    std::mutex mu;
-    std::map<int, xsh::DeviceTables> dev;  // per HIP device
+    mutable std::mutex mu;
+    mutable std::map<int, xsh::DeviceTables> dev;  // per HIP device
 };
 
 // Return XS_EDEVICE (with the HIP message) from the enclosing function if a HIP call fails.
@@ -63,7 +64,7 @@ namespace xsh {
 // Set the calling thread's last error message and return st.
 xs_status fail(xs_status st, const char *fmt, ...);
 // Device tables of an instance on `device`, uploaded on first use.
-xs_status ensure_tables(xs_instance *I, int device, DeviceTables *out);
+xs_status ensure_tables(const xs_instance *I, int device, DeviceTables *out);
 // Check a run configuration and its buffers (state buffer ignored if check_buffers is false).
 xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b,
                        bool check_buffers);

@@ -44,12 +44,12 @@ struct InstDev {
 
 // Launch wrappers implemented in kernels.hip (C++ linkage, internal to the library).
 namespace xs {
-hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
+hipError_t launch_init(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
 // threads: 64, 128, 256, 512 or 1024, at least 8 * tile_blocks of every tile it runs;
 // col_bytes: 4, 8 or 16 bytes of a spin row per task; rec_global: every tile's instance has
 // grec set (records in global memory), else records are staged in LDS; met: every tile's
 // instance has thr0 > 0 (w0 rule, no ground-state tracking).
-hipError_t launch_chunk(const InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
+hipError_t launch_chunk(InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int threads,
                         int col_bytes, bool rec_global, bool met, size_t lds_bytes,
                         hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
