@@ -39,6 +39,12 @@
  *     where C_t is the configuration before sweep t, or -1. With thr0 > 0 a ground state can be
  *     left again, and only the final configuration is tested: first_hit = the end sweep if it
  *     has E = -N, else -1.
+ *
+ * Parity unpinned (or_run, or_trace): the exact trajectories for 0 < w1 < 1 follow from the
+ * random-number reading above, which the paper does not fix; the tests pin the rule itself
+ * (per update, the deterministic w1 = 0 and w1 = 1 sweeps worked by hand, acceptance
+ * frequencies, the energy change per flip, the absorbing ground state, the paramagnetic energy
+ * of the w0 = w1^3 rule), not the stochastic trajectories.
  */
 #include <stdint.h>
 #include <stdlib.h>
