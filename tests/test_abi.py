@@ -8,6 +8,8 @@ import re
 
 import numpy as np
 import pytest
+from hypothesis import given, settings
+from hypothesis import strategies as st
 
 import oracle
 from paper_2102_09510_amd import xorsat
@@ -126,3 +128,62 @@ def test_tune_table_roundtrip(lib, tmp_path):
     with pytest.raises(xorsat.XsError) as e:
         xorsat.tune_load(str(tmp_path / "missing.txt"))
     assert e.value.status == 5
+
+
+@settings(max_examples=150, deadline=None)
+@given(st.data())
+def test_instance_create_fuzz(lib, data):
+    """Random triplet lists (valid or not): creation either succeeds, and then the partition is
+    the oracle's and the schedule covers every spin, or fails with XS_EINVAL; never anything
+    else."""
+    n = data.draw(st.integers(4, 40))
+    m = data.draw(st.sampled_from([n, n, n, n - 1, n + 1]))
+    tri = np.array(data.draw(st.lists(st.lists(st.integers(-1, n), min_size=3, max_size=3),
+                                      min_size=max(m, 1), max_size=max(m, 1))),
+                   dtype=np.int32).reshape(-1, 3)[:m]
+    J = np.array(data.draw(st.lists(st.sampled_from([1, -1, 1, -1, 0]), min_size=m,
+                                    max_size=m)), dtype=np.int8)
+    cap = data.draw(st.integers(0, 40))
+    try:
+        h = xorsat.Instance(tri, J, colour_cap=cap)
+    except xorsat.XsError as e:
+        assert e.status == 1
+        return
+    # accepted: it must be a valid 3-regular instance
+    assert m == n and set(np.unique(J)) <= {1, -1}
+    assert np.all(np.bincount(tri.ravel(), minlength=n) == 3)
+    perm, off = h.partition()
+    operm, ooff = oracle.colour(tri, cap or 32)
+    assert np.array_equal(perm, operm) and np.array_equal(off, ooff)
+    order, soff = h.schedule(0)
+    assert sorted(order.tolist()) == list(range(n)) and soff[-1] == n
+    h.close()
+
+
+@settings(max_examples=100, deadline=None)
+@given(n=st.integers(4, 300), seed=st.integers(0, 10**6), cap=st.integers(0, 64),
+       mutate=st.sampled_from(["none", "none", "index", "spin", "coupling"]),
+       where=st.integers(0, 10**6))
+def test_instance_create_mutations(lib, n, seed, cap, mutate, where):
+    """Planted instances with at most one corrupted entry: valid ones are accepted with the
+    oracle's partition, corrupted ones (a spin out of range or repeated, a coupling not +-1)
+    are rejected with XS_EINVAL."""
+    inst = planted_instance(n, seed)
+    tri, J = inst.tri.copy(), inst.J.copy()
+    t, q = where % n, (where // n) % 3
+    if mutate == "index":
+        tri[t, q] = n + where % 3
+    elif mutate == "spin":
+        tri[t, q] = tri[t, (q + 1) % 3]
+    elif mutate == "coupling":
+        J[t] = 0
+    if mutate != "none":
+        with pytest.raises(xorsat.XsError) as e:
+            xorsat.Instance(tri, J, colour_cap=cap)
+        assert e.value.status == 1
+        return
+    h = xorsat.Instance(tri, J, colour_cap=cap)
+    perm, off = h.partition()
+    operm, ooff = oracle.colour(tri, cap or 32)
+    assert np.array_equal(perm, operm) and np.array_equal(off, ooff)
+    h.close()
