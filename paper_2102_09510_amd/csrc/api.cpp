@@ -327,7 +327,8 @@ struct RunOpts {
     double *kernel_ms = nullptr;   // if set: time every sweep-chunk launch, add the sum here
 };
 
-// Tuned (tile_blocks, wg_threads) per workload key, filled by xs_autotune or xs_tune_load.
+// Tuned launch knobs (tile_blocks, wg_threads, col_bytes, rec_global) per workload key,
+// filled by xs_autotune or xs_tune_load.
 struct TuneKey {
     uint32_t n_bucket, clones, count_bucket;
     bool operator<(const TuneKey &o) const {
