@@ -206,7 +206,9 @@ typedef struct xs_server xs_server;
 typedef struct {
     uint32_t struct_size;
     uint32_t max_resident;     /* requests resident at once (0 = no limit besides memory) */
-    uint64_t hbm_budget_bytes; /* device bytes the resident requests may hold */
+    uint64_t hbm_budget_bytes; /* device bytes the resident requests may hold; reserved as one
+                                  allocation at the first admission and sub-allocated from then
+                                  on (no device allocation while serving) */
     uint32_t max_pending;      /* queued, not yet admitted requests (0 = no limit); a submit
                                   beyond it returns XS_EAGAIN (back-pressure) */
     uint32_t reserved;         /* must be 0 */

@@ -7,6 +7,7 @@
 #include <climits>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <vector>
 
 #include "../../include/xorsat.h"
@@ -36,6 +37,57 @@ struct Request {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// First-fit sub-allocator over one device allocation of the server's whole memory budget, so
+// that admitting and completing requests never calls the device allocator. Free ranges are
+// kept by offset and merged with their neighbours on release. Sizes are multiples of 256.
+class DevicePool {
+  public:
+    ~DevicePool() {
+        if (base_) (void)hipFree(base_);
+    }
+    // Allocate the budget on first use.
+    xs_status reserve(size_t bytes) {
+        if (base_) return XS_OK;
+        XS_HIP(hipMalloc(&base_, bytes));
+        size_ = bytes;
+        free_[0] = bytes;
+        return XS_OK;
+    }
+    // Offset of a free range of `bytes`, or false if none is large enough now.
+    bool alloc(size_t bytes, uint8_t **out) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > bytes) free_[off + bytes] = len - bytes;
+            *out = base_ + off;
+            return true;
+        }
+        return false;
+    }
+    void release(uint8_t *p, size_t bytes) {
+        size_t off = (size_t)(p - base_), len = bytes;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + len == next->first) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += len;
+                return;
+            }
+        }
+        free_[off] = len;
+    }
+
+  private:
+    uint8_t *base_ = nullptr;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
 size_t footprint(const xs_instance *I, const xs_run_config &c) {
     const size_t n = (size_t)I->n, nc = c.n_clones;
     return align256(n * nc / 8) + 2 * align256(4 * nc) + align256(n);
@@ -54,13 +106,11 @@ struct xs_server {
     xs_server_stats stats{};
     uint8_t *scratch = nullptr;  // descriptors | tiles | active counter
     size_t scratch_bytes = 0;
+    DevicePool pool;             // the resident requests' device memory
 
     ~xs_server() {
         for (Request *r : pending) delete r;
-        for (Request *r : resident) {
-            if (r->mem) (void)hipFree(r->mem);
-            delete r;
-        }
+        for (Request *r : resident) delete r;
         if (scratch) (void)hipFree(scratch);
     }
 
@@ -77,7 +127,7 @@ struct xs_server {
 
     void release(Request *r) {
         if (r->mem) {
-            (void)hipFree(r->mem);
+            pool.release(r->mem, r->bytes);
             r->mem = nullptr;
             stats.bytes_in_use -= r->bytes;
         }
@@ -93,17 +143,22 @@ struct xs_server {
                 continue;
             }
             if (cfg.max_resident && resident.size() >= cfg.max_resident) break;
-            if (stats.bytes_in_use + r->bytes > cfg.hbm_budget_bytes) {
-                if (!resident.empty()) break;  // wait for memory to free up
-                pending.pop_front();           // can never fit
+            if (r->bytes > cfg.hbm_budget_bytes) {  // can never fit
+                pending.pop_front();
                 complete(r, XS_ENOMEM, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0, 0});
                 delete r;
                 continue;
             }
-            xsh::DeviceTables t;
-            xs_status st = xsh::ensure_tables(r->inst, device, &t);
+            xs_status st = pool.reserve(align256(cfg.hbm_budget_bytes));
             if (st != XS_OK) return st;
-            XS_HIP(hipMalloc(&r->mem, r->bytes));
+            if (!pool.alloc(r->bytes, &r->mem)) break;  // wait for memory to free up
+            xsh::DeviceTables t;
+            st = xsh::ensure_tables(r->inst, device, &t);
+            if (st != XS_OK) {
+                pool.release(r->mem, r->bytes);
+                r->mem = nullptr;
+                return st;
+            }
             const size_t n = (size_t)r->inst->n, nc = r->cfg.n_clones;
             uint64_t *state = reinterpret_cast<uint64_t *>(r->mem);
             int32_t *fh = reinterpret_cast<int32_t *>(r->mem + align256(n * nc / 8));
@@ -213,6 +268,7 @@ struct xs_server {
                 XS_HIP(hipStreamSynchronize(stream));
             }
             std::vector<Request *> still;
+            std::vector<std::pair<Request *, xs_run_result>> ended;
             for (int k = 0; k < R; ++k) {
                 Request *r = resident[k];
                 r->desc = h[k];
@@ -244,10 +300,13 @@ struct xs_server {
                 if (r->outs.solved && d.winner != INT32_MAX)
                     XS_HIP(hipMemcpyAsync(r->outs.solved, d.solved, n, hipMemcpyDeviceToHost,
                                           stream));
-                XS_HIP(hipStreamSynchronize(stream));
-                release(r);
-                complete(r, XS_OK, res);
-                delete r;
+                ended.emplace_back(r, res);
+            }
+            if (!ended.empty()) XS_HIP(hipStreamSynchronize(stream));  // outputs copied
+            for (auto &e : ended) {
+                release(e.first);
+                complete(e.first, XS_OK, e.second);
+                delete e.first;
             }
             resident.swap(still);
         }
