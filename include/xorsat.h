@@ -146,6 +146,9 @@ typedef struct {
  *              which the clone's configuration (before sweep t) has E = -N, else -1. Required.
  *   energy     device, int32 [n_clones] or NULL: E = 2U - N at the end sweep.
  *   solved     host, int8 [n] or NULL: spins (+1/-1) of the winning clone (unchanged if none).
+ * The device buffers must be addressable by the kernels (device or managed memory, or host
+ * memory mapped at the same address); anything else is rejected with XS_EINVAL before any
+ * launch.
  */
 typedef struct {
     uint64_t *state;

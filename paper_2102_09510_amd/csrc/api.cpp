@@ -246,6 +246,18 @@ uint32_t max_tile_blocks(uint32_t n, uint32_t n_blocks, uint32_t max_nb) {
 // CUs.
 constexpr size_t kTargetTiles = 1024;
 
+// True if the kernels can address p: device or managed memory, or host memory mapped for the
+// device at the same address.
+bool device_addressable(const void *p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // an unknown host pointer: clear the error it leaves
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged ||
+           a.type == hipMemoryTypeUnified || a.devicePointer == p;
+}
+
 xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_run_buffers *b,
                        bool check_buffers) {
     if (!I || !cfg || !b) return fail(XS_EINVAL, "null argument");
@@ -271,6 +283,9 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
             return fail(XS_EINVAL, "state and first_hit are required");
         if (((uintptr_t)b->state & 15) != 0)
             return fail(XS_EINVAL, "state must be 16-byte aligned");
+        if (!device_addressable(b->state) || !device_addressable(b->first_hit) ||
+            (b->energy && !device_addressable(b->energy)))
+            return fail(XS_EINVAL, "state, first_hit and energy must be device memory");
     }
     const uint32_t nb = cfg->n_clones / 256;
     if (cfg->tile_blocks) {

@@ -267,9 +267,10 @@ def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
     n, nc = inst.n, cfg.n_clones
     if state is None:
         state = torch.empty((n, nc // 64), dtype=torch.int64, device=device)
-    else:
-        assert state.dtype == torch.int64 and tuple(state.shape) == (n, nc // 64)
-        assert state.is_contiguous()
+    elif (state.dtype != torch.int64 or tuple(state.shape) != (n, nc // 64)
+          or not state.is_contiguous() or state.device.type != "cuda"):
+        raise ValueError(f"state must be a contiguous int64 device tensor of shape "
+                         f"({n}, {nc // 64})")
     first_hit = torch.empty(nc, dtype=torch.int32, device=device)
     energy = torch.empty(nc, dtype=torch.int32, device=device) if want_energy else None
     solved = np.zeros(n, dtype=np.int8)

@@ -356,3 +356,27 @@ def test_metropolis_full_size_paramagnetic_energy(T):
     groups = rng.choice(clones // 32, size=3, replace=False)
     sample = np.sort(np.concatenate([32 * g + np.arange(32) for g in groups]))
     assert_parity(inst, h, cfg, out, clones=sample)
+
+
+def test_host_buffers_rejected_before_launch():
+    """A state buffer in ordinary host memory is refused by the library (XS_EINVAL, nothing
+    launched), and the binding refuses a CPU tensor before calling it."""
+    import ctypes
+    torch = _torch()
+    inst = planted_instance(64, 3)
+    h = xorsat.Instance(inst.tri, inst.J)
+    cfg = xorsat.make_config(n_clones=256, seed=1, max_sweeps=5)
+    host_state = np.zeros((64, 4), dtype=np.int64)
+    fh = torch.empty(256, dtype=torch.int32, device="cuda")
+    bufs = xorsat.RunBuffers(host_state.ctypes.data, fh.data_ptr(), None, None)
+    res = xorsat.RunResult()
+    lib = xorsat.load()
+    st = lib.xs_run(h.handle, ctypes.byref(cfg), ctypes.byref(bufs), xorsat._stream(),
+                    ctypes.byref(res))
+    assert st == xorsat.XS_STATUS_CODES["XS_EINVAL"]
+    assert "device memory" in lib.xs_last_error().decode()
+    with pytest.raises(ValueError):
+        xorsat.run(h, cfg, state=torch.zeros((64, 4), dtype=torch.int64))
+    # the device is still fine
+    out = xorsat.run(h, cfg)
+    assert out.sweeps_done <= 5
