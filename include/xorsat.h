@@ -192,6 +192,20 @@ xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_
                        const xs_run_buffers *bufs, void *stream, xs_run_result *results);
 
 /*
+ * The same batch without blocking the caller: the arguments are checked and copied, the run is
+ * driven from a library thread on `stream` (current device of the caller), and xs_wait blocks
+ * until it ended, fills results[] and releases the handle (call it exactly once). Until then the
+ * instances, buffers and results[] must stay alive and untouched, and the caller must not use
+ * `stream`. Errors found before the run starts are returned here (no handle); errors during
+ * the run are returned by xs_wait, with the message in its thread's xs_last_error.
+ */
+typedef struct xs_pending xs_pending;
+xs_status xs_run_batch_async(int32_t count, const xs_instance *const *insts,
+                             const xs_run_config *cfgs, const xs_run_buffers *bufs, void *stream,
+                             xs_run_result *results, xs_pending **out);
+xs_status xs_wait(xs_pending *pending);
+
+/*
  * Server: continuous batching of many runs on one device. Requests are queued by
  * xs_server_submit; each xs_server_step admits queued requests in arrival order while their
  * device footprint (state n*n_clones/8 bytes, first_hit and energy 4*n_clones bytes each, n

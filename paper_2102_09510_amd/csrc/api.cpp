@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -938,6 +939,68 @@ xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_
                        const xs_run_buffers *bufs, void *stream, xs_run_result *results) {
     return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results,
                      RunOpts{});
+}
+
+}  // extern "C"
+
+struct xs_pending {
+    std::vector<const xs_instance *> insts;
+    std::vector<xs_run_config> cfgs;
+    std::vector<xs_run_buffers> bufs;
+    xs_run_result *results = nullptr;
+    xs_status status = XS_OK;
+    std::string error;
+    std::thread worker;
+};
+
+extern "C" {
+
+xs_status xs_run_batch_async(int32_t count, const xs_instance *const *insts,
+                             const xs_run_config *cfgs, const xs_run_buffers *bufs, void *stream,
+                             xs_run_result *results, xs_pending **out) {
+    if (!out) return fail(XS_EINVAL, "null argument");
+    *out = nullptr;
+    if (count <= 0 || !insts || !cfgs || !bufs || !results)
+        return fail(XS_EINVAL, "empty or null batch");
+    for (int k = 0; k < count; ++k) {
+        xs_status st = validate_run(insts[k], &cfgs[k], &bufs[k], true);
+        if (st != XS_OK) return st;
+    }
+    int device = 0;
+    XS_HIP(hipGetDevice(&device));
+    xs_pending *p = new (std::nothrow) xs_pending;
+    if (!p) return fail(XS_ENOMEM, "host allocation failed");
+    p->insts.assign(insts, insts + count);
+    p->cfgs.assign(cfgs, cfgs + count);
+    p->bufs.assign(bufs, bufs + count);
+    p->results = results;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    try {
+        p->worker = std::thread([p, device, s]() {
+            if (hipSetDevice(device) != hipSuccess) {
+                p->status = XS_EDEVICE;
+                p->error = "hipSetDevice failed in the run thread";
+                return;
+            }
+            p->status = run_batch((int32_t)p->insts.size(), p->insts.data(), p->cfgs.data(),
+                                  p->bufs.data(), s, p->results, RunOpts{});
+            if (p->status != XS_OK) p->error = g_last_error;
+        });
+    } catch (...) {
+        delete p;
+        return fail(XS_ENOMEM, "could not start the run thread");
+    }
+    *out = p;
+    return XS_OK;
+}
+
+xs_status xs_wait(xs_pending *p) {
+    if (!p) return fail(XS_EINVAL, "null argument");
+    p->worker.join();
+    const xs_status st = p->status;
+    if (st != XS_OK) g_last_error = p->error;
+    delete p;
+    return st;
 }
 
 }  // extern "C"

@@ -28,7 +28,8 @@ XS_CLONE_QUANTUM = 256
 EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_create",
            "xs_instance_destroy", "xs_instance_get_info", "xs_instance_get_partition",
            "xs_instance_get_schedule",
-           "xs_run", "xs_run_batch", "xs_profile_enable", "xs_profile_read",
+           "xs_run", "xs_run_batch", "xs_run_batch_async", "xs_wait",
+           "xs_profile_enable", "xs_profile_read",
            "xs_autotune", "xs_tune_save", "xs_tune_load", "xs_tune_clear",
            "xs_server_create", "xs_server_destroy", "xs_server_submit", "xs_server_step",
            "xs_server_poll", "xs_server_cancel", "xs_server_get_stats"]
@@ -144,6 +145,10 @@ def load():
     lib.xs_run.restype = i32
     lib.xs_run_batch.argtypes = [i32, P, P, P, P, P]
     lib.xs_run_batch.restype = i32
+    lib.xs_run_batch_async.argtypes = [i32, P, P, P, P, P, ctypes.POINTER(P)]
+    lib.xs_run_batch_async.restype = i32
+    lib.xs_wait.argtypes = [P]
+    lib.xs_wait.restype = i32
     lib.xs_autotune.argtypes = [P, ctypes.c_uint32, i32, P, ctypes.POINTER(TuneResult)]
     lib.xs_autotune.restype = i32
     lib.xs_tune_save.argtypes = [ctypes.c_char_p]
@@ -315,6 +320,38 @@ def run_batch(insts: list[Instance], cfgs: list[RunConfig], *, states=None,
     res_arr = (RunResult * count)()
     _check(load().xs_run_batch(count, handles, cfg_arr, buf_arr, _stream(), res_arr))
     return [_output(res_arr[k], *made[k][1:]) for k in range(count)]
+
+
+class Pending:
+    """An asynchronous batch (xs_run_batch_async): keeps the buffers alive until wait()."""
+
+    def __init__(self, handle, made, res_arr):
+        self._h, self._made, self._res = handle, made, res_arr
+
+    def wait(self) -> list[RunOutput]:
+        if self._h is None:
+            raise RuntimeError("already waited")
+        h, self._h = self._h, None
+        _check(load().xs_wait(h))
+        return [_output(self._res[k], *self._made[k][1:]) for k in range(len(self._made))]
+
+
+def run_batch_async(insts: list[Instance], cfgs: list[RunConfig], *, want_energy: bool = True,
+                    device="cuda", stream=None) -> Pending:
+    """xs_run_batch_async: returns at once; Pending.wait() gives the outputs. `stream` (a torch
+    stream) must not be used until then; default: the current stream."""
+    count = len(insts)
+    assert count == len(cfgs) and count > 0
+    made = [_buffers(i, c, None, want_energy, device) for i, c in zip(insts, cfgs)]
+    handles = (ctypes.c_void_p * count)(*[i.handle.value for i in insts])
+    cfg_arr = (RunConfig * count)(*cfgs)
+    buf_arr = (RunBuffers * count)(*[m[0] for m in made])
+    res_arr = (RunResult * count)()
+    s = _stream() if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    h = ctypes.c_void_p()
+    _check(load().xs_run_batch_async(count, handles, cfg_arr, buf_arr, s, res_arr,
+                                     ctypes.byref(h)))
+    return Pending(h, made, res_arr)
 
 
 def profile_enable(on: bool = True):

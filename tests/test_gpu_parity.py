@@ -380,3 +380,37 @@ def test_host_buffers_rejected_before_launch():
     # the device is still fine
     out = xorsat.run(h, cfg)
     assert out.sweeps_done <= 5
+
+
+def test_async_batches_equal_sync():
+    """Two asynchronous batches on two streams, driven from library threads while the host
+    keeps working, give the same results as the synchronous batch."""
+    torch = _torch()
+    sizes = [(48, 512), (100, 2048), (256, 4096)]
+    hs, cfgs = [], []
+    for k, (n, nc) in enumerate(sizes):
+        inst = planted_instance(n, 7700 + k)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        cfgs.append(xorsat.make_config(n_clones=nc, seed=31 + k, instance_id=k,
+                                       max_sweeps=400 if n < 100 else 60, stop_on_first=n < 100,
+                                       chunk_sweeps=20))
+    sync = xorsat.run_batch(hs, cfgs)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = xorsat.run_batch_async(hs, cfgs, stream=s1)
+    b = xorsat.run_batch_async(hs[::-1], cfgs[::-1], stream=s2)
+    busy = sum(range(100000))  # host work meanwhile
+    ra, rb = a.wait(), b.wait()[::-1]
+    assert busy > 0
+    for x, y, z in zip(sync, ra, rb):
+        for o in (y, z):
+            assert torch.equal(o.state, x.state)
+            assert torch.equal(o.first_hit, x.first_hit)
+            assert torch.equal(o.energy, x.energy)
+            assert (o.tts_sweeps, o.winner_clone, o.end_sweep) == \
+                (x.tts_sweeps, x.winner_clone, x.end_sweep)
+    with pytest.raises(RuntimeError):
+        a.wait()
+    # argument errors come back from the call itself, before any thread starts
+    bad = xorsat.make_config(n_clones=300, seed=1)
+    with pytest.raises(xorsat.XsError):
+        xorsat.run_batch_async([hs[0]], [bad])
