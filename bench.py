@@ -155,7 +155,9 @@ def pct(v, q):
 
 
 def workload_steady(args, xorsat, torch):
-    """16 instances, N = 1024, 2^20 clones each, a fixed sweep budget (default 10^4)."""
+    """16 instances, N = 1024, 2^20 clones each, a fixed sweep budget (default 10^4). The LDS
+    rows are placed whatever the budget (a run of 10^4 sweeps would place them by itself), so
+    that short profiling runs of this workload time the same kernel."""
     from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance, run_seed
 
     count, n, clones = 16, 1024, 1 << 20
@@ -164,7 +166,7 @@ def workload_steady(args, xorsat, torch):
     hs = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
     cfgs = [xorsat.make_config(n_clones=clones, seed=run_seed(3, k), instance_id=k,
                                accept_thr=THR_PAPER, max_sweeps=sweeps, stop_on_first=False,
-                               chunk_sweeps=args.chunk) for k in range(count)]
+                               chunk_sweeps=args.chunk, place_rows=True) for k in range(count)]
     print(f"# steady: {count} x N={n} x {clones} clones, {sweeps} sweeps", file=sys.stderr, flush=True)
     xorsat.profile_read(reset=True)
     xorsat.profile_enable(True)

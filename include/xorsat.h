@@ -50,6 +50,11 @@ typedef int32_t xs_status;
 #define XS_STOP_ON_FIRST 0x1u /* stop at the end of the first chunk after which some clone
                                  is in a ground state (E = -N) */
 #define XS_RESUME 0x2u        /* state already holds the start configuration (checkpoint)     */
+#define XS_PLACE_ROWS 0x4u    /* build the LDS row placement of tiles under eight blocks even
+                                 for a short run (speed only; a host cost of a few µs per spin,
+                                 once per instance and tiling, kept for later runs). Without
+                                 it, runs of fewer than 2^32 clone-sweeps use the placement
+                                 only if it already exists. */
 
 typedef struct xs_instance xs_instance;
 
@@ -116,7 +121,7 @@ typedef struct {
     uint64_t seed;         /* Philox key */
     uint32_t n_clones;     /* > 0, multiple of XS_CLONE_QUANTUM */
     uint32_t accept_thr;   /* w1 threshold, 0 .. 65536 */
-    uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME */
+    uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS */
     uint32_t max_sweeps;   /* sweep budget of this call (0 = only check the start state) */
     uint32_t start_sweep;  /* absolute index of the first sweep (for resumed runs) */
     uint32_t chunk_sweeps; /* sweeps between stop checks, K (0 = 100, as in the paper) */

@@ -83,6 +83,132 @@ void partition(xs_instance &I) {
     }
 }
 
+// LDS row placement for one-, two- and four-block tiles. A 256-byte LDS cycle of a row access
+// serves S = 8 / B consecutive tasks' spins of a step (rows of 32·B bytes), one row each; rows
+// whose index is equal modulo S sit on the same banks and serialise. Each role (own row, the
+// six partners) of each such run of S positions is a group of rows that should fall on
+// different residues. Starting from row = spin, a local search picks a random group with an
+// excess (rows on its fullest residue minus one), and trades the residues of one of its rows on
+// the fullest residue and a random row on its emptiest one when that does not raise the summed
+// excess of the groups the two rows are in; the rows of each residue are then numbered in spin
+// order, so the map is a permutation of [0, n) (the residue counts never change). The search is
+// seeded, so the map is a fixed function of the schedule.
+std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int32_t> &roles,
+                                 int n, uint32_t S) {
+    // groups: per step, per S consecutive positions, per role
+    std::vector<int32_t> goff(1, 0), grow;
+    for (size_t st = 0; st + 1 < hs.off.size(); ++st)
+        for (int g = hs.off[st]; g < hs.off[st + 1]; g += (int)S) {
+            const int e = std::min(g + (int)S, hs.off[st + 1]);
+            for (int k = 0; k < 7; ++k) {
+                const size_t first = grow.size();
+                for (int p = g; p < e; ++p) {
+                    const int32_t r = roles[7 * (size_t)hs.order[p] + k];
+                    if (std::find(grow.begin() + first, grow.end(), r) == grow.end())
+                        grow.push_back(r);  // a row read twice in one cycle is a broadcast
+                }
+                goff.push_back((int32_t)grow.size());
+            }
+        }
+    const size_t ng = goff.size() - 1;
+    std::vector<int32_t> moff(n + 1, 0), memb;  // groups of each row
+    for (size_t q = 0; q < ng; ++q)
+        for (int32_t j = goff[q]; j < goff[q + 1]; ++j) ++moff[grow[j] + 1];
+    for (int r = 0; r < n; ++r) moff[r + 1] += moff[r];
+    memb.assign(moff[n], 0);
+    {
+        std::vector<int32_t> fillp(moff.begin(), moff.end() - 1);
+        for (size_t q = 0; q < ng; ++q)
+            for (int32_t j = goff[q]; j < goff[q + 1]; ++j) memb[fillp[grow[j]]++] = (int32_t)q;
+    }
+    // residue of each row; per group, the number of its rows on each residue (one byte each)
+    std::vector<uint8_t> col(n);
+    std::vector<uint64_t> cnt(ng, 0);
+    for (int r = 0; r < n; ++r) col[r] = (uint8_t)(r % S);
+    for (size_t q = 0; q < ng; ++q)
+        for (int32_t j = goff[q]; j < goff[q + 1]; ++j) cnt[q] += 1ull << (8 * col[grow[j]]);
+    auto most = [](uint64_t c) {
+        uint64_t m = 0;
+        for (int k = 0; k < 64; k += 8) m = std::max(m, (c >> k) & 0xFF);
+        return (int)m;
+    };
+    std::vector<uint8_t> top(ng);  // the fullest residue's count of each group
+    for (size_t q = 0; q < ng; ++q) top[q] = (uint8_t)most(cnt[q]);
+    // Change of a group's fullest count when one of its rows moves from residue f to t.
+    auto shift = [](uint64_t c, int m, int f, int t) {
+        const int nt = (int)((c >> (8 * t)) & 0xFF) + 1;
+        if (nt > m) return 1;
+        if ((int)((c >> (8 * f)) & 0xFF) < m || nt == m) return 0;
+        const uint64_t x = c ^ (0x0101010101010101ull * (uint64_t)m);  // zero bytes: count m
+        const uint64_t z = ~(((x & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full) | x) &
+                           0x8080808080808080ull;
+        return __builtin_popcountll(z) == 1 ? -1 : 0;
+    };
+    // Row r moving from residue `from` to `to`, in its groups that do not also hold row
+    // `other` (there the two rows trade residues and the counts stay): the change of the cost,
+    // and with `apply` the new counts.
+    auto move = [&](int r, int other, int from, int to, bool apply) {
+        int d = 0;
+        const uint64_t step = (1ull << (8 * to)) - (1ull << (8 * from));
+        const int32_t *o = memb.data() + moff[other], *oe = memb.data() + moff[other + 1];
+        for (int32_t j = moff[r]; j < moff[r + 1]; ++j) {
+            const int32_t q = memb[j];
+            while (o < oe && *o < q) ++o;
+            if (o < oe && *o == q) continue;
+            const int e = shift(cnt[q], top[q], from, to);
+            d += e;
+            if (apply) {
+                cnt[q] += step;
+                top[q] = (uint8_t)(top[q] + e);
+            }
+        }
+        return d;
+    };
+    uint64_t rng = 0x9E3779B97F4A7C15ull ^ (uint64_t)n;
+    auto next = [&]() {  // xorshift64*
+        rng ^= rng >> 12;
+        rng ^= rng << 25;
+        rng ^= rng >> 27;
+        return (uint32_t)((rng * 0x2545F4914F6CDD1Dull) >> 32);
+    };
+    // rows of each residue, and each row's place in its list
+    std::vector<std::vector<int32_t>> of(S);
+    std::vector<int32_t> at(n);
+    for (int r = 0; r < n; ++r) {
+        at[r] = (int32_t)of[col[r]].size();
+        of[col[r]].push_back(r);
+    }
+    // Proposals: a row on the fullest residue of a random group that has an excess, traded
+    // with a random row of the emptiest residue of that group.
+    for (int it = 0; it < 8 * n; ++it) {
+        const size_t q = next() % ng;
+        const uint64_t c = cnt[q];
+        const int mx = top[q];
+        if (mx <= 1) continue;
+        int hi = -1, lo = 0;
+        for (uint32_t k = 0; k < S; ++k) {
+            const int v = (int)((c >> (8 * k)) & 0xFF);
+            if (hi < 0 && v == mx) hi = (int)k;
+            if (v < (int)((c >> (8 * lo)) & 0xFF)) lo = (int)k;
+        }
+        int a = -1;
+        for (int32_t j = goff[q]; j < goff[q + 1] && a < 0; ++j)
+            if (col[grow[j]] == hi) a = grow[j];
+        const int b = of[lo][next() % of[lo].size()];
+        if (move(a, b, hi, lo, false) + move(b, a, lo, hi, false) > 0) continue;
+        move(a, b, hi, lo, true);
+        move(b, a, lo, hi, true);
+        col[a] = (uint8_t)lo;
+        col[b] = (uint8_t)hi;
+        std::swap(of[hi][at[a]], of[lo][at[b]]);
+        std::swap(at[a], at[b]);
+    }
+    std::vector<uint16_t> row(n);
+    std::vector<int> rank(S, 0);
+    for (int r = 0; r < n; ++r) row[r] = (uint16_t)(col[r] + S * rank[col[r]]++);
+    return row;
+}
+
 // Execution schedule of the update order. The update of a spin reads its own value and those of
 // the spins it shares a triplet with, and writes only its own, so two updates commute unless
 // their spins share a triplet. Each spin is placed in a step after every earlier spin (in update
@@ -92,8 +218,9 @@ void partition(xs_instance &I) {
 // sequential sweep. Steps are independent sets. Uncapped, there are at most as many steps as
 // classes (a member of class c has no conflicting predecessor in c, so by induction its step is
 // at most c) and far fewer when the class cap, not a shared triplet, closed the classes; the
-// cap fits the steps to the threads of a launch.
-xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap) {
+// cap fits the steps to the threads of a launch. slots > 1: the LDS rows are placed for that
+// many rows per LDS cycle.
+xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t slots) {
     const int n = I.n;
     std::vector<int32_t> inc(3 * (size_t)n), deg(n, 0), pos(n), step(n, 0), fill;
     for (int t = 0; t < n; ++t)
@@ -127,24 +254,32 @@ xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap) {
     std::vector<int32_t> next(hs.off.begin(), hs.off.end() - 1);
     hs.order.assign(n, 0);
     for (int p = 0; p < n; ++p) hs.order[next[step[I.perm[p]]]++] = I.perm[p];
-    // Records in schedule order: spin, then for each of its three triplets (ascending triplet
-    // index) the two other spins, then the three coupling bits (bit q: triplet q has J = -1).
+    // Roles of every spin: itself, then for each of its three triplets (ascending triplet index)
+    // the two other spins; and its coupling bits (bit q: triplet q has J = -1).
+    std::vector<int32_t> roles(7 * (size_t)n);
+    std::vector<uint16_t> jbits(n, 0);
+    for (int i = 0; i < n; ++i) {
+        roles[7 * (size_t)i] = i;
+        for (int q = 0; q < 3; ++q) {
+            const int t = inc[3 * i + q];
+            int k = 0;
+            for (int z = 0; z < 3; ++z)
+                if (I.tri[3 * t + z] != i) roles[7 * (size_t)i + 1 + 2 * q + k++] = I.tri[3 * t + z];
+            if (I.J[t] < 0) jbits[i] |= (uint16_t)(1u << q);
+        }
+    }
+    if (slots > 1 && n >= 2 * (int)slots) hs.rowmap = place_rows(hs, roles, n, slots);
+    // Records in schedule order: the LDS rows of the spin and of its six partners, then
+    // meta = spin | coupling bits << 13.
     hs.rec.assign(8 * (size_t)n, 0);
     for (int p = 0; p < n; ++p) {
         const int i = hs.order[p];
         uint16_t *r = &hs.rec[8 * (size_t)p];
-        r[0] = (uint16_t)i;
-        uint16_t jbits = 0;
-        for (int q = 0; q < 3; ++q) {
-            const int t = inc[3 * i + q];
-            int other[2], k = 0;
-            for (int z = 0; z < 3; ++z)
-                if (I.tri[3 * t + z] != i) other[k++] = I.tri[3 * t + z];
-            r[1 + 2 * q] = (uint16_t)other[0];
-            r[2 + 2 * q] = (uint16_t)other[1];
-            if (I.J[t] < 0) jbits |= (uint16_t)(1u << q);
+        for (int k = 0; k < 7; ++k) {
+            const int32_t u = roles[7 * (size_t)i + k];
+            r[k] = hs.rowmap.empty() ? (uint16_t)u : hs.rowmap[u];
         }
-        r[7] = jbits;
+        r[7] = (uint16_t)(i | (jbits[i] << 13));
     }
     return hs;
 }
@@ -180,6 +315,15 @@ uint32_t step_cap(const xs::InstDev &d) {
     return d.wg_threads * d.col_bytes / (32u * d.tile_blocks);
 }
 
+// Tasks whose rows one 256-byte LDS cycle serves: rows of 32 * B bytes, 256 / (32 * B) of them.
+uint32_t row_slots(uint32_t tile_blocks) { return tile_blocks < 8 ? 8u / tile_blocks : 1u; }
+
+// Schedules are kept per (step cap, row slots); caps stay below 2^16.
+uint32_t sched_key(uint32_t cap, uint32_t slots) { return cap | slots << 16; }
+
+// Clone-sweeps (clones x sweeps left) from which a run builds the row placement.
+constexpr uint64_t kPlaceMinWork = 1ull << 32;
+
 xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *insts, int count,
                         int device) {
     for (int k = 0; k < count; ++k) {
@@ -187,10 +331,20 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
         const xs_instance *I = insts[k];
         const uint32_t cap = step_cap(d);
         std::lock_guard<std::mutex> lock(I->mu);
-        auto hit = I->sched.find(cap);
-        if (hit == I->sched.end()) hit = I->sched.emplace(cap, make_schedule(*I, cap)).first;
+        uint32_t slots = row_slots(d.tile_blocks);
+        // The row placement costs about 3 µs of host time per spin and saves about 5 % of the
+        // sweep time; a run too short to pay that back uses the unplaced schedule unless the
+        // placed one already exists. Either gives the same results.
+        const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
+        if (slots > 1 && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
+            !I->sched.count(sched_key(cap, slots)))
+            slots = 1;
+        const uint32_t key = sched_key(cap, slots);
+        auto hit = I->sched.find(key);
+        if (hit == I->sched.end())
+            hit = I->sched.emplace(key, make_schedule(*I, cap, slots)).first;
         const xsh::HostSched &hs = hit->second;
-        xsh::DevSched &ds = I->dev[device].sched[cap];
+        xsh::DevSched &ds = I->dev[device].sched[key];
         if (!ds.rec) {
             const size_t n = (size_t)I->n;
             XS_HIP(hipMalloc(&ds.rec, 16 * n));
@@ -198,10 +352,15 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
             XS_HIP(hipMemcpy(ds.rec, hs.rec.data(), 16 * n, hipMemcpyHostToDevice));
             XS_HIP(hipMemcpy(ds.off, hs.off.data(), sizeof(int32_t) * hs.off.size(),
                              hipMemcpyHostToDevice));
+            if (!hs.rowmap.empty()) {
+                XS_HIP(hipMalloc(&ds.rowmap, 2 * n));
+                XS_HIP(hipMemcpy(ds.rowmap, hs.rowmap.data(), 2 * n, hipMemcpyHostToDevice));
+            }
             ds.steps = (uint32_t)hs.off.size() - 1;
         }
         d.rec = ds.rec;
         d.step_off = ds.off;
+        d.rowmap = ds.rowmap;
         d.n_steps = ds.steps;
         d.grec = nullptr;
         if (!d.rec_global) continue;
@@ -211,11 +370,10 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
             std::vector<uint32_t> g(4 * (size_t)I->n);
             for (int p = 0; p < I->n; ++p) {
                 const uint16_t *r = &hs.rec[8 * (size_t)p];
-                const uint32_t i = r[0];
-                g[4 * p + 0] = (i * rowb) | ((r[1] * rowb) << 16);
+                g[4 * p + 0] = (r[0] * rowb) | ((r[1] * rowb) << 16);
                 g[4 * p + 1] = (r[2] * rowb) | ((r[3] * rowb) << 16);
                 g[4 * p + 2] = (r[4] * rowb) | ((r[5] * rowb) << 16);
-                g[4 * p + 3] = (r[6] * rowb) | ((i | ((uint32_t)r[7] << 13)) << 16);
+                g[4 * p + 3] = (r[6] * rowb) | ((uint32_t)r[7] << 16);
             }
             uint4 *dp = nullptr;
             XS_HIP(hipMalloc(&dp, 16 * (size_t)I->n));
@@ -275,7 +433,7 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
     if (cfg->accept_thr0 && (cfg->flags & XS_STOP_ON_FIRST))
         return fail(XS_EINVAL, "XS_STOP_ON_FIRST needs accept_thr0 = 0 (with w0 > 0 a ground "
                                "state is not absorbing and no sweep is tested)");
-    if (cfg->flags & ~(XS_STOP_ON_FIRST | XS_RESUME))
+    if (cfg->flags & ~(XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS))
         return fail(XS_EINVAL, "unknown flags 0x%x", cfg->flags);
     if ((uint64_t)cfg->start_sweep + cfg->max_sweeps >= 0xFFFFFFFFull)
         return fail(XS_EINVAL, "start_sweep + max_sweeps must stay below 2^32 - 1");
@@ -726,7 +884,8 @@ xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int
     I->J.assign(J, J + m);
     partition(*I);
     build_triplets(*I);
-    I->sched.emplace(0u, make_schedule(*I, 0));  // uncapped steps, reported by get_info
+    // uncapped steps, reported by get_info
+    I->sched.emplace(sched_key(0, 1), make_schedule(*I, 0, 1));
     *out = I;
     return XS_OK;
 }
@@ -741,6 +900,7 @@ void xs_instance_destroy(xs_instance *I) {
         for (auto &s : kv.second.sched) {
             (void)hipFree(s.second.rec);
             (void)hipFree(s.second.off);
+            (void)hipFree(s.second.rowmap);
             for (auto &g : s.second.grec) (void)hipFree(g.second);
         }
     }
@@ -755,7 +915,7 @@ xs_status xs_instance_get_info(const xs_instance *I, xs_instance_info *info) {
     info->colour_cap = I->cap;
     info->max_class = I->max_class;
     std::lock_guard<std::mutex> lock(I->mu);
-    const xsh::HostSched &lv = I->sched.at(0u);
+    const xsh::HostSched &lv = I->sched.at(sched_key(0, 1));
     info->n_levels = (int32_t)lv.off.size() - 1;
     info->max_level = lv.max_step;
     return XS_OK;
@@ -772,8 +932,10 @@ xs_status xs_instance_get_schedule(const xs_instance *I, uint32_t step_cap, int3
                                    int32_t *step_off, int32_t *n_steps) {
     if (!I || !order || !step_off || !n_steps) return fail(XS_EINVAL, "null argument");
     std::lock_guard<std::mutex> lock(I->mu);
-    auto it = I->sched.find(step_cap);
-    if (it == I->sched.end()) it = I->sched.emplace(step_cap, make_schedule(*I, step_cap)).first;
+    const uint32_t cap = std::min<uint32_t>(step_cap, 0xFFFFu);  // at least n: no limit
+    auto it = I->sched.find(sched_key(cap, 1));
+    if (it == I->sched.end())
+        it = I->sched.emplace(sched_key(cap, 1), make_schedule(*I, cap, 1)).first;
     const xsh::HostSched &hs = it->second;
     std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
     std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());

@@ -396,6 +396,12 @@ __device__ __forceinline__ uint32_t check_state(const Tile &T, uint32_t t, uint3
     return lds_u32(T.flag);
 }
 
+// LDS row of spin i: the instance's row map, or i itself.
+__device__ __forceinline__ uint32_t lds_row(const Tile &T, uint32_t i) {
+    const uint16_t *rm = T.I->rowmap;
+    return rm ? rm[i] : i;
+}
+
 // Stage the tile's rows global -> LDS in 16-byte pieces.
 template <int NT>
 __device__ __forceinline__ void load_state(const Tile &T) {
@@ -403,7 +409,7 @@ __device__ __forceinline__ void load_state(const Tile &T) {
     for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
         const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
         const uint4 *src = src0 + ((size_t)i * T.W >> 1);
-        *reinterpret_cast<uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k) = src[k];
+        *reinterpret_cast<uint4 *>(xs_lds + T.st + lds_row(T, i) * T.rowb + 16 * k) = src[k];
     }
 }
 
@@ -414,7 +420,7 @@ __device__ __forceinline__ void store_state(const Tile &T) {
     for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
         const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
         (dst0 + ((size_t)i * T.W >> 1))[k] =
-            *reinterpret_cast<const uint4 *>(xs_lds + T.st + i * T.rowb + 16 * k);
+            *reinterpret_cast<const uint4 *>(xs_lds + T.st + lds_row(T, i) * T.rowb + 16 * k);
     }
 }
 
@@ -478,16 +484,15 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     T.iid = I->inst_id;
     T.nsteps = I->n_steps;
 
-    // Records: spin indices -> byte offsets of the rows in this tile (GR: done by the host).
+    // Records: LDS rows -> byte offsets of the rows in this tile (GR: done by the host).
     for (uint32_t p = T.tid; !GR && p < T.n; p += NT) {
         const uint4 r = I->rec[p];
         const uint32_t rowb = T.rowb;
-        const uint32_t i = r.x & 0xFFFFu;
         uint4 o;
-        o.x = (i * rowb) | (((r.x >> 16) * rowb) << 16);
+        o.x = ((r.x & 0xFFFFu) * rowb) | (((r.x >> 16) * rowb) << 16);
         o.y = ((r.y & 0xFFFFu) * rowb) | (((r.y >> 16) * rowb) << 16);
         o.z = ((r.z & 0xFFFFu) * rowb) | (((r.z >> 16) * rowb) << 16);
-        o.w = ((r.w & 0xFFFFu) * rowb) | ((i | ((r.w >> 16) << 13)) << 16);
+        o.w = ((r.w & 0xFFFFu) * rowb) | (r.w & 0xFFFF0000u);
         lds_rec(p) = o;
     }
     load_state<NT>(T);

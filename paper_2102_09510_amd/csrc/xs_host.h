@@ -14,22 +14,24 @@ namespace xsh {
 
 // One execution schedule of the sweep on a device: records in schedule order and step offsets.
 struct DevSched {
-    uint4 *rec = nullptr;              // [n] records (spin indices)
+    uint4 *rec = nullptr;              // [n] records (LDS rows of the spins, meta)
     int32_t *off = nullptr;            // [steps + 1]
+    uint16_t *rowmap = nullptr;        // [n] LDS row of each spin (null: identity)
     uint32_t steps = 0;
     std::map<uint32_t, uint4 *> grec;  // records as row offsets, per tile_blocks
 };
 
 struct DeviceTables {
     uint2 *tri = nullptr;
-    std::map<uint32_t, DevSched> sched;  // per step cap
+    std::map<uint32_t, DevSched> sched;  // per (step cap, row slots)
 };
 
 // The host side of a schedule: the update order regrouped into parallel steps.
 struct HostSched {
-    std::vector<int32_t> order;  // spins in schedule order
-    std::vector<int32_t> off;    // [steps + 1]
-    std::vector<uint16_t> rec;   // [n][8] records in schedule order
+    std::vector<int32_t> order;    // spins in schedule order
+    std::vector<int32_t> off;      // [steps + 1]
+    std::vector<uint16_t> rec;     // [n][8] records in schedule order
+    std::vector<uint16_t> rowmap;  // [n] LDS row of each spin (empty: identity)
     int32_t max_step = 0;
 };
 
@@ -44,7 +46,7 @@ struct xs_instance {
     std::vector<int32_t> perm;       // update order
     std::vector<int32_t> class_off;  // [n_classes + 1]
     // Caches filled on first use (under mu), so they may change behind a const instance.
-    mutable std::map<uint32_t, xsh::HostSched> sched;  // per step cap (0: uncapped levels)
+    mutable std::map<uint32_t, xsh::HostSched> sched;  // per (step cap, row slots)
     std::vector<uint16_t> tri16;     // [n][4]: a, b, c, j
     int32_t max_class = 0;
     mutable std::mutex mu;

@@ -14,10 +14,12 @@ constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
 // the constant part, the kernels update the control part.
 struct InstDev {
     // tables (device pointers owned by the instance)
-    const uint4 *rec;        // [n] 16-byte records in step order: u16 {i, a1, b1, a2, b2, a3, b3, jbits}
+    const uint4 *rec;        // [n] 16-byte records in step order: u16 LDS rows {i, a1, b1, a2, b2,
+                             // a3, b3} of the spin and its partners, then meta = i | jbits << 13
     const int32_t *step_off; // [n_steps + 1] schedule steps (independent sets, run in order)
     const uint2 *tri;        // [n] triplets: x = a | b << 16, y = c | j << 16 (j = 1 <=> J = -1)
     const uint4 *grec;       // [n] records with row offsets for this tiling (global-record kernels)
+    const uint16_t *rowmap;  // [n] LDS row of each spin, or null for row = spin
     // caller buffers
     uint64_t *state;         // [n][n_words]
     int32_t *first_hit;      // [n_clones]

@@ -21,6 +21,7 @@ XS_STATUS = {0: "XS_OK", 1: "XS_EINVAL", 2: "XS_ENOMEM", 3: "XS_EDEVICE", 4: "XS
 XS_STATUS_CODES = {v: k for k, v in XS_STATUS.items()}
 XS_STOP_ON_FIRST = 0x1
 XS_RESUME = 0x2
+XS_PLACE_ROWS = 0x4
 XS_MAX_N = 2048
 XS_CLONE_QUANTUM = 256
 
@@ -258,10 +259,12 @@ def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: i
                 max_sweeps: int = 100000, stop_on_first: bool = True, resume: bool = False,
                 start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0,
                 wg_threads: int = 0, col_bytes: int = 0, rec_global: int = 0,
-                accept_thr0: int = 0) -> RunConfig:
+                accept_thr0: int = 0, place_rows: bool = False) -> RunConfig:
     """accept_thr0 > 0 selects the rule with w0 = accept_thr0 / 65536 (no ground-state
-    tracking: first_hit marks only clones whose end configuration is a ground state)."""
-    flags = (XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0)
+    tracking: first_hit marks only clones whose end configuration is a ground state).
+    place_rows builds the LDS row placement even for a short run (speed only)."""
+    flags = ((XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0) |
+             (XS_PLACE_ROWS if place_rows else 0))
     return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
                      accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks,
                      wg_threads, col_bytes, rec_global, accept_thr0, 0)

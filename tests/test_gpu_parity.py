@@ -66,13 +66,13 @@ def assert_parity(inst, h, cfg, out, clones=None, init_spins=None):
 
 
 def run_and_check_full(n, seed, n_clones, *, max_sweeps, stop=True, chunk=0, tile_blocks=0,
-                       thr=THR_PAPER, cap=32, iid=3):
+                       thr=THR_PAPER, cap=32, iid=3, place=False):
     _torch()
     inst = planted_instance(n, seed)
     h = xorsat.Instance(inst.tri, inst.J, colour_cap=cap)
     cfg = xorsat.make_config(n_clones=n_clones, seed=seed * 7 + 1, instance_id=iid,
                              accept_thr=thr, max_sweeps=max_sweeps, stop_on_first=stop,
-                             chunk_sweeps=chunk, tile_blocks=tile_blocks)
+                             chunk_sweeps=chunk, tile_blocks=tile_blocks, place_rows=place)
     out = xorsat.run(h, cfg)
     ref = assert_parity(inst, h, cfg, out)
     tts, winner = oracle.solve_results(ref["first_hit"])
@@ -91,15 +91,24 @@ def test_small_instance_full_parity_to_first_ground_state():
     assert out.end_sweep % 100 == 0 or out.end_sweep == 100000
 
 
-@pytest.mark.parametrize("n,clones,B,chunk,sweeps", [
-    (100, 4096, 2, 7, 40),     # ragged classes, 8 tiles, chunk does not divide the budget
-    (37, 2048, 0, 0, 33),      # odd N, auto tiling, single chunk
-    (257, 1024, 1, 5, 23),     # N just above 256, one-block tiles
-    (4, 256, 1, 1, 9),         # smallest instance and clone count
+def test_first_ground_state_with_placed_rows():
+    """The same run with the LDS rows placed (one-block tiles: eight rows per LDS cycle),
+    through the end-of-chunk check and the replay."""
+    inst, h, cfg, out = run_and_check_full(64, 1000001, 1024, max_sweeps=100000, place=True)
+    assert out.tile_blocks < 8 and out.tts_sweeps >= 0
+
+
+@pytest.mark.parametrize("n,clones,B,chunk,sweeps,place", [
+    (100, 4096, 2, 7, 40, False),  # ragged classes, 8 tiles, chunk does not divide the budget
+    (100, 4096, 2, 7, 40, True),   # the same with LDS rows placed
+    (37, 2048, 0, 0, 33, True),    # odd N, auto tiling, single chunk
+    (257, 1024, 1, 5, 23, False),  # N just above 256, one-block tiles
+    (257, 1024, 1, 5, 23, True),
+    (4, 256, 1, 1, 9, True),       # smallest instance and clone count (too small to place)
 ])
-def test_budget_runs_every_clone(n, clones, B, chunk, sweeps):
+def test_budget_runs_every_clone(n, clones, B, chunk, sweeps, place):
     run_and_check_full(n, 500 + n, clones, max_sweeps=sweeps, stop=False, chunk=chunk,
-                       tile_blocks=B)
+                       tile_blocks=B, place=place)
 
 
 @pytest.mark.parametrize("thr", [0, 65536])
@@ -119,13 +128,16 @@ def test_tiling_is_result_neutral():
     inst = planted_instance(128, 9)
     h = xorsat.Instance(inst.tri, inst.J)
     outs = []
-    for B, T, C, G in ((1, 0, 0, 0), (2, 0, 0, 0), (4, 0, 0, 0), (8, 0, 0, 0), (16, 0, 0, 0),
-                       (1, 64, 16, 2), (2, 128, 16, 1), (4, 1024, 16, 2), (8, 256, 16, 1),
-                       (16, 256, 16, 2), (1, 256, 4, 1), (1, 64, 8, 2), (2, 256, 4, 1),
-                       (4, 256, 8, 1), (16, 128, 4, 1), (8, 512, 8, 2)):
+    shapes = ((1, 0, 0, 0), (2, 0, 0, 0), (4, 0, 0, 0), (8, 0, 0, 0), (16, 0, 0, 0),
+              (1, 64, 16, 2), (2, 128, 16, 1), (4, 1024, 16, 2), (8, 256, 16, 1),
+              (16, 256, 16, 2), (1, 256, 4, 1), (1, 64, 8, 2), (2, 256, 4, 1),
+              (4, 256, 8, 1), (16, 128, 4, 1), (8, 512, 8, 2))
+    # tiles under eight blocks again with their LDS rows placed
+    for (B, T, C, G), place in [(s, False) for s in shapes] + [(s, True) for s in shapes
+                                                               if s[0] < 8]:
         cfg = xorsat.make_config(n_clones=8192, seed=99, instance_id=1, max_sweeps=300,
                                  stop_on_first=False, tile_blocks=B, chunk_sweeps=64,
-                                 wg_threads=T, col_bytes=C, rec_global=G)
+                                 wg_threads=T, col_bytes=C, rec_global=G, place_rows=place)
         out = xorsat.run(h, cfg)
         if G:
             assert out.rec_global == (G == 1)
@@ -266,7 +278,7 @@ def test_metropolis_budget_runs(n, clones, B, T, C, G, chunk, sweeps, thr, thr0)
     cfg = xorsat.make_config(n_clones=clones, seed=n * 3 + 1, instance_id=5, accept_thr=thr,
                              accept_thr0=thr0, max_sweeps=sweeps, stop_on_first=False,
                              chunk_sweeps=chunk, tile_blocks=B, wg_threads=T, col_bytes=C,
-                             rec_global=G)
+                             rec_global=G, place_rows=n % 2 == 1)
     out = xorsat.run(h, cfg)
     ref = assert_parity(inst, h, cfg, out)
     assert set(np.unique(ref["first_hit"])) <= {-1, sweeps}
