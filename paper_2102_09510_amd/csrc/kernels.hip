@@ -93,7 +93,6 @@ __device__ __forceinline__ uint4 philox10_draw(uint32_t i, uint64_t pz, uint32_t
     return c;
 }
 
-__device__ __forceinline__ uint32_t below(uint32_t v, uint32_t thr) { return v < thr ? 1u : 0u; }
 
 // One 32-clone word of one spin: eight three-input operations, a ninth when ground states are
 // tracked (kAcc: acc collects "k >= 1").
@@ -231,11 +230,24 @@ __device__ __forceinline__ void col_store(uint32_t addr, const uint32_t (&w)[CW 
 }
 
 // Bit g of the result: draw g of the eight 16-bit draws in o is below thr.
+// 1 in each 16-bit half of w that is at most the same half of lim (saturating 16-bit
+// subtractions: w - lim is 0 exactly then, and 1 - (w - lim) is 1 exactly then).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t halves_at_most(uint32_t w, uint32_t lim) {
+    const u16x2 one = {1, 1};
+    const u16x2 d = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, w),
+                                                  __builtin_bit_cast(u16x2, lim));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(one, d));
+}
+
+// Bit g (g = 0..7) set iff the g-th 16-bit draw of o (half g & 1 of word g >> 1) is below thr,
+// 0 <= thr <= 65536: for thr >= 1, d < thr <=> d <= thr - 1. The low halves' bits land on even
+// positions, the high halves' on 16 + even positions, folded down by 15.
 __device__ __forceinline__ uint32_t draws_below(uint4 o, uint32_t thr) {
-    return below(o.x & 0xFFFFu, thr) | below(o.x >> 16, thr) << 1 |
-           below(o.y & 0xFFFFu, thr) << 2 | below(o.y >> 16, thr) << 3 |
-           below(o.z & 0xFFFFu, thr) << 4 | below(o.z >> 16, thr) << 5 |
-           below(o.w & 0xFFFFu, thr) << 6 | below(o.w >> 16, thr) << 7;
+    const uint32_t lim = (thr - 1u) * 0x00010001u;
+    const uint32_t x = halves_at_most(o.x, lim) | halves_at_most(o.y, lim) << 2 |
+                       halves_at_most(o.z, lim) << 4 | halves_at_most(o.w, lim) << 6;
+    return (x | x >> 15) & (thr ? 0xFFu : 0u);
 }
 
 // Acceptance bits of sweep t: one Philox call per (position, block) gives the eight 16-bit draws
