@@ -42,6 +42,21 @@ def test_every_declared_symbol_is_exported(lib):
     assert lib.xs_status_str(1) == b"XS_EINVAL"
 
 
+def test_header_constants_match_the_binding():
+    text = open(os.path.join(ROOT, "include", "xorsat.h")).read()
+    defs = {m.group(1): int(m.group(2), 0)
+            for m in re.finditer(r"#define\s+(XS_[A-Z_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text)}
+    for name in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_MAX_N",
+                 "XS_CLONE_QUANTUM", "XS_TUNE_MAX_TRIALS"):
+        assert defs[name] == getattr(xorsat, name), name
+    for code, name in xorsat.XS_STATUS.items():
+        assert defs[name] == code, name
+    flags = [defs[k] for k in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS")]
+    assert len(set(flags)) == 3 and all(f & (f - 1) == 0 for f in flags)
+    cfg = xorsat.make_config(n_clones=256, seed=1, stop_on_first=False, place_rows=True)
+    assert cfg.flags == xorsat.XS_PLACE_ROWS
+
+
 def test_struct_layouts():
     assert ctypes.sizeof(xorsat.RunConfig) == 64  # 64 bytes of fields
     assert ctypes.sizeof(xorsat.RunBuffers) == 32
