@@ -303,8 +303,10 @@ xs_status ensure_tables(const xs_instance *I, int device, DeviceTables *out) {
     }
     DeviceTables t;
     const size_t n = (size_t)I->n;
-    XS_HIP(hipMalloc(&t.tri, 8 * n));
-    XS_HIP(hipMemcpy(t.tri, I->tri16.data(), 8 * n, hipMemcpyHostToDevice));
+    DevAlloc tri;
+    XS_HIP(hipMalloc(&tri.p, 8 * n));
+    XS_HIP(hipMemcpy(tri.p, I->tri16.data(), 8 * n, hipMemcpyHostToDevice));
+    t.tri = tri.release<uint2>();
     I->dev[device] = t;
     *out = t;
     return XS_OK;
@@ -346,16 +348,19 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
         const xsh::HostSched &hs = hit->second;
         xsh::DevSched &ds = I->dev[device].sched[key];
         if (!ds.rec) {
-            const size_t n = (size_t)I->n;
-            XS_HIP(hipMalloc(&ds.rec, 16 * n));
-            XS_HIP(hipMalloc(&ds.off, sizeof(int32_t) * hs.off.size()));
-            XS_HIP(hipMemcpy(ds.rec, hs.rec.data(), 16 * n, hipMemcpyHostToDevice));
-            XS_HIP(hipMemcpy(ds.off, hs.off.data(), sizeof(int32_t) * hs.off.size(),
-                             hipMemcpyHostToDevice));
+            const size_t n = (size_t)I->n, off_bytes = sizeof(int32_t) * hs.off.size();
+            DevAlloc rec, off, rowmap;
+            XS_HIP(hipMalloc(&rec.p, 16 * n));
+            XS_HIP(hipMemcpy(rec.p, hs.rec.data(), 16 * n, hipMemcpyHostToDevice));
+            XS_HIP(hipMalloc(&off.p, off_bytes));
+            XS_HIP(hipMemcpy(off.p, hs.off.data(), off_bytes, hipMemcpyHostToDevice));
             if (!hs.rowmap.empty()) {
-                XS_HIP(hipMalloc(&ds.rowmap, 2 * n));
-                XS_HIP(hipMemcpy(ds.rowmap, hs.rowmap.data(), 2 * n, hipMemcpyHostToDevice));
+                XS_HIP(hipMalloc(&rowmap.p, 2 * n));
+                XS_HIP(hipMemcpy(rowmap.p, hs.rowmap.data(), 2 * n, hipMemcpyHostToDevice));
             }
+            ds.rec = rec.release<uint4>();
+            ds.off = off.release<int32_t>();
+            ds.rowmap = rowmap.release<uint16_t>();
             ds.steps = (uint32_t)hs.off.size() - 1;
         }
         d.rec = ds.rec;
@@ -375,10 +380,10 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
                 g[4 * p + 2] = (r[4] * rowb) | ((r[5] * rowb) << 16);
                 g[4 * p + 3] = (r[6] * rowb) | ((uint32_t)r[7] << 16);
             }
-            uint4 *dp = nullptr;
-            XS_HIP(hipMalloc(&dp, 16 * (size_t)I->n));
-            XS_HIP(hipMemcpy(dp, g.data(), 16 * (size_t)I->n, hipMemcpyHostToDevice));
-            it = ds.grec.emplace(d.tile_blocks, dp).first;
+            DevAlloc dp;
+            XS_HIP(hipMalloc(&dp.p, 16 * (size_t)I->n));
+            XS_HIP(hipMemcpy(dp.p, g.data(), 16 * (size_t)I->n, hipMemcpyHostToDevice));
+            it = ds.grec.emplace(d.tile_blocks, dp.release<uint4>()).first;
         }
         d.grec = it->second;
     }

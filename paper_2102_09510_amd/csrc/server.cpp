@@ -179,12 +179,13 @@ struct xs_server {
 
     xs_status ensure_scratch(size_t bytes) {
         if (bytes <= scratch_bytes) return XS_OK;
+        const size_t want = std::max(bytes, 2 * scratch_bytes);
         if (scratch) {
             XS_HIP(hipStreamSynchronize(stream));
             XS_HIP(hipFree(scratch));
             scratch = nullptr;
+            scratch_bytes = 0;  // a failed allocation below leaves no stale size behind
         }
-        const size_t want = std::max(bytes, 2 * scratch_bytes);
         XS_HIP(hipMalloc(&scratch, want));
         scratch_bytes = want;
         return XS_OK;

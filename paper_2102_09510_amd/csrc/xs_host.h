@@ -63,6 +63,23 @@ struct xs_instance {
 
 namespace xsh {
 
+// A device allocation freed when the scope ends unless released (uploads that fail halfway
+// leave nothing behind and nothing half-built).
+struct DevAlloc {
+    void *p = nullptr;
+    DevAlloc() = default;
+    DevAlloc(const DevAlloc &) = delete;
+    DevAlloc &operator=(const DevAlloc &) = delete;
+    ~DevAlloc() {
+        if (p) (void)hipFree(p);
+    }
+    template <typename T> T *release() {
+        T *q = static_cast<T *>(p);
+        p = nullptr;
+        return q;
+    }
+};
+
 // Set the calling thread's last error message and return st.
 xs_status fail(xs_status st, const char *fmt, ...);
 // Device tables of an instance on `device`, uploaded on first use.

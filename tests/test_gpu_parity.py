@@ -232,17 +232,19 @@ def test_zero_budget_and_ground_state_start():
     assert out.tts_sweeps == 17 and out.winner_clone == 0
 
 
-@pytest.mark.parametrize("n,clones,sweeps", [(256, 65536, 120), (1024, 1 << 20, 12),
-                                             (2048, 16384, 20)])
-def test_full_size_sampled_clones(n, clones, sweeps):
-    """Full-size shapes (the batched N = 256 workload, the N = 1024 steady-state workload and
-    the largest N): every clone's energy must be a valid E = 2U - N; sampled clones from
-    different tiles match the oracle bit for bit."""
+@pytest.mark.parametrize("n,clones,sweeps,place", [(256, 65536, 120, False),
+                                                   (1024, 1 << 20, 12, True),
+                                                   (2048, 16384, 20, True)])
+def test_full_size_sampled_clones(n, clones, sweeps, place):
+    """Full-size shapes in the launch configuration the benchmarks time (the batched N = 256
+    workload, the N = 1024 steady-state workload with its LDS rows placed, and the largest N):
+    every clone's energy must be a valid E = 2U - N; sampled clones from different tiles match
+    the oracle bit for bit."""
     _torch()
     inst = planted_instance(n, 9000 + n)
     h = xorsat.Instance(inst.tri, inst.J)
     cfg = xorsat.make_config(n_clones=clones, seed=n, instance_id=n, max_sweeps=sweeps,
-                             stop_on_first=False)
+                             stop_on_first=False, place_rows=place)
     out = xorsat.run(h, cfg)
     en = out.energy.cpu().numpy()
     assert en.min() >= -n and en.max() <= n and np.all((en + n) % 2 == 0)
