@@ -83,34 +83,78 @@ void partition(xs_instance &I) {
     }
 }
 
-// LDS row placement for one-, two- and four-block tiles. A 256-byte LDS cycle of a row access
-// serves S = 8 / B consecutive tasks' spins of a step (rows of 32·B bytes), one row each; rows
-// whose index is equal modulo S sit on the same banks and serialise. Each role (own row, the
-// six partners) of each such run of S positions is a group of rows that should fall on
-// different residues. Starting from row = spin, a local search picks a random group with an
-// excess (rows on its fullest residue minus one), and trades the residues of one of its rows on
-// the fullest residue and a random row on its emptiest one when that does not raise the summed
-// excess of the groups the two rows are in; the rows of each residue are then numbered in spin
-// order, so the map is a permutation of [0, n) (the residue counts never change). The search is
-// seeded, so the map is a fixed function of the schedule.
+// LDS passes of a row access (measured on gfx950 with a probe of lane pairs and bank
+// conflicts): ds_read_b64 serves lanes 0-31 and 32-63 in two passes; ds_read_b128 serves four
+// passes of 16 lanes, lanes with the same l >> 5 and the same parity of the bits of
+// (l >> 2) & 7 together; a ds_read_b32 is taken as one pass. Within a pass, lanes that read
+// different rows of 32 * B < 256 bytes collide when they read the same column of rows equal
+// modulo S = 8 / B. RowModel lists, for a tile of B blocks read in CW-byte columns, the sets of
+// positions (relative to the first position of a wave, which takes P consecutive positions of
+// a step) whose rows must differ modulo S for the access to be free of conflicts.
+struct RowModel {
+    uint32_t S = 1, P = 1;
+    std::vector<std::vector<uint8_t>> sets;
+};
+
+RowModel row_model(uint32_t B, uint32_t CW) {
+    RowModel m;
+    if (B == 0 || B >= 8) return m;
+    m.S = 8 / B;
+    const uint32_t ncol = 32 * B / CW;
+    m.P = 64 / ncol;
+    std::map<std::pair<uint32_t, uint32_t>, std::vector<uint8_t>> by;  // (pass, column)
+    for (uint32_t l = 0; l < 64; ++l) {
+        const uint32_t pos = l / ncol, col = l % ncol;
+        uint32_t pass = 0;
+        if (CW == 16) pass = (l >> 5) * 2 + (__builtin_popcount((l >> 2) & 7) & 1);
+        else if (CW == 8) pass = l >> 5;
+        auto &v = by[{pass, col}];
+        if (std::find(v.begin(), v.end(), (uint8_t)pos) == v.end()) v.push_back((uint8_t)pos);
+    }
+    for (auto &kv : by)
+        if (kv.second.size() > 1 &&
+            std::find(m.sets.begin(), m.sets.end(), kv.second) == m.sets.end())
+            m.sets.push_back(kv.second);
+    return m;
+}
+
+// LDS row placement for one-, two- and four-block tiles. Each role (own row, the six partners)
+// of each position set of each wave's share of a step (RowModel) is a group of rows that should
+// fall on different residues modulo S. Starting from row = spin, a local search picks a random
+// group with an excess (rows on its fullest residue minus one), and trades the residues of one
+// of its rows on the fullest residue and a random row on its emptiest one when that does not
+// raise the summed excess of the groups the two rows are in; the rows of each residue are then
+// numbered in spin order, so the map is a permutation of [0, n) (the residue counts never
+// change). The search is seeded, so the map is a fixed function of the schedule.
 std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int32_t> &roles,
-                                 int n, uint32_t S) {
-    // groups: per step, per S consecutive positions, per role
+                                 int n, const RowModel &m) {
+    const uint32_t S = m.S;
+    // groups: per step, per wave's share, per position set, per role
     std::vector<int32_t> goff(1, 0), grow;
     for (size_t st = 0; st + 1 < hs.off.size(); ++st)
-        for (int g = hs.off[st]; g < hs.off[st + 1]; g += (int)S) {
-            const int e = std::min(g + (int)S, hs.off[st + 1]);
-            for (int k = 0; k < 7; ++k) {
-                const size_t first = grow.size();
-                for (int p = g; p < e; ++p) {
-                    const int32_t r = roles[7 * (size_t)hs.order[p] + k];
-                    if (std::find(grow.begin() + first, grow.end(), r) == grow.end())
-                        grow.push_back(r);  // a row read twice in one cycle is a broadcast
+        for (int g = hs.off[st]; g < hs.off[st + 1]; g += (int)m.P)
+            for (const auto &set : m.sets)
+                for (int k = 0; k < 7; ++k) {
+                    const size_t first = grow.size();
+                    for (uint8_t d : set) {
+                        const int p = g + d;
+                        if (p >= hs.off[st + 1]) continue;
+                        const int32_t r = roles[7 * (size_t)hs.order[p] + k];
+                        if (std::find(grow.begin() + first, grow.end(), r) == grow.end())
+                            grow.push_back(r);  // a row read twice in one pass is a broadcast
+                    }
+                    if (grow.size() - first < 2) {
+                        grow.resize(first);  // one row alone cannot collide
+                        continue;
+                    }
+                    goff.push_back((int32_t)grow.size());
                 }
-                goff.push_back((int32_t)grow.size());
-            }
-        }
     const size_t ng = goff.size() - 1;
+    if (ng == 0) {
+        std::vector<uint16_t> row(n);
+        for (int r = 0; r < n; ++r) row[r] = (uint16_t)r;
+        return row;
+    }
     std::vector<int32_t> moff(n + 1, 0), memb;  // groups of each row
     for (size_t q = 0; q < ng; ++q)
         for (int32_t j = goff[q]; j < goff[q + 1]; ++j) ++moff[grow[j] + 1];
@@ -218,9 +262,9 @@ std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int
 // sequential sweep. Steps are independent sets. Uncapped, there are at most as many steps as
 // classes (a member of class c has no conflicting predecessor in c, so by induction its step is
 // at most c) and far fewer when the class cap, not a shared triplet, closed the classes; the
-// cap fits the steps to the threads of a launch. slots > 1: the LDS rows are placed for that
-// many rows per LDS cycle.
-xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t slots) {
+// cap fits the steps to the threads of a launch. B > 0: the LDS rows are placed for tiles of B
+// blocks read in CW-byte columns.
+xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uint32_t CW) {
     const int n = I.n;
     std::vector<int32_t> inc(3 * (size_t)n), deg(n, 0), pos(n), step(n, 0), fill;
     for (int t = 0; t < n; ++t)
@@ -268,7 +312,8 @@ xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t slots)
             if (I.J[t] < 0) jbits[i] |= (uint16_t)(1u << q);
         }
     }
-    if (slots > 1 && n >= 2 * (int)slots) hs.rowmap = place_rows(hs, roles, n, slots);
+    const RowModel model = row_model(B, CW);
+    if (!model.sets.empty() && n >= 2 * (int)model.S) hs.rowmap = place_rows(hs, roles, n, model);
     // Records in schedule order: the LDS rows of the spin and of its six partners, then
     // meta = spin | coupling bits << 13.
     hs.rec.assign(8 * (size_t)n, 0);
@@ -317,11 +362,10 @@ uint32_t step_cap(const xs::InstDev &d) {
     return d.wg_threads * d.col_bytes / (32u * d.tile_blocks);
 }
 
-// Tasks whose rows one 256-byte LDS cycle serves: rows of 32 * B bytes, 256 / (32 * B) of them.
-uint32_t row_slots(uint32_t tile_blocks) { return tile_blocks < 8 ? 8u / tile_blocks : 1u; }
-
-// Schedules are kept per (step cap, row slots); caps stay below 2^16.
-uint32_t sched_key(uint32_t cap, uint32_t slots) { return cap | slots << 16; }
+// Schedules are kept per (step cap, placement layout); caps stay below 2^16. Layout 0: rows not
+// placed; else tile blocks | column bytes << 8.
+uint32_t sched_key(uint32_t cap, uint32_t layout) { return cap | layout << 16; }
+uint32_t place_layout(uint32_t B, uint32_t CW) { return B < 8 ? B | CW << 8 : 0u; }
 
 // Clone-sweeps (clones x sweeps left) from which a run builds the row placement.
 constexpr uint64_t kPlaceMinWork = 1ull << 32;
@@ -333,18 +377,19 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
         const xs_instance *I = insts[k];
         const uint32_t cap = step_cap(d);
         std::lock_guard<std::mutex> lock(I->mu);
-        uint32_t slots = row_slots(d.tile_blocks);
-        // The row placement costs about 3 µs of host time per spin and saves about 5 % of the
+        uint32_t layout = place_layout(d.tile_blocks, d.col_bytes);
+        // The row placement costs a few µs of host time per spin and saves about 5 % of the
         // sweep time; a run too short to pay that back uses the unplaced schedule unless the
         // placed one already exists. Either gives the same results.
         const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
-        if (slots > 1 && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
-            !I->sched.count(sched_key(cap, slots)))
-            slots = 1;
-        const uint32_t key = sched_key(cap, slots);
+        if (layout && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
+            !I->sched.count(sched_key(cap, layout)))
+            layout = 0;
+        const uint32_t key = sched_key(cap, layout);
         auto hit = I->sched.find(key);
         if (hit == I->sched.end())
-            hit = I->sched.emplace(key, make_schedule(*I, cap, slots)).first;
+            hit = I->sched.emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8))
+                      .first;
         const xsh::HostSched &hs = hit->second;
         xsh::DevSched &ds = I->dev[device].sched[key];
         if (!ds.rec) {
@@ -890,7 +935,7 @@ xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int
     partition(*I);
     build_triplets(*I);
     // uncapped steps, reported by get_info
-    I->sched.emplace(sched_key(0, 1), make_schedule(*I, 0, 1));
+    I->sched.emplace(sched_key(0, 0), make_schedule(*I, 0, 0, 0));
     *out = I;
     return XS_OK;
 }
@@ -920,7 +965,7 @@ xs_status xs_instance_get_info(const xs_instance *I, xs_instance_info *info) {
     info->colour_cap = I->cap;
     info->max_class = I->max_class;
     std::lock_guard<std::mutex> lock(I->mu);
-    const xsh::HostSched &lv = I->sched.at(sched_key(0, 1));
+    const xsh::HostSched &lv = I->sched.at(sched_key(0, 0));
     info->n_levels = (int32_t)lv.off.size() - 1;
     info->max_level = lv.max_step;
     return XS_OK;
@@ -938,9 +983,9 @@ xs_status xs_instance_get_schedule(const xs_instance *I, uint32_t step_cap, int3
     if (!I || !order || !step_off || !n_steps) return fail(XS_EINVAL, "null argument");
     std::lock_guard<std::mutex> lock(I->mu);
     const uint32_t cap = std::min<uint32_t>(step_cap, 0xFFFFu);  // at least n: no limit
-    auto it = I->sched.find(sched_key(cap, 1));
+    auto it = I->sched.find(sched_key(cap, 0));
     if (it == I->sched.end())
-        it = I->sched.emplace(sched_key(cap, 1), make_schedule(*I, cap, 1)).first;
+        it = I->sched.emplace(sched_key(cap, 0), make_schedule(*I, cap, 0, 0)).first;
     const xsh::HostSched &hs = it->second;
     std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
     std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());
