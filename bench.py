@@ -40,8 +40,10 @@ ALGO_OPS_PER_UPDATE_W0 = 9 / 32 + (10 * (2 + 2) + 16) / 256
 # Algorithmic LDS traffic per update: the 7 state bits an update reads (own spin and the two
 # partners in each of its three triplets) and the 1 bit it writes = 1 byte.
 ALGO_LDS_BYTES_PER_UPDATE = 1.0
-# LDS peak: 256 CUs x 128 B/clk x 2.4 GHz.
-LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+# LDS peak for 16-byte reads: a conflict-free ds_read_b128 keeps the LDS busy 4 clocks per wave
+# (1 KB), so 256 CUs x 256 B/clk x 2.4 GHz = 157.3 TB/s (a streaming microbenchmark with 16
+# waves per CU reached 136 TB/s at 94 % LDS busy).
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
 
 
 def parse():
