@@ -529,8 +529,9 @@ uint32_t default_threads(uint32_t B, uint32_t n) {
 }
 
 // Default tile: the largest with n * B <= 1024 (at most 32 KB of clone state, four workgroups
-// per CU), raised to eight blocks (256-byte rows: a 16-lane LDS access stays on one row, free
-// of bank conflicts) where n * 8 <= 2048 still leaves two workgroups per CU.
+// per CU), raised to eight blocks (256-byte rows: each pass of a 16-byte row read takes
+// complementary quarters of two rows, free of bank conflicts whatever the rows) where
+// n * 8 <= 2048 still leaves two workgroups per CU.
 uint32_t default_tile_blocks(uint32_t n, uint32_t nb) {
     uint32_t B = max_tile_blocks(n, nb, 1024);
     if (B < 8 && n * 8 <= 2048 && nb % 8 == 0) B = 8;
