@@ -64,7 +64,7 @@ def parse():
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
     ap.add_argument("--workload", default="batched",
                     choices=["batched", "steady", "uneven", "serve", "tts", "w1scan", "paper",
-                             "single"],
+                             "paper256", "single"],
                     help="batched: the default line; steady: 16 x N=1024 x 2^20 clones, fixed "
                          "sweeps; uneven: 512 instances of uneven N and clone count, batched vs "
                          "served vs one at a time; serve: Poisson stream through the server vs "
@@ -73,7 +73,8 @@ def parse():
                          "w1scan: mean TTS against w1 on one small instance, and the same w1 "
                          "with w0 = w1^3; paper: TTS_99 in seconds at the paper's clone count "
                          "(327,680) on planted N = 128 instances, one run at a time, and a "
-                         "short-timeout estimate at N = 256; single: the N = 64, 1,024-clone "
+                         "short-timeout estimate at N = 256; paper256: per-instance TTS_99 at "
+                         "N = 256 by the short-timeout protocol; single: the N = 64, 1,024-clone "
                          "instance run to its first ground state with many seeds, one run at a "
                          "time vs all runs batched, and the oracle on the same runs")
     ap.add_argument("--accept-thr0", type=int, default=0,
@@ -93,6 +94,11 @@ def parse():
                     help="paper: N = 256 instances, one capped run each")
     ap.add_argument("--paper-timeout-sweeps", type=int, default=2000000,
                     help="paper: sweep cap of the N = 256 runs")
+    ap.add_argument("--p256-first", type=int, default=0, help="paper256: first instance")
+    ap.add_argument("--p256-instances", type=int, default=4, help="paper256: instances")
+    ap.add_argument("--p256-runs", type=int, default=32, help="paper256: runs per instance")
+    ap.add_argument("--p256-cap", type=int, default=1000000,
+                    help="paper256: sweep cap of every run")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
@@ -470,7 +476,8 @@ def workload_w1scan(args, xorsat, torch):
 def workload_paper(args, xorsat, torch):
     """The paper's headline quantity on synthetic planted instances (Section "Numerical
     results", Table 1: TTS_99 of the median instance, 327,680 clones, w1 = 0.055, one run on the
-    GPU at a time), at the paper's clone count unless --paper-clones says otherwise. N = 128: every run to its first ground state, tau of an
+    GPU at a time), at the paper's clone count unless --paper-clones says otherwise. N = 128:
+    every run to its first ground state, tau of an
     instance = mean wall time of its runs, TTS_99 = ln(100) tau. N = 256: runs capped at a short
     timeout (Section "Running with a short timeout"); with few successes per instance the
     instances are pooled into one posterior (inverse-gamma with shape = successes and scale =
@@ -543,6 +550,61 @@ def workload_paper(args, xorsat, torch):
                     tts99_s_pooled_68=[ln100 * q[0] * s_per_sweep, ln100 * q[2] * s_per_sweep])
     out["n256_timeout"] = n256
     return out
+
+
+def workload_paper256(args, xorsat, torch):
+    """Per-instance TTS_99 at N = 256 by the paper's short-timeout protocol (Section "Running
+    with a short timeout"): R runs of each instance capped at a sweep budget, tau of the instance
+    from the exact posterior of its successes, TTS_99 = ln(100) tau in seconds of one run
+    alone; the median over instances is the Table 1 quantity. Instances k0 .. k0 + K - 1, so
+    that the set can be split over several invocations."""
+    from paper_2102_09510_amd import tts_stats as ts
+    from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance
+
+    ncl, runs, cap = args.paper_clones, args.p256_runs, args.p256_cap
+    k0, count = args.p256_first, args.p256_instances
+    n = 256
+    ln100 = math.log(100.0)
+    per = []
+    t_all = time.perf_counter()
+    s_per_sweep = None
+    for k in range(k0, k0 + count):
+        inst = planted_instance(n, gen_seed(9, k))
+        h = xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap)
+        if s_per_sweep is None:
+            o1 = xorsat.run(h, xorsat.make_config(n_clones=ncl, seed=1, instance_id=k,
+                                                  accept_thr=THR_PAPER, max_sweeps=2000,
+                                                  stop_on_first=False, chunk_sweeps=100),
+                            want_energy=False)
+            s_per_sweep = o1.seconds / 2000
+        tts = []
+        for g in range(0, runs, 8):  # groups of 8 runs of the instance, so that progress shows
+            m = min(8, runs - g)
+            cfgs = [xorsat.make_config(n_clones=ncl, seed=0xBEEF + 7919 * (g + j) + 104729 * k,
+                                       instance_id=k, accept_thr=THR_PAPER, max_sweeps=cap,
+                                       stop_on_first=True, chunk_sweeps=100) for j in range(m)]
+            outs = xorsat.run_batch([h] * m, cfgs, want_energy=False)
+            tts += [o.tts_sweeps for o in outs]
+            print(f"# N=256 instance {k}: {len(tts)} runs, {sum(t >= 0 for t in tts)} solved, "
+                  f"{time.perf_counter() - t_all:.0f} s", file=sys.stderr, flush=True)
+        solved = [t for t in tts if t >= 0]
+        rec = {"instance": k, "runs": runs, "solved": len(solved)}
+        if 0 < len(solved) < runs:
+            q = ts.timeout_posterior_quantiles(len(solved), runs, cap)
+            rec.update(tau_sweeps=q[1], tau_sweeps_68=[q[0], q[2]])
+        elif len(solved) == runs:
+            rec.update(tau_sweeps=float(np.mean(solved)))  # nothing censored
+        if "tau_sweeps" in rec:
+            rec["tts99_s"] = ln100 * rec["tau_sweeps"] * s_per_sweep
+        per.append(rec)
+    done = [r["tts99_s"] for r in per if "tts99_s" in r]
+    return {"metric": f"TTS_99 (s) per instance, N=256, {ncl} clones, w1 = 0.055",
+            "config": {"workload": f"planted instances {k0}..{k0 + count - 1}, {runs} runs "
+                                   f"each capped at {cap} sweeps"},
+            "seconds_per_sweep_one_run": s_per_sweep, "instances": per,
+            "tts99_s_median": float(np.median(done)) if done else None,
+            "unsolved_instances": sum(1 for r in per if r["solved"] == 0),
+            "paper_tts99_s_v100": 640.0}
 
 
 def workload_single(args, xorsat, torch):
@@ -630,7 +692,7 @@ def main():
         fn = {"steady": workload_steady, "uneven": workload_uneven,
               "serve": workload_serve, "tts": workload_tts,
               "w1scan": workload_w1scan, "paper": workload_paper,
-              "single": workload_single}[args.workload]
+              "paper256": workload_paper256, "single": workload_single}[args.workload]
         out = fn(args, xorsat, torch)
         out.setdefault("config", {})["colour_cap"] = args.cap
         print(json.dumps(out), flush=True)

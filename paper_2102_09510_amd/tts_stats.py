@@ -134,6 +134,26 @@ class TimeoutPosterior:
         return self.t_tot / (0.5 * (lo + hi))
 
 
+def timeout_posterior_quantiles(n: int, n_run: int, t_max: float, qs=(0.16, 0.5, 0.84),
+                                grid: int = 20000) -> list[float]:
+    """Quantiles of the exact posterior of tau (binomial likelihood of n successes in n_run runs
+    capped at t_max, prior 1/tau; Section "Running with a short timeout"), for any t_max/tau,
+    by integration on a log grid of tau (the inverse-gamma form needs t_max << tau)."""
+    if not 0 < n < n_run:
+        raise ValueError("need 0 < n < n_run (with every run solved the 1/tau prior leaves "
+                         "the posterior improper at small tau)")
+    post = TimeoutPosterior(n, n_run, t_max)
+    lo, hi = t_max * 1e-3, post.t_tot * 1e3
+    lt = np.linspace(math.log(lo), math.log(hi), grid)
+    tau = np.exp(lt)
+    # density in log tau: p(tau) tau
+    logd = post.log_exact(tau) + lt
+    w = np.exp(logd - logd.max())
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    return [float(np.exp(np.interp(q, cdf, lt))) for q in qs]
+
+
 def summarize(tts, censored: int = 0, cap: float | None = None,
               n_clones: int | None = None) -> dict:
     """Estimates of tau from run TTS values; `censored` runs reached `cap` without a solution

@@ -109,3 +109,28 @@ def test_tail_tau_ignores_early_times():
     tau, used = ts.tail_tau(x, 400.0)
     assert tau == pytest.approx(200.0, rel=0.05) and used > 1000
     assert abs(ts.tau_mean(x) - 200.0) > 20
+
+
+def test_exact_timeout_posterior_quantiles():
+    """The exact short-timeout posterior: its quantiles match the inverse-gamma form when
+    t_max << tau, and a direct quadrature of the binomial-likelihood posterior otherwise."""
+    import math
+
+
+    q_ig = ts.TimeoutPosterior(10, 2000, 1e3)
+    exact = ts.timeout_posterior_quantiles(10, 2000, 1e3)
+    for q, v in zip((0.16, 0.5, 0.84), exact):
+        assert abs(v / q_ig.quantile(q) - 1) < 0.01
+    n, n_run, t_max = 9, 25, 1e6  # t_max / tau about 0.5: the inverse-gamma form is off
+    post = ts.TimeoutPosterior(n, n_run, t_max)
+    dens = lambda lt: math.exp(float(post.log_exact(math.exp(lt))) + lt + 60.0)
+    lo, hi = math.log(t_max * 1e-2), math.log(t_max * 1e4)
+    total = integrate.quad(dens, lo, hi, limit=400)[0]
+    med = ts.timeout_posterior_quantiles(n, n_run, t_max, qs=(0.5,))[0]
+    below = integrate.quad(dens, lo, math.log(med), limit=400)[0]
+    assert abs(below / total - 0.5) < 0.005
+    # near the binomial MLE tau = -t_max / ln(1 - n / n_run)
+    mle = -t_max / math.log(1 - n / n_run)
+    assert 0.8 < med / mle < 1.4
+    with pytest.raises(ValueError):
+        ts.timeout_posterior_quantiles(5, 5, 1.0)
