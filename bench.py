@@ -572,11 +572,14 @@ def workload_paper256(args, xorsat, torch):
         inst = planted_instance(n, gen_seed(9, k))
         h = xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap)
         if s_per_sweep is None:
-            o1 = xorsat.run(h, xorsat.make_config(n_clones=ncl, seed=1, instance_id=k,
-                                                  accept_thr=THR_PAPER, max_sweeps=2000,
-                                                  stop_on_first=False, chunk_sweeps=100),
-                            want_energy=False)
-            s_per_sweep = o1.seconds / 2000
+            # seconds per sweep of one run alone, from the second of two runs (the first one
+            # pays the process's one-time set-up)
+            for _ in range(2):
+                o1 = xorsat.run(h, xorsat.make_config(n_clones=ncl, seed=1, instance_id=k,
+                                                      accept_thr=THR_PAPER, max_sweeps=5000,
+                                                      stop_on_first=False, chunk_sweeps=100),
+                                want_energy=False)
+            s_per_sweep = o1.seconds / 5000
         tts = []
         for g in range(0, runs, 8):  # groups of 8 runs of the instance, so that progress shows
             m = min(8, runs - g)
