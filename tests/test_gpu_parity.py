@@ -169,6 +169,37 @@ def test_chunk_length_changes_only_end_sweep():
     assert res[0].end_sweep == res[0].tts_sweeps + 1 or res[0].end_sweep == res[0].tts_sweeps
 
 
+def test_graph_replay_equals_eager_launches():
+    """Untimed runs replay the chunk loop from a captured hipGraph (groups of up to 64 chunks,
+    replayed many times with host synchronisations between replays); timed runs launch every
+    chunk eagerly. Both give the same outputs, in a budget run and in a stop-on-first batch."""
+    torch = _torch()
+    inst = planted_instance(64, 4242)
+    h = xorsat.Instance(inst.tri, inst.J)
+    insts = [planted_instance(n, 4300 + n) for n in (40, 72, 96)]
+    hs = [xorsat.Instance(i.tri, i.J) for i in insts]
+    budget = xorsat.make_config(n_clones=4096, seed=5, instance_id=2, max_sweeps=12000,
+                                stop_on_first=False, chunk_sweeps=25)
+    batch = [xorsat.make_config(n_clones=2048, seed=11 + k, instance_id=k, max_sweeps=60000,
+                                chunk_sweeps=10) for k in range(3)]
+    outs = {}
+    for timed in (False, True):
+        xorsat.profile_enable(timed)
+        try:
+            outs[timed] = [xorsat.run(h, budget)] + xorsat.run_batch(hs, batch)
+        finally:
+            xorsat.profile_enable(False)
+    xorsat.profile_read(reset=True)  # leave no timing totals to later tests
+    for a, b in zip(outs[False], outs[True]):
+        assert torch.equal(a.state, b.state)
+        assert torch.equal(a.first_hit, b.first_hit)
+        assert torch.equal(a.energy, b.energy)
+        assert (a.tts_sweeps, a.winner_clone, a.end_sweep) == (b.tts_sweeps, b.winner_clone,
+                                                               b.end_sweep)
+    assert outs[False][0].end_sweep == 12000
+    assert_parity(inst, h, budget, outs[False][0], clones=np.r_[0:32, 4064:4096])
+
+
 def test_batch_equals_single_runs():
     """Uneven instances in one batched run give bit-identical results to one run each."""
     torch = _torch()
