@@ -843,7 +843,14 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
                 .count();
         if (ms < 2.0 * group && group < 64) group *= 2;
     }
-    for (int k = 0; k < count; ++k) XS_HIP(xs::launch_final(d_inst + k, h[k], stream));
+    {
+        uint32_t max_words = 0, max_n = 0;
+        for (int k = 0; k < count; ++k) {
+            max_words = std::max(max_words, h[k].n_words);
+            max_n = std::max(max_n, h[k].n);
+        }
+        XS_HIP(xs::launch_final(d_inst, count, max_words, max_n, stream));
+    }
     std::vector<xs::InstDev> out(count);
     XS_HIP(hipMemcpyAsync(out.data(), d_inst, sizeof(xs::InstDev) * count, hipMemcpyDeviceToHost,
                           stream));

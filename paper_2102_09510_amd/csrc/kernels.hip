@@ -604,10 +604,14 @@ __global__ __launch_bounds__(256) void qg_decide(InstDev *insts, int count, uint
 
 // ------------------------------------------------------------------------------ final pass
 
+// Final pass. Each kernel serves instance I + blockIdx.y, so one launch covers a whole batch
+// (grids sized for the batch's largest instance; threads beyond an instance's range return).
+//
 // Energies at the end sweep, E = 2U - N, from bit-sliced counters of unsatisfied triplets (one
 // thread per 64-clone word). A clone whose end configuration is a ground state and has no
 // recorded hit gets first_hit = end sweep.
 __global__ __launch_bounds__(256) void qg_energy(InstDev *I) {
+    I += blockIdx.y;
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t W = I->n_words, n = I->n;
     if (w >= W) return;
@@ -640,6 +644,7 @@ __global__ __launch_bounds__(256) void qg_energy(InstDev *I) {
 }
 
 __global__ __launch_bounds__(256) void qg_tts(InstDev *I) {
+    I += blockIdx.y;
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= (size_t)I->n_words * 64) return;
     const int32_t f = I->first_hit[c];
@@ -647,12 +652,14 @@ __global__ __launch_bounds__(256) void qg_tts(InstDev *I) {
 }
 
 __global__ __launch_bounds__(256) void qg_winner(InstDev *I) {
+    I += blockIdx.y;
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= (size_t)I->n_words * 64) return;
     if (I->tts != INT32_MAX && I->first_hit[c] == I->tts) atomicMin(&I->winner, (int32_t)c);
 }
 
 __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
+    I += blockIdx.y;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= I->n || I->winner == INT32_MAX) return;
     const uint32_t c = (uint32_t)I->winner;
@@ -742,13 +749,17 @@ hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_final(InstDev *d_inst, const InstDev &h, hipStream_t s) {
-    const uint64_t n_clones = (uint64_t)h.n_words * 64;
-    hipLaunchKernelGGL(qg_energy, dim3((h.n_words + 255) / 256), dim3(256), 0, s, d_inst);
-    hipLaunchKernelGGL(qg_tts, dim3((uint32_t)((n_clones + 255) / 256)), dim3(256), 0, s, d_inst);
-    hipLaunchKernelGGL(qg_winner, dim3((uint32_t)((n_clones + 255) / 256)), dim3(256), 0, s,
-                       d_inst);
-    hipLaunchKernelGGL(qg_gather, dim3((h.n + 255) / 256), dim3(256), 0, s, d_inst);
+hipError_t launch_final(InstDev *d_insts, int count, uint32_t max_words, uint32_t max_n,
+                        hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const uint64_t max_clones = (uint64_t)max_words * 64;
+    const dim3 g_words((max_words + 255) / 256, (uint32_t)count);
+    const dim3 g_clones((uint32_t)((max_clones + 255) / 256), (uint32_t)count);
+    const dim3 g_spins((max_n + 255) / 256, (uint32_t)count);
+    hipLaunchKernelGGL(qg_energy, g_words, dim3(256), 0, s, d_insts);
+    hipLaunchKernelGGL(qg_tts, g_clones, dim3(256), 0, s, d_insts);
+    hipLaunchKernelGGL(qg_winner, g_clones, dim3(256), 0, s, d_insts);
+    hipLaunchKernelGGL(qg_gather, g_spins, dim3(256), 0, s, d_insts);
     return hipGetLastError();
 }
 

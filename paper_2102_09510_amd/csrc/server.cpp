@@ -259,7 +259,7 @@ struct xs_server {
                 stats.clone_spin_updates +=
                     (uint64_t)h[k].n_words * 64 * h[k].n * (h[k].t_cur - t_before[k]);
                 if (h[k].done) {
-                    XS_HIP(xs::launch_final(d_inst + k, h[k], stream));
+                    XS_HIP(xs::launch_final(d_inst + k, 1, h[k].n_words, h[k].n, stream));
                     any_done = true;
                 }
             }

@@ -55,6 +55,9 @@ hipError_t launch_chunk(InstDev *d_insts, const uint2 *d_tiles, int n_tiles, int
                         int col_bytes, bool rec_global, bool met, size_t lds_bytes,
                         hipStream_t s);
 hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStream_t s);
-hipError_t launch_final(InstDev *d_inst, const InstDev &h_inst, hipStream_t s);
+// The final pass (energies, end-sweep ground states, TTS, winner, its spins) of the count
+// consecutive descriptors at d_insts; max_words and max_n bound their n_words and n.
+hipError_t launch_final(InstDev *d_insts, int count, uint32_t max_words, uint32_t max_n,
+                        hipStream_t s);
 size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, bool rec_global, bool met);
 }  // namespace xs
