@@ -14,14 +14,15 @@
 //   LDS            rec  [n]      16-byte records in step order, u16 fields: byte offsets of
 //                               the spin's own row and of the two other spins of each of its
 //                               three triplets, then meta = i | jbits << 13;
-//                  state [n][32*B] the tile's rows;
+//                  state [n][32*B] the tile's rows, spin i in row rowmap[i] when the host
+//                               placed the rows (tiles under eight blocks), else in row i;
 //                  rbits [n][B]  k = 1 acceptance bits of the current sweep, one byte per
 //                               (position, block): bit k belongs to group k of the block;
 //                  acc   [8*B]   per-group OR of "some triplet of the visited spin is
 //                               unsatisfied" over the current sweep.
-//   task           one spin of the current step x 16 bytes of its row (2 words, 4 groups,
-//                  128 clones). Consecutive threads take consecutive 16-byte columns of the
-//                  same row, so a wave reads contiguous LDS runs.
+//   task           one spin of the current step x one CW-byte column of its row (CW = 16, 8
+//                  or 4: 128, 64 or 32 clones). Consecutive threads take consecutive columns
+//                  of the same row, so a wave reads contiguous LDS runs.
 //
 // Per update, with p_t = x_a ^ x_b ^ j_t the value that satisfies triplet t of spin x:
 //   k = #{t : x != p_t};  m = majority(p1, p2, p3) is the new spin when k != 1 (k = 0 keeps
