@@ -105,6 +105,7 @@ def test_first_ground_state_with_placed_rows():
     (257, 1024, 1, 5, 23, False),  # N just above 256, one-block tiles
     (257, 1024, 1, 5, 23, True),
     (4, 256, 1, 1, 9, True),       # smallest instance and clone count (too small to place)
+    (64, 8192, 32, 10, 30, False),  # largest tile: 32 blocks, n * B = 2048 (1,024-byte rows)
 ])
 def test_budget_runs_every_clone(n, clones, B, chunk, sweeps, place):
     run_and_check_full(n, 500 + n, clones, max_sweeps=sweeps, stop=False, chunk=chunk,
