@@ -580,6 +580,9 @@ TuneKey tune_key(uint32_t n, uint32_t clones, int32_t count) {
 // Capture of the chunk loop: `group` chunk iterations recorded once on a private stream and
 // replayed on the caller's stream (the caller's stream may be the null stream, which cannot be
 // captured).
+// Chunks per captured graph of the chunk loop (a power of two).
+constexpr int kGraphChunks = 8;
+
 struct ChunkGraph {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -806,11 +809,14 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
                 ev.push_back(e);
             }
         if (!timed && opt.graph && group >= 2) {
-            if (cg.group != group) {
+            // A graph of at most kGraphChunks chunks, launched group / g times: larger groups
+            // reuse it instead of capturing and instantiating a graph per size.
+            const int g = std::min(group, kGraphChunks);
+            if (cg.group != g) {
                 cg.reset();
                 if (!cg.cap) XS_HIP(hipStreamCreateWithFlags(&cg.cap, hipStreamNonBlocking));
                 XS_HIP(hipStreamBeginCapture(cg.cap, hipStreamCaptureModeRelaxed));
-                const xs_status st = enqueue_chunks(cg.cap, group, false);
+                const xs_status st = enqueue_chunks(cg.cap, g, false);
                 hipGraph_t gph = nullptr;
                 const hipError_t e_end = hipStreamEndCapture(cg.cap, &gph);
                 if (st != XS_OK) {
@@ -820,9 +826,9 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
                 XS_HIP(e_end);
                 cg.graph = gph;
                 XS_HIP(hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0));
-                cg.group = group;
+                cg.group = g;
             }
-            XS_HIP(hipGraphLaunch(cg.exec, stream));
+            for (int r = 0; r < group / g; ++r) XS_HIP(hipGraphLaunch(cg.exec, stream));
         } else {
             const xs_status st = enqueue_chunks(stream, group, timed);
             if (st != XS_OK) return st;
