@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--clones", type=int, default=65536)
+    ap.add_argument("--place-rows", action="store_true",
+                    help="batched: build the LDS row placement whatever the run length "
+                         "(tiles under eight blocks, large N; speed only)")
     ap.add_argument("--budget", type=int, default=50000,
                     help="sweep budget per instance and step (first ground states at N=256 "
                          "take far longer, so most instances end at the budget)")
@@ -708,7 +711,7 @@ def main():
                                    instance_id=k, accept_thr=THR_PAPER,
                                    accept_thr0=args.accept_thr0, max_sweeps=args.budget,
                                    stop_on_first=args.accept_thr0 == 0,
-                                   chunk_sweeps=args.chunk)
+                                   chunk_sweeps=args.chunk, place_rows=args.place_rows)
                 for k in range(args.instances)]
         return xorsat.run_batch(handles, cfgs, want_energy=True)
 
@@ -765,7 +768,8 @@ def main():
                                 f"{args.accept_thr0}/65536" if args.accept_thr0 else
                                 f"to first ground state or {args.budget} sweeps per step"),
                    "chunk_sweeps": args.chunk, "accept_thr": THR_PAPER, "colour_cap": args.cap,
-                   **({"accept_thr0": args.accept_thr0} if args.accept_thr0 else {})},
+                   **({"accept_thr0": args.accept_thr0} if args.accept_thr0 else {}),
+                   **({"place_rows": True} if args.place_rows else {})},
         "tts_sweeps": {"solved": len(tts), "censored": censored,
                        "p50": float(np.percentile(tts, 50)) if tts else None,
                        "p99": float(np.percentile(tts, 99)) if tts else None},
