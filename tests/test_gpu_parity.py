@@ -112,6 +112,28 @@ def test_budget_runs_every_clone(n, clones, B, chunk, sweeps, place):
                        tile_blocks=B, place=place)
 
 
+@pytest.mark.parametrize("jdup", [1, -1])
+def test_repeated_triplet_instance(jdup):
+    """An instance with a repeated triplet (each copy counted, as in the energy) and triplets
+    sharing two spins: every clone matches the oracle. With opposite couplings on the two copies
+    one of them is always unsatisfied, so no clone can reach E = -N and the run ends at its
+    budget unsolved."""
+    import types
+
+    tri = np.array([[0, 1, 2], [0, 1, 2], [0, 3, 4], [1, 3, 5], [2, 4, 5], [3, 4, 5]], np.int32)
+    J = np.array([1, jdup, -1, 1, -1, 1], np.int8)
+    inst = types.SimpleNamespace(tri=tri, J=J)
+    _torch()
+    h = xorsat.Instance(tri, J)
+    cfg = xorsat.make_config(n_clones=2048, seed=77, instance_id=9, accept_thr=THR_PAPER,
+                             max_sweeps=60, stop_on_first=False, chunk_sweeps=7)
+    out = xorsat.run(h, cfg)
+    ref = assert_parity(inst, h, cfg, out)
+    if jdup == -1:
+        assert np.all(ref["first_hit"] == -1) and out.tts_sweeps == -1
+        assert out.energy.min().item() > -6
+
+
 @pytest.mark.parametrize("thr", [0, 65536])
 def test_deterministic_rules(thr):
     """w1 = 0 (greedy) and w1 = 1 (every spin with k >= 1 flips)."""
