@@ -106,10 +106,28 @@ def test_first_ground_state_with_placed_rows():
     (257, 1024, 1, 5, 23, True),
     (4, 256, 1, 1, 9, True),       # smallest instance and clone count (too small to place)
     (64, 8192, 32, 10, 30, False),  # largest tile: 32 blocks, n * B = 2048 (1,024-byte rows)
+    (50, 768, 0, 9, 20, True),      # three 256-clone blocks: one-block tiles, ragged batch
 ])
 def test_budget_runs_every_clone(n, clones, B, chunk, sweeps, place):
     run_and_check_full(n, 500 + n, clones, max_sweeps=sweeps, stop=False, chunk=chunk,
                        tile_blocks=B, place=place)
+
+
+def test_ferromagnet_instance():
+    """The paper's own model, J = +1 on every triplet (its ground state is all spins up): every
+    clone matches the oracle, and the solved configuration is a ground state."""
+    import types
+
+    _torch()
+    base = planted_instance(120, 31)
+    inst = types.SimpleNamespace(tri=base.tri, J=np.ones(120, np.int8))
+    h = xorsat.Instance(inst.tri, inst.J)
+    cfg = xorsat.make_config(n_clones=4096, seed=123, instance_id=4, max_sweeps=20000,
+                             chunk_sweeps=50)
+    out = xorsat.run(h, cfg)
+    assert_parity(inst, h, cfg, out)
+    if out.winner_clone >= 0:
+        assert oracle.energy(inst.tri, inst.J, out.solved) == -120
 
 
 @pytest.mark.parametrize("jdup", [1, -1])
