@@ -637,11 +637,16 @@ def workload_single(args, xorsat, torch):
         torch.cuda.synchronize()
         secs.append(time.perf_counter() - t1)
         one.append(o.tts_sweeps)
-    t0 = time.perf_counter()
-    batch = xorsat.run_batch([h] * runs, [cfg(r) for r in range(runs)], want_energy=False)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    assert [o.tts_sweeps for o in batch] == one
+    # The first batched call also pays one-time costs outside the sweeps: the process's first
+    # graph instantiation and, in Python, a full garbage collection set off by the call's
+    # allocations. The second, identical call shows the steady cost.
+    t_batch = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        batch = xorsat.run_batch([h] * runs, [cfg(r) for r in range(runs)], want_energy=False)
+        torch.cuda.synchronize()
+        t_batch.append(time.perf_counter() - t0)
+        assert [o.tts_sweeps for o in batch] == one
     tts = np.array(one)
     return {"metric": "TTS (sweeps, seconds) of single runs, N=64, 1024 clones",
             "config": {"workload": f"1 planted instance, N={n}, {ncl} clones, {runs} seeds, "
@@ -649,7 +654,8 @@ def workload_single(args, xorsat, torch):
             "solved": int((tts >= 0).sum()),
             "tts_sweeps_p50": pct(tts[tts >= 0], 50), "tts_sweeps_p99": pct(tts[tts >= 0], 99),
             "one_at_a_time_s_p50": pct(secs, 50), "one_at_a_time_s_p99": pct(secs, 99),
-            "batched_all_runs_s": round(t_batch, 4),
+            "batched_all_runs_s": round(t_batch[1], 4),
+            "batched_all_runs_first_call_s": round(t_batch[0], 4),
             "cpu_baseline": cpu_baseline_single(inst, args.cap, [cfg(r) for r in range(20)],
                                                 [o.sweeps_done for o in batch[:20]], one[:20])}
 
