@@ -35,7 +35,7 @@ extern "C" {
 typedef int32_t xs_status;
 #define XS_OK 0
 #define XS_EINVAL 1      /* an argument or an instance breaks a stated rule */
-#define XS_ENOMEM 2      /* host or device allocation failed */
+#define XS_ENOMEM 2      /* host or device allocation failed (or a thread could not start) */
 #define XS_EDEVICE 3     /* a HIP call failed (the message names it) */
 #define XS_EAGAIN 4      /* the server cannot admit the request now */
 #define XS_ENOTFOUND 5   /* unknown ticket */

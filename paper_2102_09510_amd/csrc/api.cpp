@@ -919,39 +919,41 @@ const char *xs_last_error(void) { return g_last_error.c_str(); }
 
 xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int8_t *J,
                              int32_t colour_cap, xs_instance **out) {
-    if (!out) return fail(XS_EINVAL, "out is null");
-    *out = nullptr;
-    if (!tri || !J) return fail(XS_EINVAL, "tri and J are required");
-    if (n < 4 || n > XS_MAX_N) return fail(XS_EINVAL, "n = %d outside [4, %d]", n, XS_MAX_N);
-    if (m != n) return fail(XS_EINVAL, "m = %d must equal n = %d", m, n);
-    if (colour_cap < 0 || colour_cap > XS_MAX_N)
-        return fail(XS_EINVAL, "colour_cap = %d outside [0, %d]", colour_cap, XS_MAX_N);
-    std::vector<int32_t> deg(n, 0);
-    for (int t = 0; t < m; ++t) {
-        const int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
-        if (a < 0 || a >= n || b < 0 || b >= n || c < 0 || c >= n)
-            return fail(XS_EINVAL, "triplet %d has an index outside [0, %d)", t, n);
-        if (a == b || a == c || b == c)
-            return fail(XS_EINVAL, "triplet %d repeats a spin", t);
-        if (J[t] != 1 && J[t] != -1) return fail(XS_EINVAL, "J[%d] = %d is not +1/-1", t, J[t]);
-        ++deg[a];
-        ++deg[b];
-        ++deg[c];
-    }
-    for (int v = 0; v < n; ++v)
-        if (deg[v] != 3) return fail(XS_EINVAL, "spin %d is in %d triplets, not 3", v, deg[v]);
-    xs_instance *I = new (std::nothrow) xs_instance;
-    if (!I) return fail(XS_ENOMEM, "host allocation failed");
-    I->n = n;
-    I->cap = colour_cap ? colour_cap : 32;
-    I->tri.assign(tri, tri + 3 * (size_t)m);
-    I->J.assign(J, J + m);
-    partition(*I);
-    build_triplets(*I);
-    // uncapped steps, reported by get_info
-    I->sched.emplace(sched_key(0, 0), make_schedule(*I, 0, 0, 0));
-    *out = I;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!out) return fail(XS_EINVAL, "out is null");
+        *out = nullptr;
+        if (!tri || !J) return fail(XS_EINVAL, "tri and J are required");
+        if (n < 4 || n > XS_MAX_N) return fail(XS_EINVAL, "n = %d outside [4, %d]", n, XS_MAX_N);
+        if (m != n) return fail(XS_EINVAL, "m = %d must equal n = %d", m, n);
+        if (colour_cap < 0 || colour_cap > XS_MAX_N)
+            return fail(XS_EINVAL, "colour_cap = %d outside [0, %d]", colour_cap, XS_MAX_N);
+        std::vector<int32_t> deg(n, 0);
+        for (int t = 0; t < m; ++t) {
+            const int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+            if (a < 0 || a >= n || b < 0 || b >= n || c < 0 || c >= n)
+                return fail(XS_EINVAL, "triplet %d has an index outside [0, %d)", t, n);
+            if (a == b || a == c || b == c)
+                return fail(XS_EINVAL, "triplet %d repeats a spin", t);
+            if (J[t] != 1 && J[t] != -1) return fail(XS_EINVAL, "J[%d] = %d is not +1/-1", t, J[t]);
+            ++deg[a];
+            ++deg[b];
+            ++deg[c];
+        }
+        for (int v = 0; v < n; ++v)
+            if (deg[v] != 3) return fail(XS_EINVAL, "spin %d is in %d triplets, not 3", v, deg[v]);
+        xs_instance *I = new (std::nothrow) xs_instance;
+        if (!I) return fail(XS_ENOMEM, "host allocation failed");
+        I->n = n;
+        I->cap = colour_cap ? colour_cap : 32;
+        I->tri.assign(tri, tri + 3 * (size_t)m);
+        I->J.assign(J, J + m);
+        partition(*I);
+        build_triplets(*I);
+        // uncapped steps, reported by get_info
+        I->sched.emplace(sched_key(0, 0), make_schedule(*I, 0, 0, 0));
+        *out = I;
+        return XS_OK;
+    });
 }
 
 void xs_instance_destroy(xs_instance *I) {
@@ -973,198 +975,220 @@ void xs_instance_destroy(xs_instance *I) {
 }
 
 xs_status xs_instance_get_info(const xs_instance *I, xs_instance_info *info) {
-    if (!I || !info) return fail(XS_EINVAL, "null argument");
-    info->n = I->n;
-    info->n_classes = (int32_t)I->class_off.size() - 1;
-    info->colour_cap = I->cap;
-    info->max_class = I->max_class;
-    std::lock_guard<std::mutex> lock(I->mu);
-    const xsh::HostSched &lv = I->sched.at(sched_key(0, 0));
-    info->n_levels = (int32_t)lv.off.size() - 1;
-    info->max_level = lv.max_step;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!I || !info) return fail(XS_EINVAL, "null argument");
+        info->n = I->n;
+        info->n_classes = (int32_t)I->class_off.size() - 1;
+        info->colour_cap = I->cap;
+        info->max_class = I->max_class;
+        std::lock_guard<std::mutex> lock(I->mu);
+        const xsh::HostSched &lv = I->sched.at(sched_key(0, 0));
+        info->n_levels = (int32_t)lv.off.size() - 1;
+        info->max_level = lv.max_step;
+        return XS_OK;
+    });
 }
 
 xs_status xs_instance_get_partition(const xs_instance *I, int32_t *perm, int32_t *class_off) {
-    if (!I || !perm || !class_off) return fail(XS_EINVAL, "null argument");
-    std::memcpy(perm, I->perm.data(), sizeof(int32_t) * I->perm.size());
-    std::memcpy(class_off, I->class_off.data(), sizeof(int32_t) * I->class_off.size());
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!I || !perm || !class_off) return fail(XS_EINVAL, "null argument");
+        std::memcpy(perm, I->perm.data(), sizeof(int32_t) * I->perm.size());
+        std::memcpy(class_off, I->class_off.data(), sizeof(int32_t) * I->class_off.size());
+        return XS_OK;
+    });
 }
 
 xs_status xs_instance_get_schedule(const xs_instance *I, uint32_t step_cap, int32_t *order,
                                    int32_t *step_off, int32_t *n_steps) {
-    if (!I || !order || !step_off || !n_steps) return fail(XS_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lock(I->mu);
-    const uint32_t cap = std::min<uint32_t>(step_cap, 0xFFFFu);  // at least n: no limit
-    auto it = I->sched.find(sched_key(cap, 0));
-    if (it == I->sched.end())
-        it = I->sched.emplace(sched_key(cap, 0), make_schedule(*I, cap, 0, 0)).first;
-    const xsh::HostSched &hs = it->second;
-    std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
-    std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());
-    *n_steps = (int32_t)hs.off.size() - 1;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!I || !order || !step_off || !n_steps) return fail(XS_EINVAL, "null argument");
+        std::lock_guard<std::mutex> lock(I->mu);
+        const uint32_t cap = std::min<uint32_t>(step_cap, 0xFFFFu);  // at least n: no limit
+        auto it = I->sched.find(sched_key(cap, 0));
+        if (it == I->sched.end())
+            it = I->sched.emplace(sched_key(cap, 0), make_schedule(*I, cap, 0, 0)).first;
+        const xsh::HostSched &hs = it->second;
+        std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
+        std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());
+        *n_steps = (int32_t)hs.off.size() - 1;
+        return XS_OK;
+    });
 }
 
 xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count, void *stream_v,
                       xs_tune_result *out) {
-    if (!inst || !out || count <= 0) return fail(XS_EINVAL, "null argument or count <= 0");
-    if (n_clones == 0 || n_clones % XS_CLONE_QUANTUM)
-        return fail(XS_EINVAL, "n_clones %u is not a positive multiple of %d", n_clones,
-                    XS_CLONE_QUANTUM);
-    hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
-    const uint32_t n = (uint32_t)inst->n, nb = n_clones / 256;
-    const size_t state_bytes = (size_t)n * n_clones / 8;
-    const int copies = (int)std::max<size_t>(1, std::min<size_t>((size_t)count,
-                                                                 (size_t(2) << 30) / state_bytes));
-    // Sweeps per trial: about 4e10 clone-spin updates, between 8 and 200.
-    const double upd_per_sweep = (double)copies * n_clones * n;
-    const uint32_t sweeps = (uint32_t)std::min(200.0, std::max(8.0, 4e10 / upd_per_sweep));
-    uint8_t *mem = nullptr;
-    const size_t fh_bytes = sizeof(int32_t) * n_clones;
-    const size_t per = ((state_bytes + 255) & ~size_t(255)) + ((fh_bytes + 255) & ~size_t(255));
-    XS_HIP(hipMalloc(&mem, per * copies));
-    struct Free {
-        uint8_t *p;
-        ~Free() { if (p) (void)hipFree(p); }
-    } guard{mem};
-    std::vector<const xs_instance *> insts(copies, inst);
-    std::vector<xs_run_config> cfgs(copies);
-    std::vector<xs_run_buffers> bufs(copies);
-    std::vector<xs_run_result> res(copies);
-    for (int k = 0; k < copies; ++k) {
-        xs_run_config &c = cfgs[k];
-        std::memset(&c, 0, sizeof c);
-        c.struct_size = sizeof c;
-        c.instance_id = (uint32_t)k;
-        c.seed = 0x5EEDull + k;
-        c.n_clones = n_clones;
-        c.accept_thr = 3604;
-        c.max_sweeps = sweeps;
-        c.chunk_sweeps = sweeps;
-        bufs[k].state = reinterpret_cast<uint64_t *>(mem + per * k);
-        bufs[k].first_hit = reinterpret_cast<int32_t *>(mem + per * k + ((state_bytes + 255) & ~size_t(255)));
-        bufs[k].energy = nullptr;
-        bufs[k].solved = nullptr;
-    }
-    std::memset(out, 0, sizeof *out);
-    for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
-        if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, true, false) > 160 * 1024) continue;
-        for (uint32_t T = 128; T <= 1024; T *= 2) {
-            if (T < 8 * B || (T == 128 && B > 2)) continue;
-            for (uint32_t C = 4; C <= 16; C *= 2)
-                for (uint32_t G = (n >= 512 ? 1u : 2u); G <= 2; ++G) {
-                    // skip columns that leave most threads without a task in a full step
-                    if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
-                        continue;
-                    if (xs::chunk_lds_bytes(n, B, G == 1, false) > 160 * 1024) continue;
-                    for (auto &c : cfgs) {
-                        c.tile_blocks = B;
-                        c.wg_threads = T;
-                        c.col_bytes = C;
-                        c.rec_global = G;
-                    }
-                    RunOpts opt;
-                    double ms = 0.0;
-                    opt.kernel_ms = &ms;
-                    xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(),
-                                             stream, res.data(), opt);  // warm
-                    if (st != XS_OK) return st;
-                    ms = 0.0;
-                    st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
-                                   res.data(), opt);
-                    if (st != XS_OK) return st;
-                    uint64_t upd = 0;
-                    for (auto &r : res) upd += r.clone_spin_updates;
-                    const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
-                    out->trials[out->n_trials++] = xs_tune_trial{B, T, C, G, rate};
-                    if (rate > out->updates_per_ns) {
-                        out->updates_per_ns = rate;
-                        out->tile_blocks = B;
-                        out->wg_threads = T;
-                        out->col_bytes = C;
-                        out->rec_global = G;
-                    }
-                }
+    return guarded([&]() -> xs_status {
+        if (!inst || !out || count <= 0) return fail(XS_EINVAL, "null argument or count <= 0");
+        if (n_clones == 0 || n_clones % XS_CLONE_QUANTUM)
+            return fail(XS_EINVAL, "n_clones %u is not a positive multiple of %d", n_clones,
+                        XS_CLONE_QUANTUM);
+        hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+        const uint32_t n = (uint32_t)inst->n, nb = n_clones / 256;
+        const size_t state_bytes = (size_t)n * n_clones / 8;
+        const int copies = (int)std::max<size_t>(1, std::min<size_t>((size_t)count,
+                                                                     (size_t(2) << 30) / state_bytes));
+        // Sweeps per trial: about 4e10 clone-spin updates, between 8 and 200.
+        const double upd_per_sweep = (double)copies * n_clones * n;
+        const uint32_t sweeps = (uint32_t)std::min(200.0, std::max(8.0, 4e10 / upd_per_sweep));
+        uint8_t *mem = nullptr;
+        const size_t fh_bytes = sizeof(int32_t) * n_clones;
+        const size_t per = ((state_bytes + 255) & ~size_t(255)) + ((fh_bytes + 255) & ~size_t(255));
+        XS_HIP(hipMalloc(&mem, per * copies));
+        struct Free {
+            uint8_t *p;
+            ~Free() { if (p) (void)hipFree(p); }
+        } guard{mem};
+        std::vector<const xs_instance *> insts(copies, inst);
+        std::vector<xs_run_config> cfgs(copies);
+        std::vector<xs_run_buffers> bufs(copies);
+        std::vector<xs_run_result> res(copies);
+        for (int k = 0; k < copies; ++k) {
+            xs_run_config &c = cfgs[k];
+            std::memset(&c, 0, sizeof c);
+            c.struct_size = sizeof c;
+            c.instance_id = (uint32_t)k;
+            c.seed = 0x5EEDull + k;
+            c.n_clones = n_clones;
+            c.accept_thr = 3604;
+            c.max_sweeps = sweeps;
+            c.chunk_sweeps = sweeps;
+            bufs[k].state = reinterpret_cast<uint64_t *>(mem + per * k);
+            bufs[k].first_hit = reinterpret_cast<int32_t *>(mem + per * k + ((state_bytes + 255) & ~size_t(255)));
+            bufs[k].energy = nullptr;
+            bufs[k].solved = nullptr;
         }
-    }
-    if (!out->n_trials) return fail(XS_EINVAL, "no valid launch configuration");
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[tune_key(n, n_clones, count)] = TuneVal{out->tile_blocks, out->wg_threads,
-                                                   out->col_bytes, out->rec_global,
-                                                   out->updates_per_ns};
-    return XS_OK;
+        std::memset(out, 0, sizeof *out);
+        for (uint32_t B = 1; B <= (uint32_t)xs::kMaxTileBlocks; B *= 2) {
+            if (nb % B || n * B > 2048 || xs::chunk_lds_bytes(n, B, true, false) > 160 * 1024) continue;
+            for (uint32_t T = 128; T <= 1024; T *= 2) {
+                if (T < 8 * B || (T == 128 && B > 2)) continue;
+                for (uint32_t C = 4; C <= 16; C *= 2)
+                    for (uint32_t G = (n >= 512 ? 1u : 2u); G <= 2; ++G) {
+                        // skip columns that leave most threads without a task in a full step
+                        if (32u * (8u * B / (C / 4)) < T / 4 || out->n_trials >= XS_TUNE_MAX_TRIALS)
+                            continue;
+                        if (xs::chunk_lds_bytes(n, B, G == 1, false) > 160 * 1024) continue;
+                        for (auto &c : cfgs) {
+                            c.tile_blocks = B;
+                            c.wg_threads = T;
+                            c.col_bytes = C;
+                            c.rec_global = G;
+                        }
+                        RunOpts opt;
+                        double ms = 0.0;
+                        opt.kernel_ms = &ms;
+                        xs_status st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(),
+                                                 stream, res.data(), opt);  // warm
+                        if (st != XS_OK) return st;
+                        ms = 0.0;
+                        st = run_batch(copies, insts.data(), cfgs.data(), bufs.data(), stream,
+                                       res.data(), opt);
+                        if (st != XS_OK) return st;
+                        uint64_t upd = 0;
+                        for (auto &r : res) upd += r.clone_spin_updates;
+                        const double rate = ms > 0 ? (double)upd / (ms * 1e6) : 0.0;
+                        out->trials[out->n_trials++] = xs_tune_trial{B, T, C, G, rate};
+                        if (rate > out->updates_per_ns) {
+                            out->updates_per_ns = rate;
+                            out->tile_blocks = B;
+                            out->wg_threads = T;
+                            out->col_bytes = C;
+                            out->rec_global = G;
+                        }
+                    }
+            }
+        }
+        if (!out->n_trials) return fail(XS_EINVAL, "no valid launch configuration");
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[tune_key(n, n_clones, count)] = TuneVal{out->tile_blocks, out->wg_threads,
+                                                       out->col_bytes, out->rec_global,
+                                                       out->updates_per_ns};
+        return XS_OK;
+    });
 }
 
 xs_status xs_tune_save(const char *path) {
-    if (!path) return fail(XS_EINVAL, "null path");
-    FILE *f = std::fopen(path, "w");
-    if (!f) return fail(XS_EINVAL, "cannot open %s for writing", path);
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    std::fprintf(f, "# n_bucket clones count_bucket tile_blocks wg_threads col_bytes "
-                    "rec_global updates_per_ns\n");
-    for (auto &kv : g_tune)
-        std::fprintf(f, "%u %u %u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
-                     kv.first.count_bucket, kv.second.tile_blocks, kv.second.wg_threads,
-                     kv.second.col_bytes, kv.second.rec_global, kv.second.rate);
-    std::fclose(f);
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!path) return fail(XS_EINVAL, "null path");
+        FILE *f = std::fopen(path, "w");
+        if (!f) return fail(XS_EINVAL, "cannot open %s for writing", path);
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        std::fprintf(f, "# n_bucket clones count_bucket tile_blocks wg_threads col_bytes "
+                        "rec_global updates_per_ns\n");
+        for (auto &kv : g_tune)
+            std::fprintf(f, "%u %u %u %u %u %u %u %.1f\n", kv.first.n_bucket, kv.first.clones,
+                         kv.first.count_bucket, kv.second.tile_blocks, kv.second.wg_threads,
+                         kv.second.col_bytes, kv.second.rec_global, kv.second.rate);
+        std::fclose(f);
+        return XS_OK;
+    });
 }
 
 xs_status xs_tune_load(const char *path) {
-    if (!path) return fail(XS_EINVAL, "null path");
-    FILE *f = std::fopen(path, "r");
-    if (!f) return fail(XS_ENOTFOUND, "cannot open %s", path);
-    char line[256];
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    while (std::fgets(line, sizeof line, f)) {
-        if (line[0] == '#') continue;
-        unsigned nb_, cl, cb, B, T, C, G;
-        double rate;
-        if (std::sscanf(line, "%u %u %u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &C, &G,
-                        &rate) != 8)
-            continue;
-        if (!B || (B & (B - 1)) || B > (unsigned)xs::kMaxTileBlocks || !T || (T & (T - 1)) ||
-            T < 64 || T > 1024 || T < 8 * B || (C != 4 && C != 8 && C != 16) ||
-            (G != 1 && G != 2))
-            continue;
-        g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, C, G, rate};
-    }
-    std::fclose(f);
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!path) return fail(XS_EINVAL, "null path");
+        FILE *f = std::fopen(path, "r");
+        if (!f) return fail(XS_ENOTFOUND, "cannot open %s", path);
+        char line[256];
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        while (std::fgets(line, sizeof line, f)) {
+            if (line[0] == '#') continue;
+            unsigned nb_, cl, cb, B, T, C, G;
+            double rate;
+            if (std::sscanf(line, "%u %u %u %u %u %u %u %lf", &nb_, &cl, &cb, &B, &T, &C, &G,
+                            &rate) != 8)
+                continue;
+            if (!B || (B & (B - 1)) || B > (unsigned)xs::kMaxTileBlocks || !T || (T & (T - 1)) ||
+                T < 64 || T > 1024 || T < 8 * B || (C != 4 && C != 8 && C != 16) ||
+                (G != 1 && G != 2))
+                continue;
+            g_tune[TuneKey{nb_, cl, cb}] = TuneVal{B, T, C, G, rate};
+        }
+        std::fclose(f);
+        return XS_OK;
+    });
 }
 
 xs_status xs_tune_clear(void) {
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune.clear();
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune.clear();
+        return XS_OK;
+    });
 }
 
 xs_status xs_profile_enable(int32_t on) {
-    std::lock_guard<std::mutex> lock(g_prof.mu);
-    g_prof.on = on != 0;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        std::lock_guard<std::mutex> lock(g_prof.mu);
+        g_prof.on = on != 0;
+        return XS_OK;
+    });
 }
 
 xs_status xs_profile_read(xs_kernel_stats *out, int32_t reset) {
-    if (!out) return fail(XS_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lock(g_prof.mu);
-    *out = g_prof.stats;
-    if (reset) g_prof.stats = xs_kernel_stats{};
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!out) return fail(XS_EINVAL, "null argument");
+        std::lock_guard<std::mutex> lock(g_prof.mu);
+        *out = g_prof.stats;
+        if (reset) g_prof.stats = xs_kernel_stats{};
+        return XS_OK;
+    });
 }
 
 xs_status xs_run(const xs_instance *inst, const xs_run_config *cfg, const xs_run_buffers *bufs,
                  void *stream, xs_run_result *result) {
-    return run_batch(1, &inst, cfg, bufs, reinterpret_cast<hipStream_t>(stream), result,
-                     RunOpts{});
+    return guarded([&]() -> xs_status {
+        return run_batch(1, &inst, cfg, bufs, reinterpret_cast<hipStream_t>(stream), result,
+                         RunOpts{});
+    });
 }
 
 xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
                        const xs_run_buffers *bufs, void *stream, xs_run_result *results) {
-    return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results,
-                     RunOpts{});
+    return guarded([&]() -> xs_status {
+        return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results,
+                         RunOpts{});
+    });
 }
 
 }  // extern "C"
@@ -1184,49 +1208,60 @@ extern "C" {
 xs_status xs_run_batch_async(int32_t count, const xs_instance *const *insts,
                              const xs_run_config *cfgs, const xs_run_buffers *bufs, void *stream,
                              xs_run_result *results, xs_pending **out) {
-    if (!out) return fail(XS_EINVAL, "null argument");
-    *out = nullptr;
-    if (count <= 0 || !insts || !cfgs || !bufs || !results)
-        return fail(XS_EINVAL, "empty or null batch");
-    for (int k = 0; k < count; ++k) {
-        xs_status st = validate_run(insts[k], &cfgs[k], &bufs[k], true);
-        if (st != XS_OK) return st;
-    }
-    int device = 0;
-    XS_HIP(hipGetDevice(&device));
-    xs_pending *p = new (std::nothrow) xs_pending;
-    if (!p) return fail(XS_ENOMEM, "host allocation failed");
-    p->insts.assign(insts, insts + count);
-    p->cfgs.assign(cfgs, cfgs + count);
-    p->bufs.assign(bufs, bufs + count);
-    p->results = results;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    try {
-        p->worker = std::thread([p, device, s]() {
-            if (hipSetDevice(device) != hipSuccess) {
-                p->status = XS_EDEVICE;
-                p->error = "hipSetDevice failed in the run thread";
-                return;
-            }
-            p->status = run_batch((int32_t)p->insts.size(), p->insts.data(), p->cfgs.data(),
-                                  p->bufs.data(), s, p->results, RunOpts{});
-            if (p->status != XS_OK) p->error = g_last_error;
-        });
-    } catch (...) {
-        delete p;
-        return fail(XS_ENOMEM, "could not start the run thread");
-    }
-    *out = p;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!out) return fail(XS_EINVAL, "null argument");
+        *out = nullptr;
+        if (count <= 0 || !insts || !cfgs || !bufs || !results)
+            return fail(XS_EINVAL, "empty or null batch");
+        for (int k = 0; k < count; ++k) {
+            xs_status st = validate_run(insts[k], &cfgs[k], &bufs[k], true);
+            if (st != XS_OK) return st;
+        }
+        int device = 0;
+        XS_HIP(hipGetDevice(&device));
+        xs_pending *p = new (std::nothrow) xs_pending;
+        if (!p) return fail(XS_ENOMEM, "host allocation failed");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        try {
+            p->insts.assign(insts, insts + count);
+            p->cfgs.assign(cfgs, cfgs + count);
+            p->bufs.assign(bufs, bufs + count);
+            p->results = results;
+            p->worker = std::thread([p, device, s]() {
+                if (hipSetDevice(device) != hipSuccess) {
+                    p->status = XS_EDEVICE;
+                    p->error = "hipSetDevice failed in the run thread";
+                    return;
+                }
+                p->status = guarded([&]() -> xs_status {
+                    return run_batch((int32_t)p->insts.size(), p->insts.data(), p->cfgs.data(),
+                                     p->bufs.data(), s, p->results, RunOpts{});
+                });
+                if (p->status != XS_OK) {
+                    try {
+                        p->error = g_last_error;
+                    } catch (...) {  // xs_wait still returns the status
+                    }
+                }
+            });
+        } catch (...) {
+            delete p;
+            return fail(XS_ENOMEM, "host allocation or run thread start failed");
+        }
+        *out = p;
+        return XS_OK;
+    });
 }
 
 xs_status xs_wait(xs_pending *p) {
-    if (!p) return fail(XS_EINVAL, "null argument");
-    p->worker.join();
-    const xs_status st = p->status;
-    if (st != XS_OK) g_last_error = p->error;
-    delete p;
-    return st;
+    return guarded([&]() -> xs_status {
+        if (!p) return fail(XS_EINVAL, "null argument");
+        p->worker.join();
+        const xs_status st = p->status;
+        if (st != XS_OK) g_last_error = p->error;
+        delete p;
+        return st;
+    });
 }
 
 }  // extern "C"

@@ -14,6 +14,7 @@
 #include "xs_host.h"
 
 using xsh::fail;
+using xsh::guarded;
 
 namespace {
 
@@ -322,23 +323,25 @@ struct xs_server {
 extern "C" {
 
 xs_status xs_server_create(const xs_server_config *cfg, void *stream, xs_server **out) {
-    if (!cfg || !out) return fail(XS_EINVAL, "null argument");
-    *out = nullptr;
-    if (cfg->struct_size < sizeof(xs_server_config))
-        return fail(XS_EINVAL, "xs_server_config.struct_size too small");
-    if (cfg->hbm_budget_bytes == 0) return fail(XS_EINVAL, "hbm_budget_bytes is 0");
-    if (cfg->reserved) return fail(XS_EINVAL, "xs_server_config.reserved must be 0");
-    xs_server *S = new (std::nothrow) xs_server;
-    if (!S) return fail(XS_ENOMEM, "host allocation failed");
-    S->cfg = *cfg;
-    S->stream = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = hipGetDevice(&S->device);
-    if (e != hipSuccess) {
-        delete S;
-        return fail(XS_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
-    }
-    *out = S;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!cfg || !out) return fail(XS_EINVAL, "null argument");
+        *out = nullptr;
+        if (cfg->struct_size < sizeof(xs_server_config))
+            return fail(XS_EINVAL, "xs_server_config.struct_size too small");
+        if (cfg->hbm_budget_bytes == 0) return fail(XS_EINVAL, "hbm_budget_bytes is 0");
+        if (cfg->reserved) return fail(XS_EINVAL, "xs_server_config.reserved must be 0");
+        xs_server *S = new (std::nothrow) xs_server;
+        if (!S) return fail(XS_ENOMEM, "host allocation failed");
+        S->cfg = *cfg;
+        S->stream = reinterpret_cast<hipStream_t>(stream);
+        hipError_t e = hipGetDevice(&S->device);
+        if (e != hipSuccess) {
+            delete S;
+            return fail(XS_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+        }
+        *out = S;
+        return XS_OK;
+    });
 }
 
 void xs_server_destroy(xs_server *srv) {
@@ -349,63 +352,78 @@ void xs_server_destroy(xs_server *srv) {
 
 xs_status xs_server_submit(xs_server *srv, const xs_instance *inst, const xs_run_config *cfg,
                            const xs_server_outputs *outs, uint64_t *ticket) {
-    if (!srv || !inst || !cfg || !ticket) return fail(XS_EINVAL, "null argument");
-    xs_run_buffers none{};
-    xs_status st = xsh::validate_run(inst, cfg, &none, false);
-    if (st != XS_OK) return st;
-    if (cfg->flags & XS_RESUME) return fail(XS_EINVAL, "XS_RESUME is not supported by the server");
-    if (srv->cfg.max_pending && srv->pending.size() >= srv->cfg.max_pending)
-        return fail(XS_EAGAIN, "%zu requests already wait for admission", srv->pending.size());
-    Request *r = new (std::nothrow) Request;
-    if (!r) return fail(XS_ENOMEM, "host allocation failed");
-    r->ticket = srv->next_ticket++;
-    r->inst = inst;
-    r->cfg = *cfg;
-    if (outs) r->outs = *outs;
-    r->bytes = footprint(inst, *cfg);
-    r->t_submit = now_s();
-    srv->pending.push_back(r);
-    srv->stats.pending = srv->pending.size();
-    *ticket = r->ticket;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!srv || !inst || !cfg || !ticket) return fail(XS_EINVAL, "null argument");
+        xs_run_buffers none{};
+        xs_status st = xsh::validate_run(inst, cfg, &none, false);
+        if (st != XS_OK) return st;
+        if (cfg->flags & XS_RESUME) return fail(XS_EINVAL, "XS_RESUME is not supported by the server");
+        if (srv->cfg.max_pending && srv->pending.size() >= srv->cfg.max_pending)
+            return fail(XS_EAGAIN, "%zu requests already wait for admission", srv->pending.size());
+        Request *r = new (std::nothrow) Request;
+        if (!r) return fail(XS_ENOMEM, "host allocation failed");
+        r->ticket = srv->next_ticket++;
+        r->inst = inst;
+        r->cfg = *cfg;
+        if (outs) r->outs = *outs;
+        r->bytes = footprint(inst, *cfg);
+        r->t_submit = now_s();
+        try {
+            srv->pending.push_back(r);
+        } catch (...) {
+            delete r;
+            throw;
+        }
+        srv->stats.pending = srv->pending.size();
+        *ticket = r->ticket;
+        return XS_OK;
+    });
 }
 
 xs_status xs_server_step(xs_server *srv, int32_t *n_active) {
-    if (!srv) return fail(XS_EINVAL, "null server");
-    return srv->step(n_active);
+    return guarded([&]() -> xs_status {
+        if (!srv) return fail(XS_EINVAL, "null server");
+        return srv->step(n_active);
+    });
 }
 
 xs_status xs_server_poll(xs_server *srv, xs_server_completion *done, int32_t cap,
                          int32_t *n_done) {
-    if (!srv || !n_done || (cap > 0 && !done)) return fail(XS_EINVAL, "null argument");
-    int32_t k = 0;
-    while (k < cap && !srv->completed.empty()) {
-        done[k++] = srv->completed.front();
-        srv->completed.pop_front();
-    }
-    *n_done = k;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!srv || !n_done || (cap > 0 && !done)) return fail(XS_EINVAL, "null argument");
+        int32_t k = 0;
+        while (k < cap && !srv->completed.empty()) {
+            done[k++] = srv->completed.front();
+            srv->completed.pop_front();
+        }
+        *n_done = k;
+        return XS_OK;
+    });
 }
 
 xs_status xs_server_cancel(xs_server *srv, uint64_t ticket) {
-    if (!srv) return fail(XS_EINVAL, "null server");
-    for (Request *r : srv->pending)
-        if (r->ticket == ticket && !r->canceled) {
-            r->canceled = true;
-            return XS_OK;
-        }
-    for (Request *r : srv->resident)
-        if (r->ticket == ticket && !r->canceled) {
-            r->canceled = true;
-            return XS_OK;
-        }
-    return fail(XS_ENOTFOUND, "ticket %llu is not queued or resident", (unsigned long long)ticket);
+    return guarded([&]() -> xs_status {
+        if (!srv) return fail(XS_EINVAL, "null server");
+        for (Request *r : srv->pending)
+            if (r->ticket == ticket && !r->canceled) {
+                r->canceled = true;
+                return XS_OK;
+            }
+        for (Request *r : srv->resident)
+            if (r->ticket == ticket && !r->canceled) {
+                r->canceled = true;
+                return XS_OK;
+            }
+        return fail(XS_ENOTFOUND, "ticket %llu is not queued or resident", (unsigned long long)ticket);
+    });
 }
 
 xs_status xs_server_get_stats(const xs_server *srv, xs_server_stats *out) {
-    if (!srv || !out) return fail(XS_EINVAL, "null argument");
-    *out = srv->stats;
-    return XS_OK;
+    return guarded([&]() -> xs_status {
+        if (!srv || !out) return fail(XS_EINVAL, "null argument");
+        *out = srv->stats;
+        return XS_OK;
+    });
 }
 
 }  // extern "C"

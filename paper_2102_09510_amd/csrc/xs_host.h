@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <exception>
 #include <map>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "../../include/xorsat.h"
@@ -82,6 +84,21 @@ struct DevAlloc {
 
 // Set the calling thread's last error message and return st.
 xs_status fail(xs_status st, const char *fmt, ...);
+// Run the body of a C entry point. Exceptions of the C++ library (a failed host allocation, a
+// vector too long, a thread that cannot start) become XS_ENOMEM and a message: none crosses
+// the C ABI.
+template <class F>
+xs_status guarded(F &&body) {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(XS_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(XS_ENOMEM, "host resource failure: %s", e.what());
+    } catch (...) {
+        return fail(XS_ENOMEM, "host resource failure");
+    }
+}
 // Device tables of an instance on `device`, uploaded on first use.
 xs_status ensure_tables(const xs_instance *I, int device, DeviceTables *out);
 // Check a run configuration and its buffers (state buffer ignored if check_buffers is false).
