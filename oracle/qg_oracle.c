@@ -44,7 +44,8 @@
  * random-number reading above, which the paper does not fix; the tests pin the rule itself
  * (per update, the deterministic w1 = 0 and w1 = 1 sweeps worked by hand, acceptance
  * frequencies, the energy change per flip, the absorbing ground state, the paramagnetic energy
- * of the w0 = w1^3 rule), not the stochastic trajectories.
+ * of the w0 = w1^3 rule) and, at N <= 12, the law of first_hit (and of the end state with
+ * w0 > 0) against the exact Markov chain over all configurations, not single trajectories.
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -55,3 +55,41 @@ def all_energies(n: int, tri: np.ndarray, J: np.ndarray) -> np.ndarray:
 def spins_of(n: int, idx: int) -> np.ndarray:
     """+1/-1 spins of configuration index idx (bit i set <=> s_i = -1)."""
     return np.array([-1 if (idx >> i) & 1 else 1 for i in range(n)], dtype=np.int8)
+
+
+
+def ground_law(n: int, tri: np.ndarray, J: np.ndarray, order, w1: float, w0: float,
+               n_sweeps: int) -> np.ndarray:
+    """Exact P(the configuration after t sweeps has E = -n), t = 0..n_sweeps, for one clone
+    started uniformly at random.
+
+    The clone's state is a Markov chain over the 2^n configurations: a sweep visits the spins in
+    `order`; a spin with k unsatisfied triplets among its own flips with probability w0 (k = 0),
+    w1 (k = 1) or 1 (k >= 2) (Section "The quasi-greedy algorithm"; w0 = 0 there, w0 > 0 the
+    Metropolis-like variant). The law of the state is propagated over all configurations, one
+    single-spin update at a time. With w0 = 0 a ground state has k = 0 at every spin and is never
+    left, so the result is then also P(first hit <= t)."""
+    assert n <= 14
+    x = np.arange(1 << n, dtype=np.int64)
+    ground = all_energies(n, tri, J) == -n
+    # unsat[t] is 1 where triplet t is unsatisfied (x_a ^ x_b ^ x_c ^ j_t = 1).
+    unsat = []
+    for t in range(tri.shape[0]):
+        a, b, c = (int(v) for v in tri[t])
+        j = 1 if J[t] < 0 else 0
+        unsat.append(((x >> a) ^ (x >> b) ^ (x >> c) ^ j) & 1)
+    p_flip = []
+    for i in range(n):
+        k = np.zeros(1 << n, dtype=np.int64)
+        for t in range(tri.shape[0]):
+            k += unsat[t] * sum(1 for v in tri[t] if int(v) == i)
+        p_flip.append(np.where(k == 0, w0, np.where(k == 1, w1, 1.0)))
+    p = np.full(1 << n, 1.0 / (1 << n))
+    out = np.zeros(n_sweeps + 1)
+    out[0] = p[ground].sum()
+    for t in range(1, n_sweeps + 1):
+        for i in order:
+            moved = p * p_flip[int(i)]
+            p = p - moved + moved[x ^ (1 << int(i))]
+        out[t] = p[ground].sum()
+    return out

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2102_09510_amd.instances import THR_PAPER, planted_instance
-from tests.pins import all_energies, gf2_rank_and_consistent, spins_of
+from tests.pins import all_energies, gf2_rank_and_consistent, ground_law, spins_of
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -425,3 +425,49 @@ def test_metropolis_first_hit_only_at_end():
                    n_sweeps=3, clone_count=4, init_spins=init)
     assert np.all((r["first_hit"] == 3) == (r["energy"] == -64))
     assert np.all(r["first_hit"][r["energy"] > -64] == -1)
+
+
+def _group_tolerance(F: np.ndarray, groups: int, z: float) -> np.ndarray:
+    """z standard deviations of a mean over `groups` independent 32-clone groups. A group's hit
+    fraction lies in [0, 1] with mean F, so its variance is at most F (1 - F), whatever the
+    correlation of the clones that share its draws."""
+    return z * np.sqrt(np.maximum(F * (1 - F), 1e-12) / groups)
+
+
+@pytest.mark.parametrize("n,seed", [(8, 3), (10, 3), (12, 3)])
+def test_first_hit_law_of_the_exact_chain(n, seed):
+    """The distribution of first_hit over 131,072 clones equals the exact law of the sweep as a
+    Markov chain over all 2^N configurations (Section "The quasi-greedy algorithm": k = 0 never
+    flips, k = 1 with probability w1, k >= 2 always), computed without the oracle by propagating
+    the law of the state. This pins the whole dynamics independently of the random stream:
+    doubling or halving w1 or inverting the k = 1 test moves the exact law by 11 to 45 times the
+    tolerance, and an off-by-one sweep in first_hit by 1.6 to 4.9 times (N = 12 to 10)."""
+    inst = planted_instance(n, seed)
+    perm, _ = oracle.colour(inst.tri, 32)
+    T, clones = 300, 131072
+    exact = ground_law(n, inst.tri, inst.J, perm, THR_PAPER / 65536, 0.0, T)
+    fh = oracle.run(inst.tri, inst.J, perm, seed=11, instance_id=0, thr=THR_PAPER, n_sweeps=T,
+                    clone_count=clones)["first_hit"]
+    emp = np.cumsum(np.bincount(fh[fh >= 0], minlength=T + 1)) / clones
+    assert np.all(np.abs(emp - exact) <= _group_tolerance(exact, clones // 32, 5.5) + 1e-9)
+    # Tighter than the worst case in practice: the clones of a group start independently.
+    assert np.abs(emp - exact).max() < 0.015
+
+
+@pytest.mark.parametrize("thr0", [3277, 13107])
+def test_metropolis_end_state_law_of_the_exact_chain(thr0):
+    """With w0 > 0 the share of clones whose configuration after T sweeps is a ground state
+    (the only first_hit the rule records) equals the exact chain's P(E = -N after T sweeps).
+    Halving w0 moves the exact values by 2.6 to 3.8 times the tolerance at some T, dropping it
+    (the quasi-greedy rule) by up to 49 times."""
+    n = 10
+    inst = planted_instance(n, 3)
+    perm, _ = oracle.colour(inst.tri, 32)
+    clones = 1 << 20
+    exact = ground_law(n, inst.tri, inst.J, perm, THR_PAPER / 65536, thr0 / 65536, 30)
+    for T in (1, 3, 10, 30):
+        r = oracle.run(inst.tri, inst.J, perm, seed=5, instance_id=0, thr=THR_PAPER, thr0=thr0,
+                       n_sweeps=T, clone_count=clones)
+        share = float(np.mean(r["first_hit"] == T))
+        assert abs(share - exact[T]) <= _group_tolerance(exact[T], clones // 32, 5.0), (T, share)
+
