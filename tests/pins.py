@@ -93,3 +93,11 @@ def ground_law(n: int, tri: np.ndarray, J: np.ndarray, order, w1: float, w0: flo
             p = p - moved + moved[x ^ (1 << int(i))]
         out[t] = p[ground].sum()
     return out
+
+
+def group_tolerance(F, groups: int, z: float):
+    """z standard deviations of a mean over `groups` independent 32-clone groups. A group's hit
+    fraction lies in [0, 1] with mean F, so its variance is at most F (1 - F), whatever the
+    correlation of the clones that share its draws."""
+    F = np.asarray(F, dtype=np.float64)
+    return z * np.sqrt(np.maximum(F * (1 - F), 1e-12) / groups)

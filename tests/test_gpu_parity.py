@@ -9,6 +9,7 @@ import pytest
 import oracle
 from paper_2102_09510_amd import xorsat
 from paper_2102_09510_amd.instances import THR_PAPER, planted_instance
+from tests.pins import ground_law, group_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -500,3 +501,42 @@ def test_async_batches_equal_sync():
     bad = xorsat.make_config(n_clones=300, seed=1)
     with pytest.raises(xorsat.XsError):
         xorsat.run_batch_async([hs[0]], [bad])
+
+
+@pytest.mark.parametrize("n", [8, 10, 12])
+def test_first_hit_law_of_the_exact_chain(n):
+    """Without the oracle: the GPU's first_hit distribution over 131,072 clones equals the exact
+    law of the sweep's Markov chain over all 2^N configurations (quasi-greedy rule), computed by
+    propagating the law of the state in the library's update order."""
+    _torch()
+    inst = planted_instance(n, 3)
+    h = xorsat.Instance(inst.tri, inst.J)
+    perm, _ = h.partition()
+    T, clones = 300, 131072
+    out = xorsat.run(h, xorsat.make_config(n_clones=clones, seed=23, max_sweeps=T,
+                                           stop_on_first=False))
+    assert out.sweeps_done == T
+    exact = ground_law(n, inst.tri, inst.J, perm, THR_PAPER / 65536, 0.0, T)
+    fh = out.first_hit.cpu().numpy()
+    emp = np.cumsum(np.bincount(fh[fh >= 0], minlength=T + 1)) / clones
+    assert np.all(np.abs(emp - exact) <= group_tolerance(exact, clones // 32, 5.5) + 1e-9)
+    assert np.abs(emp - exact).max() < 0.015
+
+
+@pytest.mark.parametrize("thr0", [3277, 13107])
+def test_metropolis_end_state_law_of_the_exact_chain(thr0):
+    """Without the oracle: with w0 > 0 the share of 2^20 clones in a ground state after T sweeps
+    equals the exact chain's P(E = -N after T sweeps)."""
+    _torch()
+    n = 10
+    inst = planted_instance(n, 3)
+    h = xorsat.Instance(inst.tri, inst.J)
+    perm, _ = h.partition()
+    clones = 1 << 20
+    exact = ground_law(n, inst.tri, inst.J, perm, THR_PAPER / 65536, thr0 / 65536, 30)
+    for T in (1, 3, 10, 30):
+        out = xorsat.run(h, xorsat.make_config(n_clones=clones, seed=29, max_sweeps=T,
+                                               stop_on_first=False, accept_thr0=thr0))
+        share = float((out.first_hit == T).float().mean())
+        assert abs(share - exact[T]) <= group_tolerance(exact[T], clones // 32, 5.0), (T, share)
+

@@ -12,7 +12,8 @@ import pytest
 
 import oracle
 from paper_2102_09510_amd.instances import THR_PAPER, planted_instance
-from tests.pins import all_energies, gf2_rank_and_consistent, ground_law, spins_of
+from tests.pins import (all_energies, gf2_rank_and_consistent, ground_law, group_tolerance,
+                        spins_of)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -427,13 +428,6 @@ def test_metropolis_first_hit_only_at_end():
     assert np.all(r["first_hit"][r["energy"] > -64] == -1)
 
 
-def _group_tolerance(F: np.ndarray, groups: int, z: float) -> np.ndarray:
-    """z standard deviations of a mean over `groups` independent 32-clone groups. A group's hit
-    fraction lies in [0, 1] with mean F, so its variance is at most F (1 - F), whatever the
-    correlation of the clones that share its draws."""
-    return z * np.sqrt(np.maximum(F * (1 - F), 1e-12) / groups)
-
-
 @pytest.mark.parametrize("n,seed", [(8, 3), (10, 3), (12, 3)])
 def test_first_hit_law_of_the_exact_chain(n, seed):
     """The distribution of first_hit over 131,072 clones equals the exact law of the sweep as a
@@ -449,7 +443,7 @@ def test_first_hit_law_of_the_exact_chain(n, seed):
     fh = oracle.run(inst.tri, inst.J, perm, seed=11, instance_id=0, thr=THR_PAPER, n_sweeps=T,
                     clone_count=clones)["first_hit"]
     emp = np.cumsum(np.bincount(fh[fh >= 0], minlength=T + 1)) / clones
-    assert np.all(np.abs(emp - exact) <= _group_tolerance(exact, clones // 32, 5.5) + 1e-9)
+    assert np.all(np.abs(emp - exact) <= group_tolerance(exact, clones // 32, 5.5) + 1e-9)
     # Tighter than the worst case in practice: the clones of a group start independently.
     assert np.abs(emp - exact).max() < 0.015
 
@@ -469,5 +463,5 @@ def test_metropolis_end_state_law_of_the_exact_chain(thr0):
         r = oracle.run(inst.tri, inst.J, perm, seed=5, instance_id=0, thr=THR_PAPER, thr0=thr0,
                        n_sweeps=T, clone_count=clones)
         share = float(np.mean(r["first_hit"] == T))
-        assert abs(share - exact[T]) <= _group_tolerance(exact[T], clones // 32, 5.0), (T, share)
+        assert abs(share - exact[T]) <= group_tolerance(exact[T], clones // 32, 5.0), (T, share)
 
