@@ -766,9 +766,6 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
 
     bool any_running = false;
     for (int k = 0; k < count; ++k) any_running |= !h[k].done;
-    // Chunk loop: a chunk launch over all tiles, then the device-side decision. The host reads
-    // the count of running instances every `group` chunks (finished instances' tiles exit at
-    // once, so launching ahead changes no result).
     int group = 1;
     bool profile;
     {
@@ -801,7 +798,6 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     // once, so launching ahead changes no result). Untimed loops of two or more chunks are
     // replayed from a captured graph.
     while (any_running) {
-        const auto c0 = std::chrono::steady_clock::now();
         if (timed)
             while (ev.size() < 2 * (size_t)group) {
                 hipEvent_t e;
@@ -844,10 +840,9 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
                 local.total_ms += ms;
                 local.launches += 1;
             }
-        const double ms =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0)
-                .count();
-        if (ms < 2.0 * group && group < 64) group *= 2;
+        // Read back less and less often: chunks launched after every instance has finished cost
+        // only their launch (every tile exits at once), while each read-back drains the GPU.
+        if (group < 64) group *= 2;
     }
     {
         uint32_t max_words = 0, max_n = 0;
