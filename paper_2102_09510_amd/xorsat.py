@@ -314,7 +314,9 @@ def run_batch(insts: list[Instance], cfgs: list[RunConfig], *, states=None,
               want_energy: bool = True, device="cuda") -> list[RunOutput]:
     """xs_run_batch over several instances (one chunk launch covers all of them)."""
     count = len(insts)
-    assert count == len(cfgs) and count > 0
+    if count == 0 or count != len(cfgs):
+        raise ValueError(f"need one config per instance and at least one instance "
+                         f"({count} instances, {len(cfgs)} configs)")
     states = states or [None] * count
     made = [_buffers(i, c, s, want_energy, device) for i, c, s in zip(insts, cfgs, states)]
     handles = (ctypes.c_void_p * count)(*[i.handle.value for i in insts])
@@ -344,7 +346,9 @@ def run_batch_async(insts: list[Instance], cfgs: list[RunConfig], *, want_energy
     """xs_run_batch_async: returns at once; Pending.wait() gives the outputs. `stream` (a torch
     stream) must not be used until then; default: the current stream."""
     count = len(insts)
-    assert count == len(cfgs) and count > 0
+    if count == 0 or count != len(cfgs):
+        raise ValueError(f"need one config per instance and at least one instance "
+                         f"({count} instances, {len(cfgs)} configs)")
     made = [_buffers(i, c, None, want_energy, device) for i, c in zip(insts, cfgs)]
     handles = (ctypes.c_void_p * count)(*[i.handle.value for i in insts])
     cfg_arr = (RunConfig * count)(*cfgs)

@@ -202,3 +202,13 @@ def test_instance_create_mutations(lib, n, seed, cap, mutate, where):
     operm, ooff = oracle.colour(tri, cap or 32)
     assert np.array_equal(perm, operm) and np.array_equal(off, ooff)
     h.close()
+
+
+def test_batch_binding_rejects_empty_and_mismatched_lists():
+    """The binding checks list lengths before any marshalling or device work."""
+    with pytest.raises(ValueError):
+        xorsat.run_batch([], [])
+    with pytest.raises(ValueError):
+        xorsat.run_batch([object()], [])
+    with pytest.raises(ValueError):
+        xorsat.run_batch_async([], [])
