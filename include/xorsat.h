@@ -45,6 +45,8 @@ typedef int32_t xs_status;
 #define XS_MAX_N 2048
 /* Clone counts are multiples of this (one random-number block: 8 groups of 32 clones). */
 #define XS_CLONE_QUANTUM 256
+/* Largest clone count: clone indices (the winner) are int32 with INT32_MAX meaning none. */
+#define XS_MAX_CLONES 0x7FFFFF00u
 
 /* Run flags (xs_run_config.flags). */
 #define XS_STOP_ON_FIRST 0x1u /* stop at the end of the first chunk after which some clone
@@ -119,7 +121,7 @@ typedef struct {
     uint32_t struct_size;
     uint32_t instance_id;  /* part of every random counter; keeps instances independent */
     uint64_t seed;         /* Philox key */
-    uint32_t n_clones;     /* > 0, multiple of XS_CLONE_QUANTUM */
+    uint32_t n_clones;     /* > 0, multiple of XS_CLONE_QUANTUM, <= XS_MAX_CLONES */
     uint32_t accept_thr;   /* w1 threshold, 0 .. 65536 */
     uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS */
     uint32_t max_sweeps;   /* sweep budget of this call (0 = only check the start state) */

@@ -476,6 +476,8 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
     if (cfg->n_clones == 0 || cfg->n_clones % XS_CLONE_QUANTUM != 0)
         return fail(XS_EINVAL, "n_clones %u is not a positive multiple of %d", cfg->n_clones,
                     XS_CLONE_QUANTUM);
+    if (cfg->n_clones > XS_MAX_CLONES)
+        return fail(XS_EINVAL, "n_clones %u > %u", cfg->n_clones, XS_MAX_CLONES);
     if (cfg->accept_thr > 65536) return fail(XS_EINVAL, "accept_thr %u > 65536", cfg->accept_thr);
     if (cfg->accept_thr0 > 65536)
         return fail(XS_EINVAL, "accept_thr0 %u > 65536", cfg->accept_thr0);
@@ -1017,6 +1019,8 @@ xs_status xs_autotune(const xs_instance *inst, uint32_t n_clones, int32_t count,
         if (n_clones == 0 || n_clones % XS_CLONE_QUANTUM)
             return fail(XS_EINVAL, "n_clones %u is not a positive multiple of %d", n_clones,
                         XS_CLONE_QUANTUM);
+        if (n_clones > XS_MAX_CLONES)
+            return fail(XS_EINVAL, "n_clones %u > %u", n_clones, XS_MAX_CLONES);
         hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
         const uint32_t n = (uint32_t)inst->n, nb = n_clones / 256;
         const size_t state_bytes = (size_t)n * n_clones / 8;

@@ -24,6 +24,7 @@ XS_RESUME = 0x2
 XS_PLACE_ROWS = 0x4
 XS_MAX_N = 2048
 XS_CLONE_QUANTUM = 256
+XS_MAX_CLONES = 0x7FFFFF00
 
 # Every function the header declares, for the export check.
 EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_create",

@@ -47,10 +47,13 @@ def test_header_constants_match_the_binding():
     defs = {m.group(1): int(m.group(2), 0)
             for m in re.finditer(r"#define\s+(XS_[A-Z_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text)}
     for name in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_MAX_N",
-                 "XS_CLONE_QUANTUM", "XS_TUNE_MAX_TRIALS"):
+                 "XS_CLONE_QUANTUM", "XS_MAX_CLONES", "XS_TUNE_MAX_TRIALS"):
         assert defs[name] == getattr(xorsat, name), name
     for code, name in xorsat.XS_STATUS.items():
         assert defs[name] == code, name
+    # The largest clone count is a whole number of quanta whose last index is below INT32_MAX.
+    assert defs["XS_MAX_CLONES"] % defs["XS_CLONE_QUANTUM"] == 0
+    assert defs["XS_MAX_CLONES"] - 1 < 2**31 - 1 < defs["XS_MAX_CLONES"] + defs["XS_CLONE_QUANTUM"]
     flags = [defs[k] for k in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS")]
     assert len(set(flags)) == 3 and all(f & (f - 1) == 0 for f in flags)
     cfg = xorsat.make_config(n_clones=256, seed=1, stop_on_first=False, place_rows=True)

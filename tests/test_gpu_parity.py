@@ -540,3 +540,24 @@ def test_metropolis_end_state_law_of_the_exact_chain(thr0):
         share = float((out.first_hit == T).float().mean())
         assert abs(share - exact[T]) <= group_tolerance(exact[T], clones // 32, 5.0), (T, share)
 
+
+def test_clone_count_limit_rejected_before_any_work():
+    """n_clones above XS_MAX_CLONES (clone indices would leave int32) is XS_EINVAL from the run
+    and the autotuner, found before any buffer is looked at or any kernel is launched."""
+    import ctypes
+    _torch()
+    inst = planted_instance(16, 1)
+    h = xorsat.Instance(inst.tri, inst.J)
+    lib = xorsat.load()
+    cfg = xorsat.make_config(n_clones=xorsat.XS_MAX_CLONES + xorsat.XS_CLONE_QUANTUM, seed=1,
+                             stop_on_first=False, max_sweeps=1)
+    res = xorsat.RunResult()
+    st = lib.xs_run(h.handle, ctypes.byref(cfg), ctypes.byref(xorsat.RunBuffers()), None,
+                    ctypes.byref(res))
+    assert xorsat.XS_STATUS[st] == "XS_EINVAL"
+    assert b"n_clones" in lib.xs_last_error()
+    tune = xorsat.TuneResult()
+    st = lib.xs_autotune(h.handle, xorsat.XS_MAX_CLONES + xorsat.XS_CLONE_QUANTUM, 1, None,
+                         ctypes.byref(tune))
+    assert xorsat.XS_STATUS[st] == "XS_EINVAL"
+
