@@ -465,3 +465,35 @@ def test_metropolis_end_state_law_of_the_exact_chain(thr0):
         share = float(np.mean(r["first_hit"] == T))
         assert abs(share - exact[T]) <= group_tolerance(exact[T], clones // 32, 5.0), (T, share)
 
+
+
+# ------------------------------------------------------------------ run-level results (TTS, winner)
+
+@pytest.mark.parametrize("first_hit,expect", [
+    # a run's time is its fastest clone (Section "Numerical results"); equal times resolve to
+    # the lowest clone index
+    ([5, 3, 7, 3, 3], (3, 1)),
+    ([9, 9, 9, 9], (9, 0)),
+    ([-1, -1, 4, -1, 4], (4, 2)),
+    # no clone reached a ground state
+    ([-1, -1, -1], (-1, -1)),
+    ([-1], (-1, -1)),
+    # a start configuration that is already a ground state is a hit at sweep 0
+    ([-1, 0, 4, 0], (0, 1)),
+    ([0], (0, 0)),
+    # a resumed run starting at sweep 17: hits only at its first sweep
+    ([-1, 17, -1, 17, 30], (17, 1)),
+    # the last clone alone
+    ([-1] * 1023 + [250], (250, 1023)),
+])
+def test_solve_results_hand_built(first_hit, expect):
+    assert oracle.solve_results(np.array(first_hit, dtype=np.int32)) == expect
+
+
+def test_solve_results_large_sweep_indices():
+    """Sweep indices near the top of the int32 range and a winner far into the array."""
+    fh = np.full(1 << 16, -1, dtype=np.int32)
+    fh[40000] = 2_000_000_000
+    fh[50000] = 1_999_999_999
+    fh[60000] = 1_999_999_999
+    assert oracle.solve_results(fh) == (1_999_999_999, 50000)
