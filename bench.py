@@ -1,14 +1,17 @@
 """Throughput benchmark of the quasi-greedy many-clone dynamics on one MI355X.
 
-Workload (default): 64 planted instances with N = 256 spins (3-regular 3-uniform hypergraph,
-M = N, planted J), 65536 clones each in uint64 words, run together as one batch (one sweep-chunk
-launch over all unfinished instances), each to its first ground state or a per-step sweep
-budget. One step = one full pass of the path over the batch: start configurations drawn on the
-device, sweeps in chunks of 100, stop checks, end-of-run energies, TTS and winner reduction.
+Workload (default, "steady"): 16 planted instances with N = 1024 spins (3-regular 3-uniform
+hypergraph, M = N, planted J), 2^20 clones each in uint64 words, run together as one batch (one
+sweep-chunk launch over all tiles of all instances), 10^4 sweeps per step. One step = one full
+pass of the path over the batch: start configurations drawn on the device, sweeps in chunks of
+100, ground-state capture, stop checks, end-of-run energies, TTS and winner reduction, the
+winner's configuration. `--workload batched` runs the 64 x N = 256 x 65,536-clone batch to its
+first ground state (or a per-step budget) instead.
 
-Prints one JSON line: clone-spin updates per ns for the whole job, the sweep kernel's
-roofline record (ALU bound, from HIP-event timing of every sweep-chunk launch) and the CPU
-oracle timed on a bounded sample of the same workload.
+Prints one JSON line: clone-spin updates per ns for the whole job, the sweep kernel's roofline
+record (LDS bound: 1 byte of LDS traffic per update, from HIP-event timing of every sweep-chunk
+launch on the stream it runs on), TTS p50/p99 of the small single-instance workload run one at a
+time, batched and served, and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -25,18 +28,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peak of the bound resource: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s of
-# full-rate 32-bit VALU work.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic VALU work per clone-spin update, in full-rate lane operations (gfx950 issues
-# v_bitop3_b32 and the 32x32->64 v_mad_u64_u32 at full rate): the rule and the ground-state
-# test take 9 three-input operations per 32-clone word; one Philox4x32-10 call (10 rounds of
-# 2 wide products and 2 three-input XORs) plus 8 threshold compares serve 8 groups = 256
-# clones. 9/32 + 48/256 = 0.469 lane-ops per update.
-ALGO_OPS_PER_UPDATE = 9 / 32 + (10 * (2 + 2) + 8) / 256
-# With w0 > 0 the rule also takes 9 operations per word (no ground-state test, one more
-# select) and every draw is compared with both thresholds.
-ALGO_OPS_PER_UPDATE_W0 = 9 / 32 + (10 * (2 + 2) + 16) / 256
 # Algorithmic LDS traffic per update: the 7 state bits an update reads (own spin and the two
 # partners in each of its three triplets) and the 1 bit it writes = 1 byte.
 ALGO_LDS_BYTES_PER_UPDATE = 1.0
@@ -44,6 +35,28 @@ ALGO_LDS_BYTES_PER_UPDATE = 1.0
 # (1 KB), so 256 CUs x 256 B/clk x 2.4 GHz = 157.3 TB/s (a streaming microbenchmark with 16
 # waves per CU reached 136 TB/s at 94 % LDS busy).
 LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
+# Secondary figure: VALU issue. 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s of
+# full-rate 32-bit VALU work. Algorithmic VALU instructions per clone-spin update: the rule and
+# the ground-state test take 9 three-input operations per 32-clone word; one Philox4x32-10 call
+# (10 rounds of 2 wide products and 2 three-input XORs) plus 8 threshold compares serve 8
+# groups = 256 clones: 9/32 + 48/256 = 0.469. The fraction below counts every one of them as a
+# full-rate operation (the rate of the 32x32->64 product is not measured here), so it is an
+# upper bound on VALU use.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+ALGO_OPS_PER_UPDATE = 9 / 32 + (10 * (2 + 2) + 8) / 256
+# With w0 > 0 the rule also takes 9 operations per word (no ground-state test, one more
+# select) and every draw is compared with both thresholds.
+ALGO_OPS_PER_UPDATE_W0 = 9 / 32 + (10 * (2 + 2) + 16) / 256
+
+# Headline workloads: (instances, N, clones, default sweeps per step, stop at first ground
+# state, instance-seed config number).
+HEADLINES = {
+    "steady": dict(count=16, n=1024, clones=1 << 20, budget=10000, stop=False, config=3),
+    "batched": dict(count=64, n=256, clones=65536, budget=50000, stop=True, config=2),
+}
+# HBM counter records per headline workload (FETCH_SIZE / WRITE_SIZE of the sweep kernel).
+TRAFFIC_RECORDS = {"steady": "qg_chunk_n1024x16_hbm_counters.json",
+                   "batched": "qg_chunk_n256x64_hbm_counters.json"}
 
 
 def parse():
@@ -51,25 +64,31 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=64)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--clones", type=int, default=65536)
+    ap.add_argument("--instances", type=int, default=None,
+                    help="headline workloads: instances (default: the workload's)")
+    ap.add_argument("--n", type=int, default=None, help="headline workloads: spins")
+    ap.add_argument("--clones", type=int, default=None, help="headline workloads: clones")
     ap.add_argument("--place-rows", action="store_true",
                     help="batched: build the LDS row placement whatever the run length "
                          "(tiles under eight blocks, large N; speed only)")
-    ap.add_argument("--budget", type=int, default=50000,
-                    help="sweep budget per instance and step (first ground states at N=256 "
-                         "take far longer, so most instances end at the budget)")
+    ap.add_argument("--budget", type=int, default=None,
+                    help="sweep budget per instance and step (default: 10^4 for steady, uneven "
+                         "and serve; 5*10^4 for batched, whose first ground states at N=256 take "
+                         "far longer, so most instances end at the budget)")
     ap.add_argument("--chunk", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM counters)")
-    ap.add_argument("--workload", default="batched",
-                    choices=["batched", "steady", "uneven", "serve", "tts", "w1scan", "paper",
+    ap.add_argument("--tts-runs", type=int, default=200,
+                    help="headline: runs of the small single-instance workload for the TTS "
+                         "block (0 = skip)")
+    ap.add_argument("--workload", default="steady",
+                    choices=["steady", "batched", "uneven", "serve", "tts", "w1scan", "paper",
                              "paper256", "single"],
-                    help="batched: the default line; steady: 16 x N=1024 x 2^20 clones, fixed "
-                         "sweeps; uneven: 512 instances of uneven N and clone count, batched vs "
+                    help="steady: the default line, 16 x N=1024 x 2^20 clones, 10^4 sweeps; "
+                         "batched: 64 x N=256 x 65536 clones to the first ground state or a "
+                         "budget; uneven: 512 instances of uneven N and clone count, batched vs "
                          "served vs one at a time; serve: Poisson stream through the server vs "
                          "one run at a time; tts: the exponential TTS law on many runs of one "
                          "small instance, tau x N_cl scaling and the short-timeout estimate; "
@@ -109,21 +128,28 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(args):
-    """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE record, if it was
-    taken on the current kernel source and the default workload; otherwise None."""
+def kernel_source_sha256():
+    """Hash of the kernel sources: counter records name the source they were taken on."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "qg_chunk_n256x64_hbm_counters.json")
-    if not os.path.exists(path) or (args.instances, args.n, args.clones, args.chunk,
-                                    args.accept_thr0) != (64, 256, 65536, 100, 0):
-        return None
-    rec = json.load(open(path))
     h = hashlib.sha256()
     for f in ("kernels.hip", "xs_internal.h"):
         with open(os.path.join(ROOT, "paper_2102_09510_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != rec.get("kernel_source_sha256"):
+    return h.hexdigest()
+
+
+def measured_traffic(args, wl, dims):
+    """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE record of the
+    headline workload, if it was taken on the current kernel source and this workload's default
+    configuration; otherwise None."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_RECORDS[wl])
+    H = HEADLINES[wl]
+    if (not os.path.exists(path) or dims != (H["count"], H["n"], H["clones"]) or
+            args.chunk != 100 or args.accept_thr0 or args.cap != 32):
+        return None
+    rec = json.load(open(path))
+    if kernel_source_sha256() != rec.get("kernel_source_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -156,62 +182,14 @@ def cpu_baseline(insts, args, target_s):
     return {"value": updates / dt / 1e9, "unit": "clone-spin updates/ns", "cores": threads,
             "kind": "oracle",
             "sample": f"{len(insts)} instances x 256 clones x {sweeps} sweeps (N={insts[0].n}), "
-                      f"{updates:.3e} updates in {dt:.1f} s",
+                      f"{updates:.3e} updates in {dt:.1f} s; the rate on this sample is taken "
+                      f"as the whole workload's (extrapolated)",
             "single_core_value": one,
             "single_core_sample": f"1 instance x 256 clones x {s1} sweeps, 1 thread"}
 
 
 def pct(v, q):
     return float(np.percentile(v, q)) if len(v) else None
-
-
-def workload_steady(args, xorsat, torch):
-    """16 instances, N = 1024, 2^20 clones each, a fixed sweep budget (default 10^4). The LDS
-    rows are placed whatever the budget (a run of 10^4 sweeps would place them by itself), so
-    that short profiling runs of this workload time the same kernel. A one-chunk run first, timed
-    apart, builds the schedules and placements, so the timed run is the steady state."""
-    from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance, run_seed
-
-    count, n, clones = 16, 1024, 1 << 20
-    sweeps = args.budget if args.budget != 50000 else 10000
-    insts = [planted_instance(n, gen_seed(3, k)) for k in range(count)]
-    hs = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
-    cfgs = [xorsat.make_config(n_clones=clones, seed=run_seed(3, k), instance_id=k,
-                               accept_thr=THR_PAPER, max_sweeps=sweeps, stop_on_first=False,
-                               chunk_sweeps=args.chunk, place_rows=True) for k in range(count)]
-    print(f"# steady: {count} x N={n} x {clones} clones, {sweeps} sweeps", file=sys.stderr, flush=True)
-    # One-time set-up outside the timed run: a one-chunk run of the same configurations builds
-    # and uploads every instance's step schedule and LDS row placement.
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    warm = [xorsat.make_config(n_clones=clones, seed=run_seed(3, k), instance_id=k,
-                               accept_thr=THR_PAPER, max_sweeps=max(args.chunk, 1),
-                               stop_on_first=False, chunk_sweeps=args.chunk, place_rows=True)
-            for k in range(count)]
-    xorsat.run_batch(hs, warm, want_energy=False)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    print(f"# steady: set-up run done in {t_setup:.2f} s", file=sys.stderr, flush=True)
-    xorsat.profile_read(reset=True)
-    xorsat.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = xorsat.run_batch(hs, cfgs, want_energy=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    xorsat.profile_enable(False)
-    prof = xorsat.profile_read(reset=True)
-    upd = sum(o.clone_spin_updates for o in outs)
-    tts = [o.tts_sweeps for o in outs if o.tts_sweeps >= 0]
-    return {"metric": "clone-spin updates/ns on 1 MI355X (steady state)",
-            "value": round(upd / dt / 1e9, 3), "unit": "clone-spin updates/ns",
-            "kernel_updates_per_ns": round(prof["clone_spin_updates"] / prof["total_ms"] / 1e6, 3),
-            "seconds": round(dt, 3), "setup_run_s": round(t_setup, 3),
-            "config": {"workload": f"{count} planted instances, N={n}, "
-                                                            f"{clones} clones each, {sweeps} sweeps",
-                                                "tile_blocks": outs[0].tile_blocks,
-                                                "wg_threads": outs[0].wg_threads},
-            "tts_sweeps": {"solved": len(tts), "censored": count - len(tts)}}
 
 
 def workload_uneven(args, xorsat, torch):
@@ -224,7 +202,7 @@ def workload_uneven(args, xorsat, torch):
     sizes = uneven_sizes(512)
     insts = [planted_instance(n, gen_seed(4, k)) for k, (n, _) in enumerate(sizes)]
     hs = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
-    budget = args.budget if args.budget != 50000 else 10000
+    budget = args.budget if args.budget is not None else 10000
 
     def cfg(k):
         return xorsat.make_config(n_clones=sizes[k][1], seed=run_seed(4, k), instance_id=k,
@@ -303,7 +281,7 @@ def workload_serve(args, xorsat, torch):
                                                 poisson_stream, run_seed)
 
     arrivals = poisson_stream(args.rate, args.duration)
-    budget = args.budget if args.budget != 50000 else 10000
+    budget = args.budget if args.budget is not None else 10000
     print(f"# serve: {len(arrivals)} requests over {args.duration} s, preparing instances",
           file=sys.stderr, flush=True)
     hs = []
@@ -691,53 +669,110 @@ def cpu_baseline_single(inst, cap, cfgs, sweeps, tts):
             "kind": "oracle", "sample": f"{len(cfgs)} runs in full, TTS equal to the GPU's"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this solver runs on one GPU; several GPUs would each take "
-                                   "a share of the 32-clone groups and combine first hits with "
-                                   "one min-reduction, which is not implemented here",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    import torch
-
-    from paper_2102_09510_amd import xorsat
+def tts_block(args, xorsat, torch):
+    """TTS of the small single-instance workload (one planted N = 64 instance, 1,024 clones, to
+    the first ground state or 10^5 sweeps) over many seeds, three ways on the same GPU: one run
+    at a time, all runs in one batched call, and all runs submitted at once to the server. TTS
+    in sweeps is identical by construction (checked); the wall-clock times differ. All runs
+    arrive together, so a run's completion time is its place in the one-at-a-time sequence,
+    the batched call's end, or its own completion in the server."""
     from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance, run_seed
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    torch.cuda.set_device(0)
-    if args.copy_calibrate:
-        src = torch.ones(args.copy_calibrate << 18, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+    runs, n, ncl = args.tts_runs, 64, 1024
+    inst = planted_instance(n, gen_seed(1, 0))
+    h = xorsat.Instance(inst.tri, inst.J, colour_cap=args.cap)
+
+    def cfg(r):
+        return xorsat.make_config(n_clones=ncl, seed=run_seed(1, 0) + r, instance_id=0,
+                                  accept_thr=THR_PAPER, max_sweeps=100000, stop_on_first=True,
+                                  chunk_sweeps=args.chunk)
+
+    xorsat.run(h, cfg(0))  # warm
+    torch.cuda.synchronize()
+    one, service = [], []
+    for r in range(runs):
+        t1 = time.perf_counter()
+        o = xorsat.run(h, cfg(r), want_energy=False)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
-        return
-    if args.workload != "batched":
-        fn = {"steady": workload_steady, "uneven": workload_uneven,
-              "serve": workload_serve, "tts": workload_tts,
-              "w1scan": workload_w1scan, "paper": workload_paper,
-              "paper256": workload_paper256, "single": workload_single}[args.workload]
-        out = fn(args, xorsat, torch)
-        out.setdefault("config", {})["colour_cap"] = args.cap
-        print(json.dumps(out), flush=True)
-        return
-    insts = [planted_instance(args.n, gen_seed(2, k)) for k in range(args.instances)]
+        service.append(time.perf_counter() - t1)
+        one.append(o.tts_sweeps)
+    completion = np.cumsum(service)
+    batch_s = []
+    for _ in range(2):  # the first call also pays one-time costs (graph instantiation)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch = xorsat.run_batch([h] * runs, [cfg(r) for r in range(runs)], want_energy=False)
+        torch.cuda.synchronize()
+        batch_s.append(time.perf_counter() - t0)
+        assert [o.tts_sweeps for o in batch] == one
+    srv = xorsat.Server(hbm_budget_bytes=1 << 30)
+    t0 = time.perf_counter()
+    tickets = {srv.submit(h, cfg(r), want_first_hit=False, want_energy=False): r
+               for r in range(runs)}
+    served = {}
+    while True:
+        active = srv.step()
+        for c in srv.poll():
+            served[tickets[c.ticket]] = c
+        if active == 0:
+            break
+    for c in srv.poll():
+        served[tickets[c.ticket]] = c
+    served_s = time.perf_counter() - t0
+    srv.close()
+    assert [served[r].tts_sweeps for r in range(runs)] == one
+    lat = [served[r].latency_s for r in range(runs)]
+    tts = np.array(one)
+    ok = tts[tts >= 0]
+
+    def ms(v):
+        return None if v is None else round(1e3 * v, 3)
+
+    return {"workload": f"1 planted instance, N={n}, {ncl} clones, {runs} seeds, first ground "
+                        "state or 1e5 sweeps, all runs arriving together",
+            "solved": int(ok.size), "censored": int(runs - ok.size),
+            "tts_sweeps_p50": pct(ok, 50), "tts_sweeps_p99": pct(ok, 99),
+            "one_at_a_time": {"service_ms_p50": ms(pct(service, 50)),
+                              "service_ms_p99": ms(pct(service, 99)),
+                              "completion_ms_p50": ms(pct(completion, 50)),
+                              "completion_ms_p99": ms(pct(completion, 99)),
+                              "total_ms": ms(completion[-1])},
+            "batched": {"completion_ms": ms(batch_s[1]), "total_ms": ms(batch_s[1]),
+                        "first_call_ms": ms(batch_s[0])},
+            "served": {"completion_ms_p50": ms(pct(lat, 50)),
+                       "completion_ms_p99": ms(pct(lat, 99)), "total_ms": ms(served_s)},
+            "identical_tts": True}
+
+
+def headline(args, xorsat, torch):
+    """The JSON line of a headline workload: W untimed steps, then K timed steps bracketed by
+    device synchronisations; every sweep-chunk launch timed with HIP events on the stream it is
+    launched on."""
+    from paper_2102_09510_amd.instances import THR_PAPER, gen_seed, planted_instance, run_seed
+
+    wl = args.workload
+    H = HEADLINES[wl]
+    count = args.instances or H["count"]
+    n = args.n or H["n"]
+    clones = args.clones or H["clones"]
+    budget = args.budget if args.budget is not None else H["budget"]
+    stop = H["stop"] and args.accept_thr0 == 0
+    place = args.place_rows or wl == "steady"
+    chunk = args.chunk or 100
+    insts = [planted_instance(n, gen_seed(H["config"], k)) for k in range(count)]
     handles = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
 
     def step(s):
-        cfgs = [xorsat.make_config(n_clones=args.clones, seed=run_seed(2, k) + s,
+        cfgs = [xorsat.make_config(n_clones=clones, seed=run_seed(H["config"], k) + s,
                                    instance_id=k, accept_thr=THR_PAPER,
-                                   accept_thr0=args.accept_thr0, max_sweeps=args.budget,
-                                   stop_on_first=args.accept_thr0 == 0,
-                                   chunk_sweeps=args.chunk, place_rows=args.place_rows)
-                for k in range(args.instances)]
+                                   accept_thr0=args.accept_thr0, max_sweeps=budget,
+                                   stop_on_first=stop, chunk_sweeps=chunk, place_rows=place)
+                for k in range(count)]
         return xorsat.run_batch(handles, cfgs, want_energy=True)
 
-    print(f"# bench: {args.instances} x N={args.n} x {args.clones} clones, budget "
-          f"{args.budget} sweeps/step, warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
+    print(f"# bench {wl}: {count} x N={n} x {clones} clones, {budget} sweeps/step"
+          f"{' or first ground state' if stop else ''}, warmup {args.warmup}, "
+          f"steps {args.steps}", file=sys.stderr, flush=True)
     for s in range(args.warmup):
         step(1000 + s)
         torch.cuda.synchronize()
@@ -749,14 +784,16 @@ def main():
     updates = 0
     tts = []
     censored = 0
+    shape = None
     for s in range(args.steps):
         outs = step(s)
         for o in outs:
             updates += o.clone_spin_updates
             if o.tts_sweeps >= 0:
-                tts.append(o.tts_sweeps)
+                tts.append(o.tts_sweeps)  # runs start at sweep 0
             else:
                 censored += 1
+        shape = (outs[0].tile_blocks, outs[0].wg_threads, outs[0].col_bytes, outs[0].rec_global)
         print(f"# step {s} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -764,14 +801,18 @@ def main():
     prof = xorsat.profile_read(reset=True)
     value = updates / dt / 1e9
     kern_rate = prof["clone_spin_updates"] / (prof["total_ms"] * 1e6) if prof["total_ms"] else 0
-    # A launch covers 100 sweeps of every instance; the few launched after the budget ran out
-    # (every tile exits at once, about 4 us each) are counted apart, their time stays in.
-    per_launch_updates = args.instances * args.clones * args.n * (args.chunk or 100)
+    # A launch covers `chunk` sweeps of every instance; launches after the budget ran out (every
+    # tile exits at once, a few us each) are counted apart, their time stays in.
+    per_launch_updates = count * clones * n * chunk
     full_launches = prof["clone_spin_updates"] / per_launch_updates
     avg_ms = prof["total_ms"] / max(full_launches, 1e-9)
-    ops = ALGO_OPS_PER_UPDATE_W0 if args.accept_thr0 else ALGO_OPS_PER_UPDATE
-    achieved = ops * per_launch_updates / (avg_ms * 1e-3) / 1e12
     lds_tbs = ALGO_LDS_BYTES_PER_UPDATE * per_launch_updates / (avg_ms * 1e-3) / 1e12
+    ops = ALGO_OPS_PER_UPDATE_W0 if args.accept_thr0 else ALGO_OPS_PER_UPDATE
+    valu = ops * per_launch_updates / (avg_ms * 1e-3) / 1e12
+    desc = (f"{count} planted instances, N={n}, {clones} clones each, batched, " +
+            (f"{budget} sweeps per step with w0 = {args.accept_thr0}/65536" if args.accept_thr0
+             else f"to first ground state or {budget} sweeps per step" if stop
+             else f"{budget} sweeps per step (steady state)"))
     line = {
         "metric": "clone-spin updates/ns on 1 MI355X",
         "value": round(value, 3),
@@ -785,32 +826,68 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic planted instances (seeded configuration model)",
-        "config": {"workload": f"{args.instances} planted instances, N={args.n}, "
-                               f"{args.clones} clones each, batched, " +
-                               (f"{args.budget} sweeps per step with w0 = "
-                                f"{args.accept_thr0}/65536" if args.accept_thr0 else
-                                f"to first ground state or {args.budget} sweeps per step"),
-                   "chunk_sweeps": args.chunk, "accept_thr": THR_PAPER, "colour_cap": args.cap,
+        "config": {"workload": desc, "chunk_sweeps": chunk, "accept_thr": THR_PAPER,
+                   "colour_cap": args.cap, "launch_shape": dict(zip(
+                       ("tile_blocks", "wg_threads", "col_bytes", "rec_global"), shape)),
                    **({"accept_thr0": args.accept_thr0} if args.accept_thr0 else {}),
-                   **({"place_rows": True} if args.place_rows else {})},
+                   **({"place_rows": True} if place else {})},
         "tts_sweeps": {"solved": len(tts), "censored": censored,
-                       "p50": float(np.percentile(tts, 50)) if tts else None,
-                       "p99": float(np.percentile(tts, 99)) if tts else None},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": measured_traffic(args),
+                       "p50": pct(tts, 50), "p99": pct(tts, 99)},
+        "roofline": {"bound": "lds", "achieved": round(lds_tbs, 3),
+                     "peak": round(LDS_PEAK_TBS, 2), "unit": "TB/s",
+                     "frac": round(lds_tbs / LDS_PEAK_TBS, 4),
+                     "traffic": measured_traffic(args, wl, (count, n, clones)),
+                     "bytes_per_update": ALGO_LDS_BYTES_PER_UPDATE,
                      "kernel": "qg_chunk", "launches": round(full_launches, 2),
                      "launches_past_budget": prof["launches"] - round(full_launches),
+                     "updates_per_launch": per_launch_updates,
                      "avg_launch_ms": round(avg_ms, 3),
                      "kernel_updates_per_ns": round(kern_rate, 3),
-                     "lds": {"achieved_TBs": round(lds_tbs, 3), "peak_TBs": round(LDS_PEAK_TBS, 2),
-                             "frac": round(lds_tbs / LDS_PEAK_TBS, 4),
-                             "bytes_per_update": ALGO_LDS_BYTES_PER_UPDATE}},
+                     "valu": {"algorithmic_ops_per_update": round(ops, 4),
+                              "achieved_T_ops": round(valu, 3),
+                              "peak_T_ops": round(VALU_PEAK_TOPS, 2),
+                              "frac_if_full_rate": round(valu / VALU_PEAK_TOPS, 4)}},
     }
+    if args.tts_runs > 0:
+        print("# TTS block: one at a time, batched, served", file=sys.stderr, flush=True)
+        line["tts_batched_vs_single"] = tts_block(args, xorsat, torch)
     if args.cpu_seconds > 0:
+        print("# CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(insts, args, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; several GPUs would each take "
+                                   "a share of the 32-clone groups and combine first hits with "
+                                   "one min-reduction, which is not implemented here",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2102_09510_amd import xorsat
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_calibrate:
+        src = torch.ones(args.copy_calibrate << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return
+    if args.workload not in HEADLINES:
+        fn = {"uneven": workload_uneven, "serve": workload_serve, "tts": workload_tts,
+              "w1scan": workload_w1scan, "paper": workload_paper,
+              "paper256": workload_paper256, "single": workload_single}[args.workload]
+        out = fn(args, xorsat, torch)
+        out.setdefault("config", {})["colour_cap"] = args.cap
+        print(json.dumps(out), flush=True)
+        return
+    print(json.dumps(headline(args, xorsat, torch)), flush=True)
 
 
 if __name__ == "__main__":

@@ -9,6 +9,7 @@ import pytest
 import oracle
 from paper_2102_09510_amd import xorsat
 from paper_2102_09510_amd.instances import THR_PAPER, planted_instance
+from tests.parity import check_clones
 from tests.pins import ground_law, group_tolerance
 
 pytestmark = pytest.mark.gpu
@@ -21,49 +22,17 @@ def _torch():
     return torch
 
 
-def spins_of_clones(state, clones) -> np.ndarray:
-    """[len(clones)][n] spins (+1/-1) from the device state (bit c & 63 of word c >> 6)."""
-    st = state.cpu().numpy().view(np.uint64)
-    clones = np.asarray(clones, dtype=np.int64)
-    bits = (st[:, clones >> 6] >> (clones & 63).astype(np.uint64)) & np.uint64(1)
-    return (1 - 2 * bits.T.astype(np.int16)).astype(np.int8)
-
-
-def oracle_replay(inst, h, cfg, out, clones, init_spins=None):
-    """The oracle run of the given clones from the same start to the GPU's end sweep."""
+def assert_parity(inst, h, cfg, out, clones=None, init_spins=None):
+    """Every given clone (default: all) against the oracle from the same start to the GPU's end
+    sweep, after checking that the library's partition is the oracle's."""
     perm, _ = h.partition()
     operm, _ = oracle.colour(inst.tri, h.colour_cap)
     assert np.array_equal(perm, operm)
-    res = {"first_hit": [], "energy": [], "final_spins": []}
-    clones = np.asarray(clones)
-    # contiguous runs of clones keep the oracle call count small
-    starts = np.flatnonzero(np.diff(np.r_[-2, clones]) != 1)
-    ends = np.r_[starts[1:], clones.size]
-    for a, b in zip(starts, ends):
-        init = None if init_spins is None else init_spins[a:b]
-        r = oracle.run(inst.tri, inst.J, operm, seed=cfg.seed, instance_id=cfg.instance_id,
-                       thr=cfg.accept_thr, thr0=cfg.accept_thr0, n_sweeps=out.sweeps_done,
-                       start_sweep=cfg.start_sweep, clone_begin=int(clones[a]),
-                       clone_count=int(b - a), init_spins=init, want_final=True)
-        for k in res:
-            res[k].append(r[k])
-    return {k: np.concatenate(v) for k, v in res.items()}
-
-
-def assert_parity(inst, h, cfg, out, clones=None, init_spins=None):
-    n_clones = cfg.n_clones
     if clones is None:
-        clones = np.arange(n_clones)
-    clones = np.asarray(clones)
-    ref = oracle_replay(inst, h, cfg, out, clones, init_spins)
-    fh = out.first_hit.cpu().numpy()[clones]
-    en = out.energy.cpu().numpy()[clones]
-    sp = spins_of_clones(out.state, clones)
-    bad = np.flatnonzero(fh != ref["first_hit"])
-    assert bad.size == 0, f"first_hit differs at clones {clones[bad[:8]]}"
-    assert np.array_equal(en, ref["energy"])
-    assert np.array_equal(sp, ref["final_spins"])
-    return ref
+        clones = np.arange(cfg.n_clones)
+    return check_clones(inst.tri, inst.J, operm, cfg, out.sweeps_done, clones,
+                        out.first_hit.cpu().numpy(), out.energy.cpu().numpy(), out.state,
+                        init_spins)
 
 
 def run_and_check_full(n, seed, n_clones, *, max_sweeps, stop=True, chunk=0, tile_blocks=0,
@@ -309,10 +278,11 @@ def test_zero_budget_and_ground_state_start():
                                                    (1024, 1 << 20, 12, True),
                                                    (2048, 16384, 20, True)])
 def test_full_size_sampled_clones(n, clones, sweeps, place):
-    """Full-size shapes in the launch configuration the benchmarks time (the batched N = 256
-    workload, the N = 1024 steady-state workload with its LDS rows placed, and the largest N):
-    every clone's energy must be a valid E = 2U - N; sampled clones from different tiles match
-    the oracle bit for bit."""
+    """Full-size lone instances (N = 256 with 65,536 clones, N = 1024 with 2^20 clones and its
+    LDS rows placed, the largest N) in the library's default shape for a lone instance: every
+    clone's energy must be a valid E = 2U - N; sampled clones from different tiles match the
+    oracle bit for bit. The batched and steady-state workloads' own launch shapes are checked
+    over several chunks in test_gpu_shapes.py."""
     _torch()
     inst = planted_instance(n, 9000 + n)
     h = xorsat.Instance(inst.tri, inst.J)

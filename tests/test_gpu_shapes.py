@@ -1,0 +1,203 @@
+"""GPU <-> oracle parity at the launch shapes the throughput numbers come from.
+
+* The batched N = 256 workload's kernel (tiles of eight 256-clone blocks, 512 threads, 16-byte
+  columns, records in LDS) inside a batch, over several chunks.
+* The steady-state N = 1024 workload's kernel (the library's default shape for 2^20 clones, rows
+  placed), over several chunks.
+* An uneven batch of many instances (N from 32 to 1024, mixed clone counts, mixed stop rules),
+  each instance against the oracle and against its run alone.
+
+Starts are given (XS_RESUME): most groups random, some a few spin flips away from the planted
+solution, so that clones reach a ground state at the start, inside the first chunk (the
+end-of-chunk test and its replay) and in later chunks (per-sweep tracking). Sampled 32-clone
+groups from different tiles are compared with the oracle clone by clone (first hit, energy at
+the end sweep, end spins); the run's TTS and winner with the oracle's reduction of the GPU's
+first hits, with the winner's group among the sampled ones."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_09510_amd import xorsat
+from paper_2102_09510_amd.instances import THR_PAPER, planted_instance, uneven_sizes
+from tests.parity import check_clones, check_run_reduction, group_sample, pack_spins, \
+    spins_of_clones
+
+pytestmark = pytest.mark.gpu
+
+# The library's default launch shape of the steady-state workload (16 x N = 1024 x 2^20 clones,
+# rows placed), which bench.py times: (tile_blocks, wg_threads, col_bytes, rec_global).
+STEADY_SHAPE = (1, 256, 8, 1)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def near_solution_state(inst, n_clones, rng, groups_flips):
+    """A start state: random words, except the given groups, whose clones start from the planted
+    solution tau with `flips` distinct spins flipped (each clone its own). Returns (state as
+    int64 [n][W] numpy, {group: spins [32][n]})."""
+    n = inst.n
+    W = n_clones // 64
+    state = np.frombuffer(rng.bytes(8 * n * W), dtype=np.uint64).reshape(n, W).copy()
+    starts = {}
+    for g, flips in groups_flips.items():
+        sp = np.tile(inst.tau, (32, 1)).astype(np.int8)
+        for c in range(32):
+            sp[c, rng.choice(n, flips, replace=False)] *= -1
+        starts[g] = sp
+        # write the group's 32 bits (half a word) into the state
+        bits = pack_spins(np.concatenate([sp, sp]))[:, 0]  # 64 clones -> one word; keep 32 bits
+        w, half = divmod(g, 2)
+        lo = np.uint64(0xFFFFFFFF)
+        mask = lo << np.uint64(32 * half)
+        state[:, w] = (state[:, w] & ~mask) | ((bits & lo) << np.uint64(32 * half))
+    return state.view(np.int64), starts
+
+
+def sample_init(state_i64, clones):
+    """Start spins of the given clones, read from the start state."""
+    return spins_of_clones(state_i64, clones)
+
+
+def check_instance(inst, h, cfg, out, start_state, groups, what):
+    """Oracle parity of the sampled groups (plus the winner's group) from the given start."""
+    perm, _ = h.partition()
+    operm, _ = oracle.colour(inst.tri, h.colour_cap)
+    assert np.array_equal(perm, operm), what
+    fh = out.first_hit.cpu().numpy()
+    check_run_reduction(fh, out.tts_sweeps, out.winner_clone)
+    groups = list(groups)
+    if out.winner_clone >= 0:
+        groups.append(out.winner_clone // 32)
+    clones = group_sample(cfg.n_clones, groups)
+    clones = np.unique(np.r_[clones, cfg.n_clones - 1])
+    init = sample_init(start_state, clones)
+    ref = check_clones(inst.tri, inst.J, operm, cfg, out.sweeps_done, clones, fh,
+                       out.energy.cpu().numpy(), out.state, init_spins=init, what=what)
+    if out.winner_clone >= 0:
+        k = int(np.flatnonzero(clones == out.winner_clone)[0])
+        assert np.array_equal(out.solved, ref["final_spins"][k]), what
+        assert oracle.energy(inst.tri, inst.J, out.solved) == -inst.n, what
+    return ref
+
+
+def test_batched_n256_timed_shape_resumed_near_solution():
+    """The batched N = 256 workload's kernel: three instances of 65,536 clones in one batch with
+    tile_blocks = 8, wg_threads = 512, col_bytes = 16, records in LDS; 200 sweeps in chunks of 50
+    from sweep 1000 (budget runs) and a stop-on-first run that ends after its first chunk."""
+    torch = _torch()
+    n, nc = 256, 65536  # tiles of 2,048 clones: 64 groups per tile, 32 tiles per instance
+    rng = np.random.default_rng(256)
+    insts, hs, cfgs, starts, picks = [], [], [], [], []
+    for k in range(3):
+        inst = planted_instance(n, 2_000_000 + k)
+        insts.append(inst)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        # near-solution groups: one per flip level, each in its own tile (tiles 3, 7, ..., 27)
+        levels = {0: 0, 1: 1, 4: 4, 16: 16, 32: 32, 40: 32, 48: 48}
+        gf = {}
+        for t, (lvl, flips) in enumerate(levels.items()):
+            gf[64 * (3 + 4 * t) + 5 * t + 1] = flips
+        # the zero-flip group only in the third instance, so the others' TTS comes from a
+        # descent inside the first chunk rather than from the start check
+        if k != 2:
+            gf = {g: f for g, f in gf.items() if f > 0}
+        st, sp = near_solution_state(inst, nc, rng, gf)
+        starts.append(st)
+        picks.append(sorted(gf)[:5] + [64 * 1 + 9, 64 * 30 + 63])  # + two random groups
+        cfgs.append(xorsat.make_config(
+            n_clones=nc, seed=0xC2 + k, instance_id=k, accept_thr=THR_PAPER, max_sweeps=200,
+            start_sweep=1000, resume=True, stop_on_first=(k == 1), chunk_sweeps=50,
+            tile_blocks=8, wg_threads=512, col_bytes=16, rec_global=2))
+    outs = xorsat.run_batch(hs, cfgs, states=[torch.from_numpy(s.copy()).cuda() for s in starts])
+    for k, out in enumerate(outs):
+        assert (out.tile_blocks, out.wg_threads, out.col_bytes, out.rec_global) == (8, 512, 16, 0)
+        if k == 1:
+            assert out.end_sweep == 1050 and out.tts_sweeps < 1050
+        else:
+            assert out.end_sweep == 1200
+        fh = out.first_hit.cpu().numpy()
+        # hits at the start (instance 2), inside the first chunk and in later chunks
+        assert ((fh > 1000) & (fh < 1050)).any()
+        if k != 1:
+            assert (fh >= 1050).any(), "no hit after the first chunk: tracking not exercised"
+        if k == 2:
+            assert (fh == 1000).any()
+        check_instance(insts[k], hs[k], cfgs[k], out, starts[k], picks[k], f"instance {k}")
+
+
+def test_steady_n1024_shape_over_chunks():
+    """The steady-state workload's kernel at its real size: two instances of N = 1024 with 2^20
+    clones in one batch, the library's default shape with the LDS rows placed, 30 sweeps in
+    chunks of 10 from given starts."""
+    torch = _torch()
+    n, nc = 1024, 1 << 20
+    rng = np.random.default_rng(1024)
+    insts, hs, cfgs, starts, picks = [], [], [], [], []
+    for k in range(2):
+        inst = planted_instance(n, 3_000_000 + k)
+        insts.append(inst)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        flips = (4, 32, 64, 96, 96, 128)
+        gf = {8 * (100 + 611 * t) + t: f for t, f in enumerate(flips)}  # one tile each
+        st, _ = near_solution_state(inst, nc, rng, gf)
+        starts.append(st)
+        picks.append(sorted(gf) + [8 * 7 + 3, 8 * 4000 + 5])
+        cfgs.append(xorsat.make_config(
+            n_clones=nc, seed=0xC3 + k, instance_id=k, accept_thr=THR_PAPER, max_sweeps=30,
+            resume=True, stop_on_first=False, chunk_sweeps=10, place_rows=True))
+    outs = xorsat.run_batch(hs, cfgs, states=[torch.from_numpy(s).cuda() for s in starts])
+    for k, out in enumerate(outs):
+        assert (out.tile_blocks, out.wg_threads, out.col_bytes, out.rec_global) == STEADY_SHAPE
+        assert out.end_sweep == 30
+        fh = out.first_hit.cpu().numpy()
+        assert (fh[fh >= 0] < 10).any() and (fh >= 10).any()
+        en = out.energy.cpu().numpy()
+        assert en.min() >= -n and en.max() <= n and np.all((en + n) % 2 == 0)
+        check_instance(insts[k], hs[k], cfgs[k], out, starts[k], picks[k], f"instance {k}")
+
+
+def test_uneven_batch_against_oracle_and_alone():
+    """Twenty instances of the uneven workload's family (N uniform on {32, ..., 1024}, clones
+    from 4,096 to 65,536), half run to the first ground state and half to a budget, in one
+    batch: each instance equals its run alone bit for bit, and sampled groups of each equal the
+    oracle."""
+    torch = _torch()
+    sizes = uneven_sizes(20, seed=4_000_777)
+    assert len({n for n, _ in sizes}) >= 10 and len({c for _, c in sizes}) >= 3
+    insts, hs, cfgs = [], [], []
+    for k, (n, nc) in enumerate(sizes):
+        inst = planted_instance(n, 4_000_000 + k)
+        insts.append(inst)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        cfgs.append(xorsat.make_config(n_clones=nc, seed=0xC4 + k, instance_id=k,
+                                       accept_thr=THR_PAPER, max_sweeps=300,
+                                       stop_on_first=(k % 2 == 0), chunk_sweeps=50))
+    batch = xorsat.run_batch(hs, cfgs)
+    rng = np.random.default_rng(4)
+    for k, (inst, h, cfg, out) in enumerate(zip(insts, hs, cfgs, batch)):
+        alone = xorsat.run(h, cfg)
+        assert torch.equal(out.state, alone.state), k
+        assert torch.equal(out.first_hit, alone.first_hit), k
+        assert torch.equal(out.energy, alone.energy), k
+        assert (out.tts_sweeps, out.winner_clone, out.end_sweep) == \
+            (alone.tts_sweeps, alone.winner_clone, alone.end_sweep), k
+        groups = rng.choice(cfg.n_clones // 32, size=2, replace=False)
+        perm, _ = h.partition()
+        operm, _ = oracle.colour(inst.tri, h.colour_cap)
+        assert np.array_equal(perm, operm)
+        fh = out.first_hit.cpu().numpy()
+        check_run_reduction(fh, out.tts_sweeps, out.winner_clone)
+        gl = list(groups) + ([out.winner_clone // 32] if out.winner_clone >= 0 else [])
+        clones = np.unique(np.r_[group_sample(cfg.n_clones, gl), cfg.n_clones - 1])
+        ref = check_clones(inst.tri, inst.J, operm, cfg, out.sweeps_done, clones, fh,
+                           out.energy.cpu().numpy(), out.state, what=f"instance {k} (N={inst.n})")
+        if out.winner_clone >= 0:
+            w = int(np.flatnonzero(clones == out.winner_clone)[0])
+            assert np.array_equal(out.solved, ref["final_spins"][w])
