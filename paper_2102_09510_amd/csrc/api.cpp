@@ -370,27 +370,49 @@ uint32_t place_layout(uint32_t B, uint32_t CW) { return B < 8 ? B | CW << 8 : 0u
 // Clone-sweeps (clones x sweeps left) from which a run builds the row placement.
 constexpr uint64_t kPlaceMinWork = 1ull << 32;
 
+// The host schedule a descriptor's launch uses (built on first use; caller holds I->mu), and
+// its key in the instance's caches.
+const xsh::HostSched &host_sched(const xs_instance *I, const xs::InstDev &d, uint32_t *key_out) {
+    const uint32_t cap = step_cap(d);
+    uint32_t layout = place_layout(d.tile_blocks, d.col_bytes);
+    // The row placement costs a few µs of host time per spin and saves about 5 % of the
+    // sweep time; a run too short to pay that back uses the unplaced schedule unless the
+    // placed one already exists. Either gives the same results.
+    const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
+    if (layout && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
+        !I->sched.count(sched_key(cap, layout)))
+        layout = 0;
+    const uint32_t key = sched_key(cap, layout);
+    auto hit = I->sched.find(key);
+    if (hit == I->sched.end())
+        hit = I->sched.emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8)).first;
+    *key_out = key;
+    return hit->second;
+}
+
+// Records with the byte offsets of the rows in a tile of B blocks (32 * B bytes per row), as
+// the kernels that read records from global memory take them.
+std::vector<uint32_t> grec_image(const xsh::HostSched &hs, int n, uint32_t B) {
+    const uint32_t rowb = 32u * B;
+    std::vector<uint32_t> g(4 * (size_t)n);
+    for (int p = 0; p < n; ++p) {
+        const uint16_t *r = &hs.rec[8 * (size_t)p];
+        g[4 * p + 0] = (r[0] * rowb) | ((r[1] * rowb) << 16);
+        g[4 * p + 1] = (r[2] * rowb) | ((r[3] * rowb) << 16);
+        g[4 * p + 2] = (r[4] * rowb) | ((r[5] * rowb) << 16);
+        g[4 * p + 3] = (r[6] * rowb) | ((uint32_t)r[7] << 16);
+    }
+    return g;
+}
+
 xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *insts, int count,
                         int device) {
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
         const xs_instance *I = insts[k];
-        const uint32_t cap = step_cap(d);
         std::lock_guard<std::mutex> lock(I->mu);
-        uint32_t layout = place_layout(d.tile_blocks, d.col_bytes);
-        // The row placement costs a few µs of host time per spin and saves about 5 % of the
-        // sweep time; a run too short to pay that back uses the unplaced schedule unless the
-        // placed one already exists. Either gives the same results.
-        const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
-        if (layout && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
-            !I->sched.count(sched_key(cap, layout)))
-            layout = 0;
-        const uint32_t key = sched_key(cap, layout);
-        auto hit = I->sched.find(key);
-        if (hit == I->sched.end())
-            hit = I->sched.emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8))
-                      .first;
-        const xsh::HostSched &hs = hit->second;
+        uint32_t key = 0;
+        const xsh::HostSched &hs = host_sched(I, d, &key);
         xsh::DevSched &ds = I->dev[device].sched[key];
         if (!ds.rec) {
             const size_t n = (size_t)I->n, off_bytes = sizeof(int32_t) * hs.off.size();
@@ -416,15 +438,7 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
         if (!d.rec_global) continue;
         auto it = ds.grec.find(d.tile_blocks);
         if (it == ds.grec.end()) {
-            const uint32_t rowb = 32u * d.tile_blocks;
-            std::vector<uint32_t> g(4 * (size_t)I->n);
-            for (int p = 0; p < I->n; ++p) {
-                const uint16_t *r = &hs.rec[8 * (size_t)p];
-                g[4 * p + 0] = (r[0] * rowb) | ((r[1] * rowb) << 16);
-                g[4 * p + 1] = (r[2] * rowb) | ((r[3] * rowb) << 16);
-                g[4 * p + 2] = (r[4] * rowb) | ((r[5] * rowb) << 16);
-                g[4 * p + 3] = (r[6] * rowb) | ((uint32_t)r[7] << 16);
-            }
+            const std::vector<uint32_t> g = grec_image(hs, I->n, d.tile_blocks);
             DevAlloc dp;
             XS_HIP(hipMalloc(&dp.p, 16 * (size_t)I->n));
             XS_HIP(hipMemcpy(dp.p, g.data(), 16 * (size_t)I->n, hipMemcpyHostToDevice));

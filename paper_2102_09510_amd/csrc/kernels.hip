@@ -47,11 +47,11 @@ namespace {
 constexpr uint32_t kA = 0xF0, kB = 0xCC, kC = 0xAA;
 constexpr uint32_t kXor3 = (kA ^ kB ^ kC) & 0xFF;
 constexpr uint32_t kMaj3 = ((kA & kB) | (kA & kC) | (kB & kC)) & 0xFF;
-constexpr uint32_t kOr3 = (kA | kB | kC) & 0xFF;
-constexpr uint32_t kXorAndNot = ((kA ^ kB) & ~kC) & 0xFF;  // (a ^ b) & ~c
-constexpr uint32_t kXorAnd = (kA ^ (kB & kC)) & 0xFF;      // a ^ (b & c)
 constexpr uint32_t kXorAndN = (kA ^ (kB & ~kC)) & 0xFF;    // a ^ (b & ~c)
 constexpr uint32_t kMux = ((kA & kB) | (~kA & kC)) & 0xFF; // a ? b : c, bitwise
+constexpr uint32_t kXorAnd2 = ((kA ^ kB) & kC) & 0xFF;     // (a ^ b) & c
+constexpr uint32_t kFlipIfEq = (kA ^ (kC & ~(kA ^ kB))) & 0xFF;  // a ^ (c & (a == b))
+constexpr uint32_t kAnyDiff = ((kA ^ kB) | (kA ^ kC)) & 0xFF;    // (a ^ b) | (a ^ c)
 
 template <uint32_t LUT>
 __device__ __forceinline__ uint32_t lop3(uint32_t a, uint32_t b, uint32_t c) {
@@ -95,8 +95,11 @@ __device__ __forceinline__ uint4 philox10_draw(uint32_t i, uint64_t pz, uint32_t
 }
 
 
-// One 32-clone word of one spin: eight three-input operations, a ninth when ground states are
-// tracked (kAcc: acc collects "k >= 1").
+// One 32-clone word of one spin: seven three-input operations, two more when ground states are
+// tracked (kAcc: acc collects "k >= 1"). With d_t = x ^ p_t: k is odd iff x ^ par = 1 (par =
+// p1 ^ p2 ^ p3 = x ^ d1 ^ d2 ^ d3) and k <= 1 iff x = m (x ^ m = maj(d1, d2, d3)). So
+// t = (x ^ par) & accept flips the spin exactly where k = 1 and the group accepts, provided
+// x = m; where x != m (k >= 2) the new spin is m = ~x whatever t is.
 template <bool kAcc>
 __device__ __forceinline__ uint32_t qg_word(uint32_t x, uint32_t a1, uint32_t b1, uint32_t a2,
                                             uint32_t b2, uint32_t a3, uint32_t b3, uint32_t j1,
@@ -107,10 +110,9 @@ __device__ __forceinline__ uint32_t qg_word(uint32_t x, uint32_t a1, uint32_t b1
     const uint32_t p3 = lop3<kXor3>(a3, b3, j3);
     const uint32_t m = lop3<kMaj3>(p1, p2, p3);     // new spin unless k == 1
     const uint32_t par = lop3<kXor3>(p1, p2, p3);
-    const uint32_t dmaj = x ^ m;                     // k >= 2
-    const uint32_t k1 = lop3<kXorAndNot>(x, par, dmaj);  // k == 1
-    if (kAcc) acc = lop3<kOr3>(acc, k1, dmaj);       // k >= 1
-    return lop3<kXorAnd>(m, k1, accept);
+    if (kAcc) acc |= lop3<kAnyDiff>(x, m, par);      // k >= 1
+    const uint32_t t = lop3<kXorAnd2>(x, par, accept);
+    return lop3<kFlipIfEq>(m, x, t);
 }
 
 // The same word with w0 > 0 (Section "The quasi-greedy algorithm": w0 = w1^3 gives the
@@ -170,6 +172,19 @@ extern __shared__ __align__(16) uint8_t xs_lds[];
 
 // Address space of read-only global data that uniform accesses load through the scalar cache.
 #define CONSTANT __attribute__((address_space(4)))
+// Global address space: loads through it are global_load (vector memory counter only), not
+// flat loads, which also count against the LDS counter and so make every LDS wait -- the one
+// before a step's barrier among them -- wait for them too.
+#define GLOBAL_AS __attribute__((address_space(1)))
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// 16-byte global load / store of element idx of a device array (global_load/store_dwordx4).
+__device__ __forceinline__ uint4 gload16(const void *base, size_t idx) {
+    const u32x4 v = ((const GLOBAL_AS u32x4 *)base)[idx];
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore16(void *base, size_t idx, uint4 v) {
+    ((GLOBAL_AS u32x4 *)base)[idx] = u32x4{v.x, v.y, v.z, v.w};
+}
 // LDS address space: an integer LDS address used as a pointer, so that a uniform base folds
 // into scalar arithmetic.
 #define LDS_AS __attribute__((address_space(3)))
@@ -189,6 +204,8 @@ struct Tile {
     uint32_t rb0, rb1;   // acceptance bytes, double-buffered by sweep parity
     uint32_t acc;        // per-group accumulators [8*B] (uint32)
     uint32_t flag;       // workgroup flag (uint32)
+    uint32_t meta;       // spin index of each position (u16): the low 13 bits of the record's
+                         // meta half-word in LDS, or an array of the indices alone (GR)
     uint32_t colbase;    // st + this thread's column
     uint32_t rb_sel, rb_shift;
     uint32_t thr, thr0, key0, key1, iid, nsteps;
@@ -208,7 +225,7 @@ __device__ __forceinline__ uint32_t &lds_u32(uint32_t off) {
 // tile keeps its LDS for clone state (GR).
 template <bool GR>
 __device__ __forceinline__ uint4 rec_at(const Tile &T, uint32_t p) {
-    if (GR) return T.grec[p];
+    if (GR) return gload16(T.grec, p);
     return lds_rec(p);
 }
 
@@ -261,7 +278,8 @@ __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t 
     const uint32_t t_k0 = t ^ T.key0, id_k1 = T.iid ^ T.key1;
     for (uint32_t p = T.tid >> T.lB; p < T.n; p += NT >> T.lB) {
         const uint32_t q = (p << T.lB) + b;
-        const uint32_t i = (rec_at<GR>(T, p).w >> 16) & 0x1FFFu;
+        const uint32_t v = *(const LDS_AS uint16_t *)(uintptr_t)(T.lds0 + T.meta + (GR ? 2 : 16) * p);
+        const uint32_t i = GR ? v : v & 0x1FFFu;  // GR: the array holds the spin index only
         const uint4 o = philox10_draw(i, pz, t_k0, id_k1, T.key0, T.key1);
         if constexpr (MET)
             *reinterpret_cast<uint16_t *>(xs_lds + rb + 2 * q) =
@@ -411,29 +429,29 @@ __device__ __forceinline__ uint32_t check_state(const Tile &T, uint32_t t, uint3
 
 // LDS row of spin i: the instance's row map, or i itself.
 __device__ __forceinline__ uint32_t lds_row(const Tile &T, uint32_t i) {
-    const uint16_t *rm = T.I->rowmap;
+    const GLOBAL_AS uint16_t *rm = (const GLOBAL_AS uint16_t *)T.I->rowmap;
     return rm ? rm[i] : i;
 }
 
 // Stage the tile's rows global -> LDS in 16-byte pieces.
 template <int NT>
 __device__ __forceinline__ void load_state(const Tile &T) {
-    const uint4 *src0 = reinterpret_cast<const uint4 *>(T.I->state + 4 * (size_t)T.blk0);
+    const uint64_t *src0 = T.I->state + 4 * (size_t)T.blk0;
     for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
         const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
-        const uint4 *src = src0 + ((size_t)i * T.W >> 1);
-        *reinterpret_cast<uint4 *>(xs_lds + T.st + lds_row(T, i) * T.rowb + 16 * k) = src[k];
+        *reinterpret_cast<uint4 *>(xs_lds + T.st + lds_row(T, i) * T.rowb + 16 * k) =
+            gload16(src0 + (size_t)i * T.W, k);
     }
 }
 
 // Write the tile's rows back LDS -> global (caller synchronises first).
 template <int NT>
 __device__ __forceinline__ void store_state(const Tile &T) {
-    uint4 *dst0 = reinterpret_cast<uint4 *>(T.I->state + 4 * (size_t)T.blk0);
+    uint64_t *dst0 = T.I->state + 4 * (size_t)T.blk0;
     for (uint32_t q = T.tid; q < T.n * T.n16; q += NT) {
         const uint32_t i = q >> T.l16, k = q & (T.n16 - 1);
-        (dst0 + ((size_t)i * T.W >> 1))[k] =
-            *reinterpret_cast<const uint4 *>(xs_lds + T.st + lds_row(T, i) * T.rowb + 16 * k);
+        gstore16(dst0 + (size_t)i * T.W, k,
+                 *reinterpret_cast<const uint4 *>(xs_lds + T.st + lds_row(T, i) * T.rowb + 16 * k));
     }
 }
 
@@ -483,6 +501,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     T.rb1 = T.rb0 + rbb;
     T.acc = T.rb1 + rbb;
     T.flag = T.acc + 4 * T.ngrp;
+    T.meta = GR ? T.flag + 16 : 14u;  // GR: after the flag; else the top half of each record's w
     T.colbase = T.st + T.col * CW;
     T.rb_sel = (T.col << LG) >> 3;
     T.rb_shift = (T.col << LG) & 7;
@@ -498,8 +517,12 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     T.nsteps = I->n_steps;
 
     // Records: LDS rows -> byte offsets of the rows in this tile (GR: done by the host).
+    // GR: the spin index of every position (for the acceptance pass) into its own LDS array.
+    for (uint32_t p = T.tid; GR && p < T.n; p += NT)
+        *reinterpret_cast<uint16_t *>(xs_lds + T.meta + 2 * p) =
+            (uint16_t)((((const GLOBAL_AS uint32_t *)T.grec)[4 * p + 3] >> 16) & 0x1FFFu);
     for (uint32_t p = T.tid; !GR && p < T.n; p += NT) {
-        const uint4 r = I->rec[p];
+        const uint4 r = gload16(I->rec, p);
         const uint32_t rowb = T.rowb;
         uint4 o;
         o.x = ((r.x & 0xFFFFu) * rowb) | (((r.x >> 16) * rowb) << 16);
@@ -671,7 +694,7 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 }  // namespace
 
 size_t chunk_lds_bytes(uint32_t n, uint32_t B, bool rec_global, bool met) {
-    return (rec_global ? 0 : lds_rec_bytes(n)) + (size_t)n * B * 32 +
+    return (rec_global ? align16(2 * (size_t)n) : lds_rec_bytes(n)) + (size_t)n * B * 32 +
            2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16;
 }
 
