@@ -199,6 +199,28 @@ xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_
                        const xs_run_buffers *bufs, void *stream, xs_run_result *results);
 
 /*
+ * xs_run_batch for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). Same arguments, same checks and
+ * bit-identical results and buffers; the differences:
+ *   - everything the call needs on the device besides the caller's buffers (instance
+ *     descriptors, the tile list, the running-instance counter, the winners' spins and the
+ *     instances' tables, copied in by each call) lives in one library-owned scratch array of
+ *     XS_NOALLOC_SCRATCH_BYTES per device, set aside when the library is loaded and held until
+ *     the process ends; a batch that needs more is rejected with XS_EINVAL (the message gives
+ *     the bytes needed) before anything is launched;
+ *   - no device memory is allocated or freed and no graph, event or stream is created: the
+ *     chunk loop is launched directly on `stream`, and these calls are not timed by
+ *     xs_profile_enable (host bookkeeping still uses the C++ heap);
+ *   - every such call on one device shares that device's scratch, so calls that overlap on one
+ *     device (from several threads, or on several streams) race: serialise them. The call
+ *     synchronises `stream` before it returns, like xs_run_batch.
+ */
+#define XS_NOALLOC_SCRATCH_BYTES 8388608u /* 8 MiB */
+xs_status xs_run_batch_noalloc(int32_t count, const xs_instance *const *insts,
+                               const xs_run_config *cfgs, const xs_run_buffers *bufs,
+                               void *stream, xs_run_result *results);
+
+/*
  * The same batch without blocking the caller: the arguments are checked and copied, the run is
  * driven from a library thread on `stream` (current device of the caller), and xs_wait blocks
  * until it ended, fills results[] and releases the handle (call it exactly once). Until then the

@@ -566,6 +566,11 @@ uint32_t default_rec_global(uint32_t n) { return n >= 512 ? 1u : 0u; }
 struct RunOpts {
     bool graph = true;             // replay the chunk loop as a captured hipGraph
     double *kernel_ms = nullptr;   // if set: time every sweep-chunk launch, add the sum here
+    // If set: device memory of fixed_bytes that holds everything the call needs on the device
+    // (descriptors, tiles, counter, staging, and the instances' tables, copied in per call).
+    // The call then allocates no device memory and creates no graph, event or stream.
+    uint8_t *fixed = nullptr;
+    size_t fixed_bytes = 0;
 };
 
 // Tuned launch knobs (tile_blocks, wg_threads, col_bytes, rec_global) per workload key,
@@ -735,41 +740,113 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
 
     std::vector<xs::InstDev> h(count);
     std::vector<uint2> tiles;
+    const bool fixed = opt.fixed != nullptr;
     for (int k = 0; k < count; ++k) {
         xs_status st = validate_run(insts[k], &cfgs[k], &bufs[k], true);
         if (st != XS_OK) return st;
         DeviceTables t;
-        st = ensure_tables(insts[k], device, &t);
-        if (st != XS_OK) return st;
+        if (!fixed) {
+            st = ensure_tables(insts[k], device, &t);
+            if (st != XS_OK) return st;
+        }
         fill_desc(insts[k], cfgs[k], t, bufs[k].state, bufs[k].first_hit, bufs[k].energy, h[k]);
     }
     std::vector<TileGroup> groups;
     {
         xs_status st = tile_instances(h, cfgs, count, tiles, groups);
         if (st != XS_OK) return st;
-        st = attach_tables(h, insts, count, device);
-        if (st != XS_OK) return st;
+        if (!fixed) {
+            st = attach_tables(h, insts, count, device);
+            if (st != XS_OK) return st;
+        }
     }
-    // Per-call device scratch: descriptors, tiles, the running-instance counter and the
-    // winners' spins.
+    // Device scratch of the call: descriptors, tiles, the running-instance counter and the
+    // winners' spins (and, with fixed scratch, the instances' tables).
+    auto a256 = [](size_t v) { return (v + 255) & ~size_t(255); };
     size_t solved_bytes = 0;
     std::vector<size_t> solved_off(count);
     for (int k = 0; k < count; ++k) {
         solved_off[k] = solved_bytes;
         solved_bytes += (h[k].n + 15) & ~15u;
     }
-    const size_t off_tiles = (sizeof(xs::InstDev) * count + 255) & ~size_t(255);
-    const size_t off_active = off_tiles + ((sizeof(uint2) * tiles.size() + 255) & ~size_t(255));
+    const size_t off_tiles = a256(sizeof(xs::InstDev) * count);
+    const size_t off_active = off_tiles + a256(sizeof(uint2) * tiles.size());
     const size_t off_solved = off_active + 256;
-    const size_t total = off_solved + solved_bytes;
-    uint8_t *scratch = nullptr;
-    XS_HIP(hipMalloc(&scratch, total));
+    size_t total = off_solved + solved_bytes;
+    // Fixed scratch: each distinct (instance, schedule, tiling, record placement) gets its
+    // tables (triplets, records, step offsets, row map, global-memory records) in one host
+    // image after the staging area, copied with one transfer; descriptors take their offsets.
+    const size_t off_tables = a256(total);
+    std::vector<uint8_t> image;
+    struct TabOff {
+        size_t tri, rec, off, rowmap, grec;
+        uint32_t steps;
+    };
+    std::vector<TabOff> tab_of(count);
+    if (fixed) {
+        std::map<std::tuple<const xs_instance *, uint32_t, uint32_t, uint32_t>, int> seen;
+        auto put = [&](const void *src, size_t bytes) {
+            const size_t at = image.size();
+            image.resize(a256(at + bytes), 0);
+            std::memcpy(image.data() + at, src, bytes);
+            return at;
+        };
+        for (int k = 0; k < count; ++k) {
+            const xs_instance *I = insts[k];
+            std::lock_guard<std::mutex> lock(I->mu);
+            uint32_t key = 0;
+            const xsh::HostSched &hs = host_sched(I, h[k], &key);
+            const auto id = std::make_tuple(I, key, h[k].tile_blocks, h[k].rec_global);
+            auto it = seen.find(id);
+            if (it != seen.end()) {
+                tab_of[k] = tab_of[it->second];
+                continue;
+            }
+            seen.emplace(id, k);
+            const size_t n = (size_t)I->n;
+            TabOff &o = tab_of[k];
+            o.tri = put(I->tri16.data(), 8 * n);
+            o.rec = put(hs.rec.data(), 16 * n);
+            o.off = put(hs.off.data(), sizeof(int32_t) * hs.off.size());
+            o.rowmap = hs.rowmap.empty() ? SIZE_MAX : put(hs.rowmap.data(), 2 * n);
+            o.grec = SIZE_MAX;
+            if (h[k].rec_global) {
+                const std::vector<uint32_t> g = grec_image(hs, I->n, h[k].tile_blocks);
+                o.grec = put(g.data(), 16 * n);
+            }
+            o.steps = (uint32_t)hs.off.size() - 1;
+        }
+        total = off_tables + image.size();
+        if (total > opt.fixed_bytes)
+            return fail(XS_EINVAL,
+                        "the batch needs %zu bytes of device scratch, more than the %zu the "
+                        "no-allocation entry point has",
+                        total, opt.fixed_bytes);
+    }
+    uint8_t *scratch = opt.fixed;
+    if (!fixed) XS_HIP(hipMalloc(&scratch, total));
     struct Free {
         uint8_t *p;
         ~Free() { if (p) (void)hipFree(p); }
-    } guard{scratch};
+    } guard{fixed ? nullptr : scratch};
     for (int k = 0; k < count; ++k)
         h[k].solved = reinterpret_cast<int8_t *>(scratch + off_solved + solved_off[k]);
+    if (fixed) {
+        uint8_t *tb = scratch + off_tables;
+        for (int k = 0; k < count; ++k) {
+            const TabOff &o = tab_of[k];
+            xs::InstDev &d = h[k];
+            d.tri = reinterpret_cast<const uint2 *>(tb + o.tri);
+            d.rec = reinterpret_cast<const uint4 *>(tb + o.rec);
+            d.step_off = reinterpret_cast<const int32_t *>(tb + o.off);
+            d.rowmap = o.rowmap == SIZE_MAX ? nullptr
+                                            : reinterpret_cast<const uint16_t *>(tb + o.rowmap);
+            d.grec = o.grec == SIZE_MAX ? nullptr : reinterpret_cast<const uint4 *>(tb + o.grec);
+            d.n_steps = o.steps;
+        }
+        if (!image.empty())
+            XS_HIP(hipMemcpyAsync(tb, image.data(), image.size(), hipMemcpyHostToDevice, stream));
+    }
     xs::InstDev *d_inst = reinterpret_cast<xs::InstDev *>(scratch);
     uint2 *d_tiles = reinterpret_cast<uint2 *>(scratch + off_tiles);
     uint32_t *d_active = reinterpret_cast<uint32_t *>(scratch + off_active);
@@ -788,7 +865,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         std::lock_guard<std::mutex> lock(g_prof.mu);
         profile = g_prof.on;
     }
-    const bool timed = profile || opt.kernel_ms;
+    const bool timed = !fixed && (profile || opt.kernel_ms);  // events are HIP objects
     std::vector<hipEvent_t> ev;
     struct Events {
         std::vector<hipEvent_t> *v;
@@ -820,7 +897,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
                 XS_HIP(hipEventCreate(&e));
                 ev.push_back(e);
             }
-        if (!timed && opt.graph && group >= 2) {
+        if (!timed && opt.graph && !fixed && group >= 2) {
             // A graph of at most kGraphChunks chunks, launched group / g times: larger groups
             // reuse it instead of capturing and instantiating a graph per size.
             const int g = std::min(group, kGraphChunks);
@@ -1201,6 +1278,18 @@ xs_status xs_run_batch(int32_t count, const xs_instance *const *insts, const xs_
     return guarded([&]() -> xs_status {
         return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results,
                          RunOpts{});
+    });
+}
+
+xs_status xs_run_batch_noalloc(int32_t count, const xs_instance *const *insts,
+                               const xs_run_config *cfgs, const xs_run_buffers *bufs,
+                               void *stream, xs_run_result *results) {
+    return guarded([&]() -> xs_status {
+        RunOpts opt;
+        opt.graph = false;
+        XS_HIP(xs::noalloc_scratch(&opt.fixed, &opt.fixed_bytes));
+        return run_batch(count, insts, cfgs, bufs, reinterpret_cast<hipStream_t>(stream), results,
+                         opt);
     });
 }
 

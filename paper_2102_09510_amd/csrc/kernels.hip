@@ -34,6 +34,7 @@
 // the first visited spin of any unsatisfied triplet still sees it (every spin before it had
 // k = 0 and kept its value), so the OR is one; if C_t is a ground state nothing moves.
 #include <atomic>
+#include <mutex>
 
 #include "xs_internal.h"
 
@@ -785,6 +786,31 @@ hipError_t launch_final(InstDev *d_insts, int count, uint32_t max_words, uint32_
     hipLaunchKernelGGL(qg_winner, g_clones, dim3(256), 0, s, d_insts);
     hipLaunchKernelGGL(qg_gather, g_spins, dim3(256), 0, s, d_insts);
     return hipGetLastError();
+}
+
+// Device scratch of xs_run_batch_noalloc: one array per device, held until the process ends,
+// shared by every such call on that device (calls that overlap on one device race). In host
+// code its name is not a device address; noalloc_scratch looks the address up.
+static __device__ __align__(256) uint8_t scratch[XS_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(uint8_t **ptr, size_t *bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static uint8_t *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<uint8_t *>(p);
+    }
+    *ptr = addr[dev];
+    *bytes = sizeof scratch;
+    return hipSuccess;
 }
 
 }  // namespace xs

@@ -60,4 +60,7 @@ hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStr
 hipError_t launch_final(InstDev *d_insts, int count, uint32_t max_words, uint32_t max_n,
                         hipStream_t s);
 size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, bool rec_global, bool met);
+// The no-allocation entry point's device scratch on the current device: its device address
+// (looked up once per device with hipGetSymbolAddress, with that device current) and size.
+hipError_t noalloc_scratch(uint8_t **ptr, size_t *bytes);
 }  // namespace xs

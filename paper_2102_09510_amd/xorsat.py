@@ -25,12 +25,13 @@ XS_PLACE_ROWS = 0x4
 XS_MAX_N = 2048
 XS_CLONE_QUANTUM = 256
 XS_MAX_CLONES = 0x7FFFFF00
+XS_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 # Every function the header declares, for the export check.
 EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_create",
            "xs_instance_destroy", "xs_instance_get_info", "xs_instance_get_partition",
            "xs_instance_get_schedule",
-           "xs_run", "xs_run_batch", "xs_run_batch_async", "xs_wait",
+           "xs_run", "xs_run_batch", "xs_run_batch_noalloc", "xs_run_batch_async", "xs_wait",
            "xs_profile_enable", "xs_profile_read",
            "xs_autotune", "xs_tune_save", "xs_tune_load", "xs_tune_clear",
            "xs_server_create", "xs_server_destroy", "xs_server_submit", "xs_server_step",
@@ -147,6 +148,8 @@ def load():
     lib.xs_run.restype = i32
     lib.xs_run_batch.argtypes = [i32, P, P, P, P, P]
     lib.xs_run_batch.restype = i32
+    lib.xs_run_batch_noalloc.argtypes = [i32, P, P, P, P, P]
+    lib.xs_run_batch_noalloc.restype = i32
     lib.xs_run_batch_async.argtypes = [i32, P, P, P, P, P, ctypes.POINTER(P)]
     lib.xs_run_batch_async.restype = i32
     lib.xs_wait.argtypes = [P]
@@ -325,6 +328,24 @@ def run_batch(insts: list[Instance], cfgs: list[RunConfig], *, states=None,
     buf_arr = (RunBuffers * count)(*[m[0] for m in made])
     res_arr = (RunResult * count)()
     _check(load().xs_run_batch(count, handles, cfg_arr, buf_arr, _stream(), res_arr))
+    return [_output(res_arr[k], *made[k][1:]) for k in range(count)]
+
+
+def run_batch_noalloc(insts: list[Instance], cfgs: list[RunConfig], *, states=None,
+                      want_energy: bool = True, device="cuda") -> list[RunOutput]:
+    """xs_run_batch_noalloc: the batch with the library's fixed device scratch (no device
+    allocation inside the call; torch allocates the caller's output buffers here)."""
+    count = len(insts)
+    if count == 0 or count != len(cfgs):
+        raise ValueError(f"need one config per instance and at least one instance "
+                         f"({count} instances, {len(cfgs)} configs)")
+    states = states or [None] * count
+    made = [_buffers(i, c, s, want_energy, device) for i, c, s in zip(insts, cfgs, states)]
+    handles = (ctypes.c_void_p * count)(*[i.handle.value for i in insts])
+    cfg_arr = (RunConfig * count)(*cfgs)
+    buf_arr = (RunBuffers * count)(*[m[0] for m in made])
+    res_arr = (RunResult * count)()
+    _check(load().xs_run_batch_noalloc(count, handles, cfg_arr, buf_arr, _stream(), res_arr))
     return [_output(res_arr[k], *made[k][1:]) for k in range(count)]
 
 

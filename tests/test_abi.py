@@ -47,7 +47,8 @@ def test_header_constants_match_the_binding():
     defs = {m.group(1): int(m.group(2), 0)
             for m in re.finditer(r"#define\s+(XS_[A-Z_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text)}
     for name in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_MAX_N",
-                 "XS_CLONE_QUANTUM", "XS_MAX_CLONES", "XS_TUNE_MAX_TRIALS"):
+                 "XS_CLONE_QUANTUM", "XS_MAX_CLONES", "XS_TUNE_MAX_TRIALS",
+                 "XS_NOALLOC_SCRATCH_BYTES"):
         assert defs[name] == getattr(xorsat, name), name
     for code, name in xorsat.XS_STATUS.items():
         assert defs[name] == code, name
