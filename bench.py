@@ -76,6 +76,9 @@ def parse():
                          "and serve; 5*10^4 for batched, whose first ground states at N=256 take "
                          "far longer, so most instances end at the budget)")
     ap.add_argument("--chunk", type=int, default=100)
+    ap.add_argument("--per-chunk", action="store_true",
+                    help="launch every chunk separately (XS_PER_CHUNK) instead of the persistent "
+                         "work-queue launch (speed only)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
@@ -766,7 +769,8 @@ def headline(args, xorsat, torch):
         cfgs = [xorsat.make_config(n_clones=clones, seed=run_seed(H["config"], k) + s,
                                    instance_id=k, accept_thr=THR_PAPER,
                                    accept_thr0=args.accept_thr0, max_sweeps=budget,
-                                   stop_on_first=stop, chunk_sweeps=chunk, place_rows=place)
+                                   stop_on_first=stop, chunk_sweeps=chunk, place_rows=place,
+                                   per_chunk=args.per_chunk)
                 for k in range(count)]
         return xorsat.run_batch(handles, cfgs, want_energy=True)
 
@@ -794,6 +798,7 @@ def headline(args, xorsat, torch):
             else:
                 censored += 1
         shape = (outs[0].tile_blocks, outs[0].wg_threads, outs[0].col_bytes, outs[0].rec_global)
+        persistent = bool(outs[0].persistent)
         print(f"# step {s} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -801,10 +806,16 @@ def headline(args, xorsat, torch):
     prof = xorsat.profile_read(reset=True)
     value = updates / dt / 1e9
     kern_rate = prof["clone_spin_updates"] / (prof["total_ms"] * 1e6) if prof["total_ms"] else 0
-    # A launch covers `chunk` sweeps of every instance; launches after the budget ran out (every
-    # tile exits at once, a few us each) are counted apart, their time stays in.
-    per_launch_updates = count * clones * n * chunk
-    full_launches = prof["clone_spin_updates"] / per_launch_updates
+    # Persistent launches: one launch runs up to a whole epoch of chunks of every instance, so
+    # the figures are per launch as rocprofv3 lists them. Launch per chunk: a launch covers
+    # `chunk` sweeps of every instance; launches after the budget ran out (every tile exits at
+    # once, a few us each) are counted apart, their time stays in.
+    if persistent:
+        full_launches = prof["launches"]
+        per_launch_updates = prof["clone_spin_updates"] / max(full_launches, 1)
+    else:
+        per_launch_updates = count * clones * n * chunk
+        full_launches = prof["clone_spin_updates"] / per_launch_updates
     avg_ms = prof["total_ms"] / max(full_launches, 1e-9)
     lds_tbs = ALGO_LDS_BYTES_PER_UPDATE * per_launch_updates / (avg_ms * 1e-3) / 1e12
     ops = ALGO_OPS_PER_UPDATE_W0 if args.accept_thr0 else ALGO_OPS_PER_UPDATE
@@ -829,6 +840,7 @@ def headline(args, xorsat, torch):
         "config": {"workload": desc, "chunk_sweeps": chunk, "accept_thr": THR_PAPER,
                    "colour_cap": args.cap, "launch_shape": dict(zip(
                        ("tile_blocks", "wg_threads", "col_bytes", "rec_global"), shape)),
+                   "launch": "persistent work queue" if persistent else "one per chunk",
                    **({"accept_thr0": args.accept_thr0} if args.accept_thr0 else {}),
                    **({"place_rows": True} if place else {})},
         "tts_sweeps": {"solved": len(tts), "censored": censored,
@@ -838,8 +850,10 @@ def headline(args, xorsat, torch):
                      "frac": round(lds_tbs / LDS_PEAK_TBS, 4),
                      "traffic": measured_traffic(args, wl, (count, n, clones)),
                      "bytes_per_update": ALGO_LDS_BYTES_PER_UPDATE,
-                     "kernel": "qg_chunk", "launches": round(full_launches, 2),
-                     "launches_past_budget": prof["launches"] - round(full_launches),
+                     "kernel": "qg_queue_run" if persistent else "qg_chunk",
+                     "launches": round(full_launches, 2),
+                     "launches_past_budget": 0 if persistent
+                     else prof["launches"] - round(full_launches),
                      "updates_per_launch": per_launch_updates,
                      "avg_launch_ms": round(avg_ms, 3),
                      "kernel_updates_per_ns": round(kern_rate, 3),

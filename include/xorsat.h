@@ -57,6 +57,10 @@ typedef int32_t xs_status;
                                  once per instance and tiling, kept for later runs). Without
                                  it, runs of fewer than 2^32 clone-sweeps use the placement
                                  only if it already exists. */
+#define XS_PER_CHUNK 0x8u     /* launch every chunk separately (one launch per launch shape,
+                                 then a decision kernel) instead of the persistent work-queue
+                                 launch; speed only. A batch runs per chunk if any of its
+                                 configs sets it. */
 
 typedef struct xs_instance xs_instance;
 
@@ -123,7 +127,7 @@ typedef struct {
     uint64_t seed;         /* Philox key */
     uint32_t n_clones;     /* > 0, multiple of XS_CLONE_QUANTUM, <= XS_MAX_CLONES */
     uint32_t accept_thr;   /* w1 threshold, 0 .. 65536 */
-    uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS */
+    uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS | XS_PER_CHUNK */
     uint32_t max_sweeps;   /* sweep budget of this call (0 = only check the start state) */
     uint32_t start_sweep;  /* absolute index of the first sweep (for resumed runs) */
     uint32_t chunk_sweeps; /* sweeps between stop checks, K (0 = 100, as in the paper) */
@@ -174,6 +178,8 @@ typedef struct {
     uint32_t wg_threads;         /* workgroup size used (result-neutral) */
     uint32_t col_bytes;          /* task column width used (result-neutral) */
     uint32_t rec_global;         /* 1 if records were read from global memory (result-neutral) */
+    uint32_t persistent;         /* 1 if the run used persistent work-queue launches, 0 if a
+                                    launch per chunk (result-neutral) */
     uint64_t clone_spin_updates; /* n_clones * n * sweeps_done */
     double seconds;              /* wall time of the call */
 } xs_run_result;

@@ -499,7 +499,7 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
     if (cfg->accept_thr0 && (cfg->flags & XS_STOP_ON_FIRST))
         return fail(XS_EINVAL, "XS_STOP_ON_FIRST needs accept_thr0 = 0 (with w0 > 0 a ground "
                                "state is not absorbing and no sweep is tested)");
-    if (cfg->flags & ~(XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS))
+    if (cfg->flags & ~(XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS | XS_PER_CHUNK))
         return fail(XS_EINVAL, "unknown flags 0x%x", cfg->flags);
     if ((uint64_t)cfg->start_sweep + cfg->max_sweeps >= 0xFFFFFFFFull)
         return fail(XS_EINVAL, "start_sweep + max_sweeps must stay below 2^32 - 1");
@@ -729,6 +729,118 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
     return XS_OK;
 }
 
+// A batch run as persistent work-queue launches (qg_queue_run): one launch per epoch of up to
+// epoch_chunks chunks of every unfinished instance, instead of a launch per chunk and launch
+// shape.
+struct QueuePlan {
+    bool on = false;
+    uint32_t threads = 0;
+    bool met = false;
+    size_t lds = 0;
+    int grid = 0;
+    uint32_t epoch_chunks = 0;
+    std::vector<uint2> tiles;     // largest tiles first, each instance's tiles together
+    std::vector<uint32_t> order;  // instance indices in tile-list order
+};
+
+// Queue mode needs one workgroup size and one rule for the whole batch and column widths of 8
+// or 16 bytes. The workgroup size is the configs' explicit one, else the default of the
+// instance with the most work; every descriptor then takes it (its step cap follows). The ring
+// takes 8 bytes per tile and chunk of an epoch, within ring_budget bytes. Leaves qp.on false
+// (launch per chunk) when the batch does not qualify.
+xs_status plan_queue(std::vector<xs::InstDev> &h_io, const xs_run_config *cfgs, int count,
+                     int device, size_t ring_budget, QueuePlan &qp) {
+    qp.on = false;
+    std::vector<xs::InstDev> h = h_io;  // committed only if the batch runs from the queue
+    const bool met = h[0].thr0 != 0;
+    uint32_t T = 0;
+    int heavy = 0;
+    double heavy_work = -1.0, upd_chunk = 0.0;
+    size_t n_tiles = 0;
+    for (int k = 0; k < count; ++k) {
+        const xs::InstDev &d = h[k];
+        if ((cfgs[k].flags & XS_PER_CHUNK) || (d.thr0 != 0) != met) return XS_OK;
+        if (d.col_bytes != 8 && d.col_bytes != 16) return XS_OK;
+        if (cfgs[k].wg_threads) {
+            if (T && T != cfgs[k].wg_threads) return XS_OK;
+            T = cfgs[k].wg_threads;
+        }
+        const double clones = 64.0 * d.n_words;
+        const double work = clones * d.n * (double)(d.t_stop - d.t_cur);
+        if (work > heavy_work) {
+            heavy_work = work;
+            heavy = k;
+        }
+        if (!d.done) upd_chunk += clones * d.n * d.chunk;
+        n_tiles += d.n_words * 64 / 256 / d.tile_blocks;
+    }
+    if (!T) T = h[heavy].wg_threads;
+    if (T != 256 && T != 512) return XS_OK;
+    // Every workgroup of the launch reserves the largest tile's LDS. Tiles of library-chosen
+    // size whose LDS would lower the number of workgroups per CU that the instance with the
+    // most work gets are halved until they fit its share.
+    auto lds_of = [&](const xs::InstDev &d) {
+        return xs::chunk_lds_bytes(d.n, d.tile_blocks, d.rec_global != 0, met);
+    };
+    constexpr size_t kLdsCu = 160 * 1024 - 64;  // per CU, less the kernel's own 8 bytes
+    int occ_threads = 0;
+    XS_HIP(xs::queue_blocks_per_cu((int)T, met, 0, &occ_threads));
+    const size_t lds_heavy = lds_of(h[heavy]);
+    if (occ_threads <= 0 || lds_heavy > kLdsCu) return XS_OK;
+    const size_t occ = std::min<size_t>((size_t)occ_threads, kLdsCu / lds_heavy);
+    const size_t lds_cap = kLdsCu / occ;
+    for (int k = 0; k < count; ++k) {
+        xs::InstDev &d = h[k];
+        if (cfgs[k].tile_blocks) continue;
+        while (d.tile_blocks > 1 && lds_of(d) > lds_cap) {
+            d.tile_blocks /= 2;
+            d.log2_tile_blocks -= 1;
+        }
+        if (d.col_bytes == 16 && d.tile_blocks == 1 && !cfgs[k].col_bytes) d.col_bytes = 8;
+    }
+    size_t lds = 0;
+    n_tiles = 0;
+    for (int k = 0; k < count; ++k) {
+        if (8 * h[k].tile_blocks > T) return XS_OK;
+        lds = std::max(lds, lds_of(h[k]));
+        n_tiles += h[k].n_words * 64 / 256 / h[k].tile_blocks;
+    }
+    if (lds > kLdsCu) return XS_OK;
+    // Epoch: about two seconds of the batch's sweeps at 10 K updates/ns, 1 to 64 chunks, and
+    // no more than the ring budget holds.
+    uint32_t E = (uint32_t)std::max(1.0, std::min(64.0, 2.0 / (upd_chunk / 1e13 + 1e-12)));
+    E = (uint32_t)std::min<size_t>(E, ring_budget / (8 * std::max<size_t>(n_tiles, 1)));
+    if (E < 1 || n_tiles * E >= 0xFFFFFFFFull) return XS_OK;
+    int per_cu = 0, cus = 0;
+    XS_HIP(xs::queue_blocks_per_cu((int)T, met, lds, &per_cu));
+    XS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    if (per_cu <= 0 || cus <= 0) return XS_OK;
+    // Largest tiles (spins x blocks) first; an instance's tiles stay together.
+    qp.order.resize(count);
+    for (int k = 0; k < count; ++k) qp.order[k] = (uint32_t)k;
+    std::stable_sort(qp.order.begin(), qp.order.end(), [&](uint32_t a, uint32_t b) {
+        return (uint64_t)h[a].n * h[a].tile_blocks > (uint64_t)h[b].n * h[b].tile_blocks;
+    });
+    qp.tiles.clear();
+    qp.tiles.reserve(n_tiles);
+    for (uint32_t k : qp.order) {
+        xs::InstDev &d = h[k];
+        const uint32_t nb = d.n_words * 64 / 256;
+        d.tile0 = (uint32_t)qp.tiles.size();
+        d.ntiles = nb / d.tile_blocks;
+        for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) qp.tiles.push_back(make_uint2(k, b0));
+        d.wg_threads = T;
+    }
+    qp.threads = T;
+    qp.met = met;
+    qp.lds = lds;
+    qp.grid = (int)std::min<size_t>((size_t)per_cu * cus, qp.tiles.size());
+    qp.epoch_chunks = E;
+    qp.on = true;
+    h_io.swap(h);
+    return XS_OK;
+}
+
 xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run_config *cfgs,
                     const xs_run_buffers *bufs, hipStream_t stream, xs_run_result *results,
                     const RunOpts &opt) {
@@ -752,9 +864,13 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         fill_desc(insts[k], cfgs[k], t, bufs[k].state, bufs[k].first_hit, bufs[k].energy, h[k]);
     }
     std::vector<TileGroup> groups;
+    QueuePlan qp;
     {
         xs_status st = tile_instances(h, cfgs, count, tiles, groups);
         if (st != XS_OK) return st;
+        st = plan_queue(h, cfgs, count, device, fixed ? opt.fixed_bytes / 2 : SIZE_MAX, qp);
+        if (st != XS_OK) return st;
+        if (qp.on) tiles.swap(qp.tiles);
         if (!fixed) {
             st = attach_tables(h, insts, count, device);
             if (st != XS_OK) return st;
@@ -773,6 +889,12 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     const size_t off_active = off_tiles + a256(sizeof(uint2) * tiles.size());
     const size_t off_solved = off_active + 256;
     size_t total = off_solved + solved_bytes;
+    // Queue mode: the queue counters, the instance order and the ring.
+    const size_t off_queue = a256(total);
+    const size_t off_order = off_queue + a256(sizeof(xs::QueueDev));
+    const size_t off_ring = off_order + a256(sizeof(uint32_t) * count);
+    const uint32_t ring_cap = qp.on ? (uint32_t)(tiles.size() * qp.epoch_chunks) : 0u;
+    if (qp.on) total = off_ring + sizeof(uint64_t) * ring_cap;
     // Fixed scratch: each distinct (instance, schedule, tiling, record placement) gets its
     // tables (triplets, records, step offsets, row map, global-memory records) in one host
     // image after the staging area, copied with one transfer; descriptors take their offsets.
@@ -855,6 +977,21 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
                           stream));
     XS_HIP(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(uint2) * tiles.size(),
                           hipMemcpyHostToDevice, stream));
+    xs::QueueDev *d_q = reinterpret_cast<xs::QueueDev *>(scratch + off_queue);
+    uint32_t *d_order = reinterpret_cast<uint32_t *>(scratch + off_order);
+    uint64_t *d_ring = reinterpret_cast<uint64_t *>(scratch + off_ring);
+    xs::QueueDev q_init{};
+    if (qp.on) {
+        q_init.ring = d_ring;
+        q_init.cap = ring_cap;
+        int clock_khz = 0;  // wall-clock rate of wall_clock64()
+        XS_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device));
+        q_init.wait_limit = (uint64_t)std::max(clock_khz, 1) * 1000ull * 60ull;  // a minute
+        XS_HIP(hipMemcpyAsync(d_q, &q_init, sizeof q_init, hipMemcpyHostToDevice, stream));
+        XS_HIP(hipMemcpyAsync(d_order, qp.order.data(), sizeof(uint32_t) * count,
+                              hipMemcpyHostToDevice, stream));
+        XS_HIP(xs::launch_queue_clear(d_ring, ring_cap, stream));
+    }
     for (int k = 0; k < count; ++k) XS_HIP(xs::launch_init(d_inst + k, h[k], stream));
 
     bool any_running = false;
@@ -886,6 +1023,35 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         }
         return XS_OK;
     };
+    // Queue mode: per epoch, the set-up kernel and one persistent launch; the host reads the
+    // count of unfinished instances (and the queue's error flag) after each.
+    for (uint32_t gen = 1; qp.on && any_running; ++gen) {
+        if (timed)
+            while (ev.size() < 2) {
+                hipEvent_t e;
+                XS_HIP(hipEventCreate(&e));
+                ev.push_back(e);
+            }
+        XS_HIP(xs::launch_queue_setup(d_inst, count, d_order, d_tiles, (uint32_t)tiles.size(), d_q,
+                                      gen, qp.epoch_chunks, stream));
+        if (timed) XS_HIP(hipEventRecord(ev[0], stream));
+        XS_HIP(xs::launch_queue_run(d_inst, d_tiles, d_q, gen, (int)qp.threads, qp.met, qp.lds,
+                                    qp.grid, stream));
+        if (timed) XS_HIP(hipEventRecord(ev[1], stream));
+        xs::QueueDev qh;
+        XS_HIP(hipMemcpyAsync(&qh, d_q, sizeof qh, hipMemcpyDeviceToHost, stream));
+        XS_HIP(hipStreamSynchronize(stream));
+        if (qh.error)
+            return fail(XS_EDEVICE, "persistent launch: a workgroup's wait for work reached its "
+                                    "time limit");
+        if (timed) {
+            float ms = 0.f;
+            XS_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            local.total_ms += ms;
+            local.launches += 1;
+        }
+        any_running = qh.active != 0;
+    }
     // Chunk loop: chunk launches over all tiles, then the device-side decision. The host reads
     // the count of running instances every `group` chunks (finished instances' tiles exit at
     // once, so launching ahead changes no result). Untimed loops of two or more chunks are
@@ -966,6 +1132,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         r.wg_threads = d.wg_threads;
         r.col_bytes = d.col_bytes;
         r.rec_global = d.rec_global;
+        r.persistent = qp.on ? 1u : 0u;
         r.clone_spin_updates = (uint64_t)d.n_words * 64 * d.n * r.sweeps_done;
         r.seconds = secs;
         if (bufs[k].solved && d.winner != INT32_MAX)

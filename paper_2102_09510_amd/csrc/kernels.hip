@@ -33,6 +33,7 @@
 // (k >= 1) over all visited spins is zero iff C_t has E = -N. If C_t has an unsatisfied triplet,
 // the first visited spin of any unsatisfied triplet still sees it (every spin before it had
 // k = 0 and kept its value), so the OR is one; if C_t is a ground state nothing moves.
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 
@@ -456,8 +457,18 @@ __device__ __forceinline__ void store_state(const Tile &T) {
     }
 }
 
-// K sweeps (or fewer at the budget end) of one workgroup tile. The grid holds every tile of
-// every instance of the batch; tiles of finished instances return at once.
+// Control fields of a descriptor that kernels change while others run (t_cur, done, track,
+// hit, arrived): read with vector loads at device scope, never through the scalar cache.
+__device__ __forceinline__ uint32_t ld_dev(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sweeps [t0, t1) (one chunk) of one workgroup tile: the tile of blocks blk0 .. blk0 + B - 1
+// of instance I, its rows staged in LDS and written back at the end. The caller passes
+// t0 < t1.
 //
 // The hot loop does not track ground states. After the chunk every clone is tested once; with
 // w0 = 0 a ground state is never left, so a clone in a ground state now that had no hit before
@@ -469,17 +480,9 @@ __device__ __forceinline__ void store_state(const Tile &T) {
 // MET (w0 > 0): a ground state can be left again, so no sweep is tested; the final pass tests
 // the end configuration only.
 template <int NT, int CW, bool GR, bool MET>
-__global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
-                                               const uint2 *__restrict__ tiles) {
+__device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t0, uint32_t t1) {
     constexpr int G = CW / 4;        // groups per column
     constexpr int LG = G == 4 ? 2 : G == 2 ? 1 : 0;
-    const uint2 tile = tiles[blockIdx.x];
-    InstDev *I = insts + tile.x;
-    if (I->done) return;
-    const uint32_t t0 = I->t_cur;
-    const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
-    if (t0 >= t1) return;
-
     Tile T;
     T.I = I;
     T.n = I->n;
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     T.n16 = T.B << 1;
     T.l16 = T.lB + 1;
     T.ngrp = T.B << 3;
-    T.blk0 = tile.y;
+    T.blk0 = blk0;
     T.tid = threadIdx.x;
     T.col = T.tid & (T.ncol - 1);  // fixed per thread: NT is a multiple of ncol
     T.grec = I->grec;
@@ -555,7 +558,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     __syncthreads();  // records, state and accumulators visible to every thread
     if (t0 == I->t_start) check_state<NT, CW, GR>(T, t0, hm);  // the run's start configuration
 
-    if (I->track) {
+    if (ld_dev(&I->track)) {
         // This instance keeps producing new ground-state clones: test every sweep.
         uint32_t hm_t = hm;
         accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
@@ -602,6 +605,21 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     store_state<NT>(T);
 }
 
+// One chunk (K sweeps, or fewer at the budget end) of every tile in `tiles`, one workgroup per
+// tile. The grid holds every tile of every instance of the batch with this launch shape; tiles
+// of finished instances return at once.
+template <int NT, int CW, bool GR, bool MET>
+__global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
+                                               const uint2 *__restrict__ tiles) {
+    const uint2 tile = tiles[blockIdx.x];
+    InstDev *I = insts + tile.x;
+    if (ld_dev(&I->done)) return;
+    const uint32_t t0 = ld_dev(&I->t_cur);
+    const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
+    if (t0 >= t1) return;
+    tile_chunk<NT, CW, GR, MET>(I, tile.y, t0, t1);
+}
+
 // ------------------------------------------------------------------------------ control
 
 // After a chunk: advance every unfinished instance, end it at the budget or (stop-on-first)
@@ -625,6 +643,180 @@ __global__ __launch_bounds__(256) void qg_decide(InstDev *insts, int count, uint
     atomicAdd(&total, mine);
     __syncthreads();
     if (threadIdx.x == 0) *active = total;
+}
+
+// ------------------------------------------------------------------------------ work queue
+
+// A persistent launch runs the chunks of many instances without a launch per chunk. Tickets
+// (Q->head) are taken in order; ticket q is served by slot q of the ring, which a push fills
+// with (launch tag << 32) | tile index. A set-up kernel fills the first slots with every tile
+// of every unfinished instance (largest tiles first: the host orders the tile list). The last
+// tile of an instance to finish a chunk decides for the instance, as qg_decide does for the
+// launch-per-chunk loop, and while the instance may run more chunks in this launch it reserves
+// slots for all its tiles and publishes them. Every published slot is served: a ticket below
+// the reserved count is held by a workgroup that takes it and waits for its slot, and slots
+// are published by workgroups that are running. Once no instance of the launch can push any
+// more (Q->live = 0), every reserved slot has been served, so the workgroups still waiting hold
+// tickets that no push will reach; Q->finished releases them.
+
+constexpr uint32_t kNoItem = 0xFFFFFFFFu;
+
+__global__ __launch_bounds__(256) void qg_queue_clear(uint64_t *ring, uint32_t cap) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < cap; i += (size_t)gridDim.x * 256)
+        ring[i] = 0;
+}
+
+// One workgroup: every unfinished instance (in tile-list order) gets a place in the ring for
+// its tiles and a budget of epoch_chunks chunks; the tiles are written in tile-list order.
+__global__ __launch_bounds__(1024) void qg_queue_setup(InstDev *insts, int count,
+                                                       const uint32_t *order, const uint2 *tiles,
+                                                       uint32_t n_tiles, QueueDev *Q, uint32_t gen,
+                                                       uint32_t epoch_chunks) {
+    __shared__ uint32_t scan[1024];
+    __shared__ uint32_t s_base, s_live;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        s_base = 0;
+        s_live = 0;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < count; c0 += 1024) {
+        const int j = c0 + (int)tid;
+        InstDev *I = j < count ? insts + order[j] : nullptr;
+        const bool run = I && !ld_dev(&I->done);
+        const uint32_t v = run ? I->ntiles : 0u;
+        scan[tid] = v;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {  // inclusive prefix sum
+            const uint32_t add = tid >= d ? scan[tid - d] : 0u;
+            __syncthreads();
+            scan[tid] += add;
+            __syncthreads();
+        }
+        if (run) {
+            I->ring_off = s_base + scan[tid] - v;
+            st_dev(&I->arrived, 0u);
+            st_dev(&I->epoch_left, epoch_chunks);
+        }
+        const int nrun = __syncthreads_count(run);
+        if (tid == 0) {
+            s_base += scan[1023];
+            s_live += (uint32_t)nrun;
+        }
+        __syncthreads();
+    }
+    for (uint32_t t = tid; t < n_tiles; t += 1024) {
+        const InstDev *I = insts + tiles[t].x;
+        if (!ld_dev(&I->done)) Q->ring[I->ring_off + (t - I->tile0)] = (uint64_t)gen << 32 | t;
+    }
+    if (tid == 0) {
+        st_dev(&Q->head, 0u);
+        st_dev(&Q->tail, s_base);
+        st_dev(&Q->live, s_live);
+        st_dev(&Q->active, s_live);
+        st_dev(&Q->error, 0u);
+        st_dev(&Q->finished, s_live == 0 ? 1u : 0u);
+    }
+}
+
+// Take the next ticket and wait for its slot: the tile index, or kNoItem once no push can reach
+// the ticket any more. A wait longer than Q->wait_limit wall-clock ticks (the host sets a
+// minute; a launch's chunks take seconds at most) can only come from a broken queue: the
+// workgroup then sets Q->error, which the host reports, and ends the launch.
+__device__ uint32_t queue_pop(QueueDev *Q, uint32_t gen) {
+    const uint32_t q = atomicAdd(&Q->head, 1u);
+    if (q >= Q->cap) return kNoItem;
+    const uint64_t t_start = wall_clock64();
+    for (;;) {
+        const uint64_t v =
+            __hip_atomic_load(&Q->ring[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == gen) return (uint32_t)v;
+        if (ld_dev(&Q->finished)) return kNoItem;
+        if (wall_clock64() - t_start > Q->wait_limit) {
+            st_dev(&Q->error, 1u);
+            st_dev(&Q->finished, 1u);
+            return kNoItem;
+        }
+        __builtin_amdgcn_s_sleep(32);  // about 2,000 clocks between polls
+    }
+}
+
+// The last tile of an instance's chunk [.., t1): advance the instance, end it at its budget or
+// (stop-on-first) once a ground state was seen, and reserve slots for its next chunk while it
+// may run more in this launch. Returns the first reserved slot, or kNoItem.
+__device__ uint32_t queue_decide(InstDev *I, QueueDev *Q, uint32_t t1) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every tile's hits
+    st_dev(&I->arrived, 0u);
+    st_dev(&I->t_cur, t1);
+    const bool stop = t1 >= I->t_stop || ((I->flags & XS_STOP_ON_FIRST) && ld_dev(&I->hit));
+    const uint32_t left = ld_dev(&I->epoch_left) - 1u;
+    st_dev(&I->epoch_left, left);
+    if (stop) {
+        st_dev(&I->done, 1u);
+        atomicSub(&Q->active, 1u);
+    }
+    uint32_t base = kNoItem;
+    if (!stop && left > 0) {
+        base = atomicAdd(&Q->tail, I->ntiles);
+        if (base + I->ntiles > Q->cap) {  // cannot happen with cap >= tiles x epoch_chunks
+            st_dev(&Q->error, 1u);
+            st_dev(&Q->finished, 1u);
+            base = kNoItem;
+        }
+    } else if (atomicSub(&Q->live, 1u) == 1u) {
+        st_dev(&Q->finished, 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // control fields before the slots
+    return base;
+}
+
+// The persistent kernel: `grid` workgroups serve tickets until the queue is finished. Each tile
+// runs with its instance's column width and record placement.
+template <int NT, bool MET>
+__global__ __launch_bounds__(NT) void qg_queue_run(InstDev *__restrict__ insts,
+                                                   const uint2 *__restrict__ tiles, QueueDev *Q,
+                                                   uint32_t gen) {
+    __shared__ uint32_t s_item, s_push;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_item = queue_pop(Q, gen);
+            // acquire for the whole workgroup (the barrier below passes it on): the pusher's
+            // control fields and the tile's state and first hits from its last chunk
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item == kNoItem) return;
+        const uint2 tile = tiles[item];
+        InstDev *I = insts + tile.x;
+        const uint32_t t0 = ld_dev(&I->t_cur);
+        const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
+        const bool gr = I->grec != nullptr;
+        if (I->col_bytes == 16) {
+            if (gr) tile_chunk<NT, 16, true, MET>(I, tile.y, t0, t1);
+            else tile_chunk<NT, 16, false, MET>(I, tile.y, t0, t1);
+        } else {
+            if (gr) tile_chunk<NT, 8, true, MET>(I, tile.y, t0, t1);
+            else tile_chunk<NT, 8, false, MET>(I, tile.y, t0, t1);
+        }
+        __syncthreads();  // every thread's stores of this tile done (workgroup scope)
+        if (threadIdx.x == 0) {
+            // release them to the device before the arrival
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            uint32_t push = kNoItem;
+            if (atomicAdd(&I->arrived, 1u) + 1u == I->ntiles) push = queue_decide(I, Q, t1);
+            s_push = push;
+        }
+        __syncthreads();
+        const uint32_t base = s_push;
+        if (base != kNoItem) {
+            const uint32_t n = I->ntiles, first = I->tile0;
+            for (uint32_t j = threadIdx.x; j < n; j += NT)
+                __hip_atomic_store(&Q->ring[base + j], (uint64_t)gen << 32 | (first + j),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();  // s_item and s_push are rewritten for the next ticket
+    }
 }
 
 // ------------------------------------------------------------------------------ final pass
@@ -786,6 +978,75 @@ hipError_t launch_final(InstDev *d_insts, int count, uint32_t max_words, uint32_
     hipLaunchKernelGGL(qg_winner, g_clones, dim3(256), 0, s, d_insts);
     hipLaunchKernelGGL(qg_gather, g_spins, dim3(256), 0, s, d_insts);
     return hipGetLastError();
+}
+
+hipError_t launch_queue_clear(uint64_t *ring, uint32_t cap, hipStream_t s) {
+    const uint32_t blocks = std::max(1u, std::min(1024u, (cap + 255) / 256));
+    hipLaunchKernelGGL(qg_queue_clear, dim3(blocks), dim3(256), 0, s, ring, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_queue_setup(InstDev *d_insts, int count, const uint32_t *d_order,
+                              const uint2 *d_tiles, uint32_t n_tiles, QueueDev *d_q,
+                              uint32_t gen, uint32_t epoch_chunks, hipStream_t s) {
+    hipLaunchKernelGGL(qg_queue_setup, dim3(1), dim3(1024), 0, s, d_insts, count, d_order,
+                       d_tiles, n_tiles, d_q, gen, epoch_chunks);
+    return hipGetLastError();
+}
+
+template <int NT, bool MET>
+hipError_t set_queue_lds_limit() {
+    static std::atomic<uint64_t> attr_set{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = uint64_t(1) << (dev & 63);
+    if (!(attr_set.load(std::memory_order_acquire) & bit)) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(qg_queue_run<NT, MET>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+        if (e != hipSuccess) return e;
+        attr_set.fetch_or(bit, std::memory_order_release);
+    }
+    return hipSuccess;
+}
+
+template <int NT, bool MET>
+hipError_t launch_queue_nt(InstDev *d_insts, const uint2 *d_tiles, QueueDev *d_q, uint32_t gen,
+                           size_t lds_bytes, int grid, hipStream_t s) {
+    hipError_t e = set_queue_lds_limit<NT, MET>();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((qg_queue_run<NT, MET>), dim3(grid), dim3(NT), lds_bytes, s, d_insts,
+                       d_tiles, d_q, gen);
+    return hipGetLastError();
+}
+
+hipError_t launch_queue_run(InstDev *d_insts, const uint2 *d_tiles, QueueDev *d_q, uint32_t gen,
+                            int threads, bool met, size_t lds_bytes, int grid, hipStream_t s) {
+    if (threads == 256)
+        return met ? launch_queue_nt<256, true>(d_insts, d_tiles, d_q, gen, lds_bytes, grid, s)
+                   : launch_queue_nt<256, false>(d_insts, d_tiles, d_q, gen, lds_bytes, grid, s);
+    if (threads == 512)
+        return met ? launch_queue_nt<512, true>(d_insts, d_tiles, d_q, gen, lds_bytes, grid, s)
+                   : launch_queue_nt<512, false>(d_insts, d_tiles, d_q, gen, lds_bytes, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template <int NT, bool MET>
+hipError_t queue_blocks_nt(size_t lds_bytes, int *blocks) {
+    hipError_t e = set_queue_lds_limit<NT, MET>();
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, reinterpret_cast<const void *>(qg_queue_run<NT, MET>), NT, lds_bytes);
+}
+
+hipError_t queue_blocks_per_cu(int threads, bool met, size_t lds_bytes, int *blocks) {
+    if (threads == 256)
+        return met ? queue_blocks_nt<256, true>(lds_bytes, blocks)
+                   : queue_blocks_nt<256, false>(lds_bytes, blocks);
+    if (threads == 512)
+        return met ? queue_blocks_nt<512, true>(lds_bytes, blocks)
+                   : queue_blocks_nt<512, false>(lds_bytes, blocks);
+    return hipErrorInvalidValue;
 }
 
 // Device scratch of xs_run_batch_noalloc: one array per device, held until the process ends,

@@ -139,14 +139,14 @@ struct xs_server {
             Request *r = pending.front();
             if (r->canceled) {
                 pending.pop_front();
-                complete(r, XS_ECANCELED, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0, 0});
+                complete(r, XS_ECANCELED, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0, 0, 0});
                 delete r;
                 continue;
             }
             if (cfg.max_resident && resident.size() >= cfg.max_resident) break;
             if (r->bytes > cfg.hbm_budget_bytes) {  // can never fit
                 pending.pop_front();
-                complete(r, XS_ENOMEM, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0, 0});
+                complete(r, XS_ENOMEM, xs_run_result{-1, -1, r->cfg.start_sweep, 0, 0, 0, 0, 0, 0, 0, 0});
                 delete r;
                 continue;
             }
@@ -203,7 +203,7 @@ struct xs_server {
                 continue;
             }
             xs_run_result res{-1, -1, r->desc.t_cur, r->desc.t_cur - r->desc.t_start, 0, 0, 0, 0,
-                              (uint64_t)r->desc.n_words * 64 * r->desc.n *
+                              0, (uint64_t)r->desc.n_words * 64 * r->desc.n *
                                   (r->desc.t_cur - r->desc.t_start),
                               0};
             release(r);

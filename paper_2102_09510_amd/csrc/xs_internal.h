@@ -40,6 +40,26 @@ struct InstDev {
     uint32_t col_bytes;   // task column width of this instance's launches (host side)
     uint32_t rec_global;  // records read from global memory (host side: selects the kernel)
     uint32_t thr0;        // w0 threshold: k = 0 spins flip iff the draw is below it (0: never)
+    // persistent work-queue launches (qg_persist)
+    uint32_t tile0, ntiles;  // this instance's tiles: tile list entries tile0 .. tile0 + ntiles - 1
+    uint32_t arrived;        // tiles that finished the current chunk
+    uint32_t epoch_left;     // chunks this instance may still run in the current launch
+    uint32_t ring_off;       // first ring slot of its tiles in the current launch (set-up only)
+};
+
+// Work queue of a persistent launch: tickets (head) are taken by workgroups, slots (tail) are
+// reserved by pushes; a slot holds (launch tag << 32) | tile index once published.
+struct QueueDev {
+    uint64_t *ring;     // [cap] slots (tag 0: never written)
+    uint32_t cap;       // slots: at least every push of one launch
+    uint32_t head;      // tickets taken
+    uint32_t tail;      // slots reserved
+    uint32_t live;      // instances still running chunks in this launch
+    uint32_t finished;  // set once live is 0 (nothing more is pushed) or a wait gave up
+    uint32_t error;     // set if a workgroup's wait for its slot reached the time limit
+    uint32_t active;    // instances not done (read by the host after each launch)
+    uint32_t pad;
+    uint64_t wait_limit;  // wall-clock ticks a workgroup waits for its slot before giving up
 };
 
 }  // namespace xs
@@ -60,6 +80,22 @@ hipError_t launch_decide(InstDev *d_insts, int count, uint32_t *d_active, hipStr
 hipError_t launch_final(InstDev *d_insts, int count, uint32_t max_words, uint32_t max_n,
                         hipStream_t s);
 size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, bool rec_global, bool met);
+// Persistent work-queue launches. A run clears the ring once (queue_clear); each launch then
+// runs a one-workgroup set-up (queue_setup: the tiles of every unfinished instance in tile-list
+// order, each instance allowed epoch_chunks chunks) and the persistent kernel (queue_run):
+// `grid` workgroups of `threads` threads pop tiles, run one chunk of each, and the last tile
+// of an instance's chunk decides (advance, end at the budget or the first ground state) and
+// pushes the instance's tiles again while it may run more chunks. Every instance's col_bytes
+// must be 8 or 16 and threads at least 8 * its tile_blocks; met as for launch_chunk.
+// d_order: instance indices in tile-list order; gen: tag of this launch (> 0, increasing).
+hipError_t launch_queue_clear(uint64_t *ring, uint32_t cap, hipStream_t s);
+hipError_t launch_queue_setup(InstDev *d_insts, int count, const uint32_t *d_order,
+                              const uint2 *d_tiles, uint32_t n_tiles, QueueDev *d_q,
+                              uint32_t gen, uint32_t epoch_chunks, hipStream_t s);
+hipError_t launch_queue_run(InstDev *d_insts, const uint2 *d_tiles, QueueDev *d_q, uint32_t gen,
+                            int threads, bool met, size_t lds_bytes, int grid, hipStream_t s);
+// Workgroups of the persistent kernel that fit on one CU at once.
+hipError_t queue_blocks_per_cu(int threads, bool met, size_t lds_bytes, int *blocks);
 // The no-allocation entry point's device scratch on the current device: its device address
 // (looked up once per device with hipGetSymbolAddress, with that device current) and size.
 hipError_t noalloc_scratch(uint8_t **ptr, size_t *bytes);

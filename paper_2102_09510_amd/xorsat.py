@@ -22,6 +22,7 @@ XS_STATUS_CODES = {v: k for k, v in XS_STATUS.items()}
 XS_STOP_ON_FIRST = 0x1
 XS_RESUME = 0x2
 XS_PLACE_ROWS = 0x4
+XS_PER_CHUNK = 0x8
 XS_MAX_N = 2048
 XS_CLONE_QUANTUM = 256
 XS_MAX_CLONES = 0x7FFFFF00
@@ -66,6 +67,7 @@ class RunResult(ctypes.Structure):
                 ("end_sweep", ctypes.c_uint32), ("sweeps_done", ctypes.c_uint32),
                 ("tile_blocks", ctypes.c_uint32), ("wg_threads", ctypes.c_uint32),
                 ("col_bytes", ctypes.c_uint32), ("rec_global", ctypes.c_uint32),
+                ("persistent", ctypes.c_uint32),
                 ("clone_spin_updates", ctypes.c_uint64), ("seconds", ctypes.c_double)]
 
 
@@ -251,6 +253,7 @@ class RunOutput:
     wg_threads: int
     col_bytes: int
     rec_global: int
+    persistent: int
     clone_spin_updates: int
     seconds: float
     state: object        # torch int64 [n][n_clones/64] on the device
@@ -263,12 +266,13 @@ def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: i
                 max_sweeps: int = 100000, stop_on_first: bool = True, resume: bool = False,
                 start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0,
                 wg_threads: int = 0, col_bytes: int = 0, rec_global: int = 0,
-                accept_thr0: int = 0, place_rows: bool = False) -> RunConfig:
+                accept_thr0: int = 0, place_rows: bool = False,
+                per_chunk: bool = False) -> RunConfig:
     """accept_thr0 > 0 selects the rule with w0 = accept_thr0 / 65536 (no ground-state
     tracking: first_hit marks only clones whose end configuration is a ground state).
     place_rows builds the LDS row placement even for a short run (speed only)."""
     flags = ((XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0) |
-             (XS_PLACE_ROWS if place_rows else 0))
+             (XS_PLACE_ROWS if place_rows else 0) | (XS_PER_CHUNK if per_chunk else 0))
     return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
                      accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks,
                      wg_threads, col_bytes, rec_global, accept_thr0, 0)
@@ -294,7 +298,8 @@ def _buffers(inst: Instance, cfg: RunConfig, state, want_energy: bool, device):
 def _output(res: RunResult, state, first_hit, energy, solved) -> RunOutput:
     return RunOutput(int(res.tts_sweeps), int(res.winner_clone), int(res.end_sweep),
                      int(res.sweeps_done), int(res.tile_blocks), int(res.wg_threads),
-                     int(res.col_bytes), int(res.rec_global), int(res.clone_spin_updates),
+                     int(res.col_bytes), int(res.rec_global), int(res.persistent),
+                     int(res.clone_spin_updates),
                      float(res.seconds), state, first_hit, energy,
                      solved if res.winner_clone >= 0 else None)
 

@@ -46,7 +46,7 @@ def test_header_constants_match_the_binding():
     text = open(os.path.join(ROOT, "include", "xorsat.h")).read()
     defs = {m.group(1): int(m.group(2), 0)
             for m in re.finditer(r"#define\s+(XS_[A-Z_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text)}
-    for name in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_MAX_N",
+    for name in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_PER_CHUNK", "XS_MAX_N",
                  "XS_CLONE_QUANTUM", "XS_MAX_CLONES", "XS_TUNE_MAX_TRIALS",
                  "XS_NOALLOC_SCRATCH_BYTES"):
         assert defs[name] == getattr(xorsat, name), name
@@ -55,8 +55,8 @@ def test_header_constants_match_the_binding():
     # The largest clone count is a whole number of quanta whose last index is below INT32_MAX.
     assert defs["XS_MAX_CLONES"] % defs["XS_CLONE_QUANTUM"] == 0
     assert defs["XS_MAX_CLONES"] - 1 < 2**31 - 1 < defs["XS_MAX_CLONES"] + defs["XS_CLONE_QUANTUM"]
-    flags = [defs[k] for k in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS")]
-    assert len(set(flags)) == 3 and all(f & (f - 1) == 0 for f in flags)
+    flags = [defs[k] for k in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_PER_CHUNK")]
+    assert len(set(flags)) == 4 and all(f & (f - 1) == 0 for f in flags)
     cfg = xorsat.make_config(n_clones=256, seed=1, stop_on_first=False, place_rows=True)
     assert cfg.flags == xorsat.XS_PLACE_ROWS
 

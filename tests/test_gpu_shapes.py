@@ -201,3 +201,50 @@ def test_uneven_batch_against_oracle_and_alone():
         if out.winner_clone >= 0:
             w = int(np.flatnonzero(clones == out.winner_clone)[0])
             assert np.array_equal(out.solved, ref["final_spins"][w])
+
+
+def test_persistent_queue_launch_equals_launch_per_chunk():
+    """The persistent work-queue launch (the default) and the launch-per-chunk loop
+    (XS_PER_CHUNK) on the same uneven batch: 24 instances, N from 32 to 2048, clone counts
+    from 4,096 to 65,536, mixed stop rules and chunk lengths, some instances solved in their
+    first chunks, one with no sweep budget; every buffer and result is equal, and sampled groups
+    equal the oracle."""
+    torch = _torch()
+    sizes = uneven_sizes(22, seed=4_000_999) + [(2048, 16384), (48, 4096)]
+    insts, hs, cfgs_q, cfgs_c = [], [], [], []
+    for k, (n, nc) in enumerate(sizes):
+        inst = planted_instance(n, 4_100_000 + k)
+        insts.append(inst)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        kw = dict(n_clones=nc, seed=0x9E + k, instance_id=k, accept_thr=THR_PAPER,
+                  max_sweeps=0 if k == 5 else 240, stop_on_first=(k % 3 != 0),
+                  chunk_sweeps=(40, 60, 100)[k % 3])
+        cfgs_q.append(xorsat.make_config(**kw))
+        cfgs_c.append(xorsat.make_config(per_chunk=True, **kw))
+    print("# queue launch vs launch per chunk: 24 instances", flush=True)
+    q = xorsat.run_batch(hs, cfgs_q)
+    c = xorsat.run_batch(hs, cfgs_c)
+    assert len({o.wg_threads for o in q}) == 1  # one workgroup size for the persistent launch
+    rng = np.random.default_rng(9)
+    for k, (a, b) in enumerate(zip(q, c)):
+        assert torch.equal(a.state, b.state), k
+        assert torch.equal(a.first_hit, b.first_hit), k
+        assert torch.equal(a.energy, b.energy), k
+        assert (a.tts_sweeps, a.winner_clone, a.end_sweep, a.sweeps_done) == \
+            (b.tts_sweeps, b.winner_clone, b.end_sweep, b.sweeps_done), k
+        assert (a.persistent, b.persistent) == (1, 0), k
+        if a.winner_clone >= 0:
+            assert np.array_equal(a.solved, b.solved), k
+    assert q[5].end_sweep == 0 and q[5].sweeps_done == 0
+    assert any(o.tts_sweeps >= 0 for o in q) and any(o.tts_sweeps < 0 for o in q)
+    for k in (0, 7, 22, 23):
+        inst, h, cfg, out = insts[k], hs[k], cfgs_q[k], q[k]
+        operm, _ = oracle.colour(inst.tri, h.colour_cap)
+        fh = out.first_hit.cpu().numpy()
+        check_run_reduction(fh, out.tts_sweeps, out.winner_clone)
+        groups = list(rng.choice(cfg.n_clones // 32, size=2, replace=False))
+        if out.winner_clone >= 0:
+            groups.append(out.winner_clone // 32)
+        clones = np.unique(group_sample(cfg.n_clones, groups))
+        check_clones(inst.tri, inst.J, operm, cfg, out.sweeps_done, clones, fh,
+                     out.energy.cpu().numpy(), out.state, what=f"queue instance {k}")
