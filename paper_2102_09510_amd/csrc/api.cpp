@@ -263,8 +263,10 @@ std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int
 // classes (a member of class c has no conflicting predecessor in c, so by induction its step is
 // at most c) and far fewer when the class cap, not a shared triplet, closed the classes; the
 // cap fits the steps to the threads of a launch. B > 0: the LDS rows are placed for tiles of B
-// blocks read in CW-byte columns.
-xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uint32_t CW) {
+// blocks read in CW-byte columns. j0: the records' coupling bits are 0 (runs in the gauge of
+// solve_gauge, where every coupling is +1).
+xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uint32_t CW,
+                             bool j0) {
     const int n = I.n;
     std::vector<int32_t> inc(3 * (size_t)n), deg(n, 0), pos(n), step(n, 0), fill;
     for (int t = 0; t < n; ++t)
@@ -309,7 +311,7 @@ xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uin
             int k = 0;
             for (int z = 0; z < 3; ++z)
                 if (I.tri[3 * t + z] != i) roles[7 * (size_t)i + 1 + 2 * q + k++] = I.tri[3 * t + z];
-            if (I.J[t] < 0) jbits[i] |= (uint16_t)(1u << q);
+            if (I.J[t] < 0 && !j0) jbits[i] |= (uint16_t)(1u << q);
         }
     }
     const RowModel model = row_model(B, CW);
@@ -327,6 +329,63 @@ xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uin
         r[7] = (uint16_t)(i | (jbits[i] << 13));
     }
     return hs;
+}
+
+// Gauge of an instance: bits g with g_a ^ g_b ^ g_c = [J_t = -1] for every triplet t = (a, b, c),
+// by Gaussian elimination over GF(2) (Section "The model and its energy landscape": a planted
+// instance, J_t = tau_a tau_b tau_c, is the gauge image of the ferromagnet). Flipping the spins
+// with g_i = 1 turns every coupling into +1 and leaves every k, and so every trajectory,
+// unchanged. False if no such g exists (some coupling stays -1 in every gauge).
+bool solve_gauge(const xs_instance &I, std::vector<uint8_t> &g) {
+    const int n = I.n, W = n / 64 + 1;  // n unknowns, right-hand side at bit n
+    std::vector<uint64_t> M((size_t)n * W, 0);
+    auto row = [&](int r) { return M.data() + (size_t)r * W; };
+    auto bit = [&](int r, int c) { return (row(r)[c >> 6] >> (c & 63)) & 1u; };
+    for (int t = 0; t < n; ++t) {
+        uint64_t *m = row(t);
+        for (int q = 0; q < 3; ++q) {
+            const int v = I.tri[3 * t + q];
+            m[v >> 6] ^= 1ull << (v & 63);
+        }
+        if (I.J[t] < 0) m[n >> 6] ^= 1ull << (n & 63);
+    }
+    std::vector<int> pivot;  // pivot column of each row of the echelon form
+    int rank = 0;
+    for (int c = 0; c < n && rank < n; ++c) {
+        int p = rank;
+        while (p < n && !bit(p, c)) ++p;
+        if (p == n) continue;
+        if (p != rank) std::swap_ranges(row(p), row(p) + W, row(rank));
+        const uint64_t *pr = row(rank);
+        for (int r = rank + 1; r < n; ++r)
+            if (bit(r, c)) {
+                uint64_t *m = row(r);
+                for (int w = c >> 6; w < W; ++w) m[w] ^= pr[w];
+            }
+        pivot.push_back(c);
+        ++rank;
+    }
+    for (int r = rank; r < n; ++r)
+        if (bit(r, n)) return false;  // 0 = 1: inconsistent
+    // Back substitution, free unknowns 0.
+    std::vector<uint64_t> x(W, 0);
+    for (int k = rank - 1; k >= 0; --k) {
+        const uint64_t *m = row(k);
+        uint64_t par = bit(k, n);
+        for (int w = 0; w < W; ++w) {
+            uint64_t v = m[w] & x[w];
+            if (w == (n >> 6)) v &= (1ull << (n & 63)) - 1;  // unknowns only
+            par ^= (uint64_t)__builtin_popcountll(v) & 1u;
+        }
+        // the pivot's own bit is still 0 in x, so par = rhs ^ (the other unknowns of the row)
+        if (par) x[pivot[k] >> 6] |= 1ull << (pivot[k] & 63);
+    }
+    g.assign(n, 0);
+    for (int i = 0; i < n; ++i) g[i] = (uint8_t)((x[i >> 6] >> (i & 63)) & 1u);
+    for (int t = 0; t < n; ++t)  // every coupling becomes +1
+        if ((g[I.tri[3 * t]] ^ g[I.tri[3 * t + 1]] ^ g[I.tri[3 * t + 2]]) != (I.J[t] < 0 ? 1 : 0))
+            return false;
+    return true;
 }
 
 // Triplets as the final pass reads them: a, b, c, and j = 1 for J = -1.
@@ -364,7 +423,9 @@ uint32_t step_cap(const xs::InstDev &d) {
 
 // Schedules are kept per (step cap, placement layout); caps stay below 2^16. Layout 0: rows not
 // placed; else tile blocks | column bytes << 8.
-uint32_t sched_key(uint32_t cap, uint32_t layout) { return cap | layout << 16; }
+uint32_t sched_key(uint32_t cap, uint32_t layout, bool j0 = false) {
+    return cap | layout << 16 | (j0 ? 1u << 31 : 0u);
+}
 uint32_t place_layout(uint32_t B, uint32_t CW) { return B < 8 ? B | CW << 8 : 0u; }
 
 // Clone-sweeps (clones x sweeps left) from which a run builds the row placement.
@@ -380,12 +441,13 @@ const xsh::HostSched &host_sched(const xs_instance *I, const xs::InstDev &d, uin
     // placed one already exists. Either gives the same results.
     const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
     if (layout && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
-        !I->sched.count(sched_key(cap, layout)))
+        !I->sched.count(sched_key(cap, layout, d.j0 != 0)))
         layout = 0;
-    const uint32_t key = sched_key(cap, layout);
+    const uint32_t key = sched_key(cap, layout, d.j0 != 0);
     auto hit = I->sched.find(key);
     if (hit == I->sched.end())
-        hit = I->sched.emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8)).first;
+        hit = I->sched.emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8, d.j0 != 0))
+                  .first;
     *key_out = key;
     return hit->second;
 }
@@ -434,6 +496,17 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
         d.step_off = ds.off;
         d.rowmap = ds.rowmap;
         d.n_steps = ds.steps;
+        d.gauge = nullptr;
+        if (d.j0) {
+            xsh::DeviceTables &dt = I->dev[device];
+            if (!dt.gauge) {
+                DevAlloc gb;
+                XS_HIP(hipMalloc(&gb.p, (size_t)I->n));
+                XS_HIP(hipMemcpy(gb.p, I->gauge.data(), (size_t)I->n, hipMemcpyHostToDevice));
+                dt.gauge = gb.release<uint8_t>();
+            }
+            d.gauge = dt.gauge;
+        }
         d.grec = nullptr;
         if (!d.rec_global) continue;
         auto it = ds.grec.find(d.tile_blocks);
@@ -729,6 +802,67 @@ xs_status tile_instances(std::vector<xs::InstDev> &h, const xs_run_config *cfgs,
     return XS_OK;
 }
 
+// Device scratch of the allocating entry points, kept for later calls: a small pool per device
+// of buffers that calls lease and give back once their stream has finished (idle() after the
+// final synchronisation). A call that fails before that frees its buffer instead (hipFree waits
+// for the device). The pool keeps at most kPoolKeep buffers per device and frees the smallest
+// beyond that; what it holds at exit is left to the process teardown.
+struct ScratchPool {
+    std::mutex mu;
+    std::map<int, std::vector<std::pair<size_t, uint8_t *>>> free;  // per device
+};
+ScratchPool g_pool;
+constexpr size_t kPoolKeep = 4;
+
+struct ScratchLease {
+    int device = -1;
+    size_t bytes = 0;
+    uint8_t *p = nullptr;
+    bool is_idle = false;
+    void idle() { is_idle = true; }
+    xs_status take(int dev, size_t need) {
+        device = dev;
+        {
+            std::lock_guard<std::mutex> lock(g_pool.mu);
+            auto &v = g_pool.free[dev];
+            size_t best = SIZE_MAX;
+            for (size_t k = 0; k < v.size(); ++k)
+                if (v[k].first >= need && (best == SIZE_MAX || v[k].first < v[best].first))
+                    best = k;
+            if (best != SIZE_MAX) {
+                bytes = v[best].first;
+                p = v[best].second;
+                v.erase(v.begin() + best);
+                return XS_OK;
+            }
+        }
+        bytes = std::max<size_t>(need, 1 << 16);
+        void *q = nullptr;
+        XS_HIP(hipMalloc(&q, bytes));
+        p = static_cast<uint8_t *>(q);
+        return XS_OK;
+    }
+    ~ScratchLease() {
+        if (!p) return;
+        if (!is_idle) {
+            (void)hipFree(p);
+            return;
+        }
+        std::vector<uint8_t *> drop;
+        {
+            std::lock_guard<std::mutex> lock(g_pool.mu);
+            auto &v = g_pool.free[device];
+            v.emplace_back(bytes, p);
+            while (v.size() > kPoolKeep) {
+                auto it = std::min_element(v.begin(), v.end());
+                drop.push_back(it->second);
+                v.erase(it);
+            }
+        }
+        for (uint8_t *q : drop) (void)hipFree(q);
+    }
+};
+
 // A batch run as persistent work-queue launches (qg_queue_run): one launch per epoch of up to
 // epoch_chunks chunks of every unfinished instance, instead of a launch per chunk and launch
 // shape.
@@ -748,8 +882,9 @@ struct QueuePlan {
 // instance with the most work; every descriptor then takes it (its step cap follows). The ring
 // takes 8 bytes per tile and chunk of an epoch, within ring_budget bytes. Leaves qp.on false
 // (launch per chunk) when the batch does not qualify.
-xs_status plan_queue(std::vector<xs::InstDev> &h_io, const xs_run_config *cfgs, int count,
-                     int device, size_t ring_budget, QueuePlan &qp) {
+xs_status plan_queue(std::vector<xs::InstDev> &h_io, const xs_instance *const *insts,
+                     const xs_run_config *cfgs, int count, int device, size_t ring_budget,
+                     QueuePlan &qp) {
     qp.on = false;
     std::vector<xs::InstDev> h = h_io;  // committed only if the batch runs from the queue
     const bool met = h[0].thr0 != 0;
@@ -831,6 +966,24 @@ xs_status plan_queue(std::vector<xs::InstDev> &h_io, const xs_run_config *cfgs, 
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) qp.tiles.push_back(make_uint2(k, b0));
         d.wg_threads = T;
     }
+    // Persistent launches run an instance whose tiles read their records from global memory
+    // in its gauge where one exists (every coupling +1, three fewer operations per task:
+    // measured 3-7 % faster at N = 512-1024; with records in LDS the gauged kernel measured
+    // slower, so those keep the couplings). Finding the gauge costs up to n^3/128 word
+    // operations, once per instance: done for n <= 512, for runs of 2^36 clone-spin updates or
+    // more, or with XS_PLACE_ROWS; otherwise a gauge found earlier is used.
+    for (int k = 0; k < count; ++k) {
+        const xs_instance *I = insts[k];
+        xs::InstDev &d = h[k];
+        if (!d.rec_global) continue;
+        std::lock_guard<std::mutex> lock(I->mu);
+        if (I->gauge_state == 0) {
+            const double upd = 64.0 * d.n_words * d.n * (double)(d.t_stop - d.t_cur);
+            if (I->n <= 512 || upd >= 68719476736.0 || (cfgs[k].flags & XS_PLACE_ROWS))
+                I->gauge_state = solve_gauge(*I, I->gauge) ? 1 : -1;
+        }
+        d.j0 = I->gauge_state == 1 ? 1u : 0u;
+    }
     qp.threads = T;
     qp.met = met;
     qp.lds = lds;
@@ -868,7 +1021,8 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     {
         xs_status st = tile_instances(h, cfgs, count, tiles, groups);
         if (st != XS_OK) return st;
-        st = plan_queue(h, cfgs, count, device, fixed ? opt.fixed_bytes / 2 : SIZE_MAX, qp);
+        st = plan_queue(h, insts, cfgs, count, device, fixed ? opt.fixed_bytes / 2 : SIZE_MAX,
+                        qp);
         if (st != XS_OK) return st;
         if (qp.on) tiles.swap(qp.tiles);
         if (!fixed) {
@@ -901,7 +1055,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     const size_t off_tables = a256(total);
     std::vector<uint8_t> image;
     struct TabOff {
-        size_t tri, rec, off, rowmap, grec;
+        size_t tri, rec, off, rowmap, grec, gauge;
         uint32_t steps;
     };
     std::vector<TabOff> tab_of(count);
@@ -931,6 +1085,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             o.rec = put(hs.rec.data(), 16 * n);
             o.off = put(hs.off.data(), sizeof(int32_t) * hs.off.size());
             o.rowmap = hs.rowmap.empty() ? SIZE_MAX : put(hs.rowmap.data(), 2 * n);
+            o.gauge = h[k].j0 ? put(I->gauge.data(), n) : SIZE_MAX;
             o.grec = SIZE_MAX;
             if (h[k].rec_global) {
                 const std::vector<uint32_t> g = grec_image(hs, I->n, h[k].tile_blocks);
@@ -946,11 +1101,12 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
                         total, opt.fixed_bytes);
     }
     uint8_t *scratch = opt.fixed;
-    if (!fixed) XS_HIP(hipMalloc(&scratch, total));
-    struct Free {
-        uint8_t *p;
-        ~Free() { if (p) (void)hipFree(p); }
-    } guard{fixed ? nullptr : scratch};
+    ScratchLease lease;
+    if (!fixed) {
+        const xs_status st = lease.take(device, total);
+        if (st != XS_OK) return st;
+        scratch = lease.p;
+    }
     for (int k = 0; k < count; ++k)
         h[k].solved = reinterpret_cast<int8_t *>(scratch + off_solved + solved_off[k]);
     if (fixed) {
@@ -964,6 +1120,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             d.rowmap = o.rowmap == SIZE_MAX ? nullptr
                                             : reinterpret_cast<const uint16_t *>(tb + o.rowmap);
             d.grec = o.grec == SIZE_MAX ? nullptr : reinterpret_cast<const uint4 *>(tb + o.grec);
+            d.gauge = o.gauge == SIZE_MAX ? nullptr : reinterpret_cast<const uint8_t *>(tb + o.gauge);
             d.n_steps = o.steps;
         }
         if (!image.empty())
@@ -993,6 +1150,11 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         XS_HIP(xs::launch_queue_clear(d_ring, ring_cap, stream));
     }
     for (int k = 0; k < count; ++k) XS_HIP(xs::launch_init(d_inst + k, h[k], stream));
+    // Instances run in their gauge hold the flipped state from here to the final pass.
+    uint64_t gauge_pieces = 0;
+    for (int k = 0; k < count; ++k)
+        if (h[k].j0) gauge_pieces = std::max<uint64_t>(gauge_pieces, (uint64_t)h[k].n * h[k].n_words / 2);
+    if (gauge_pieces) XS_HIP(xs::launch_gauge_flip(d_inst, count, gauge_pieces, stream));
 
     bool any_running = false;
     for (int k = 0; k < count; ++k) any_running |= !h[k].done;
@@ -1109,6 +1271,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             max_words = std::max(max_words, h[k].n_words);
             max_n = std::max(max_n, h[k].n);
         }
+        if (gauge_pieces) XS_HIP(xs::launch_gauge_flip(d_inst, count, gauge_pieces, stream));
         XS_HIP(xs::launch_final(d_inst, count, max_words, max_n, stream));
     }
     std::vector<xs::InstDev> out(count);
@@ -1119,6 +1282,7 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         XS_HIP(hipMemcpyAsync(solved.data(), scratch + off_solved, solved_bytes,
                               hipMemcpyDeviceToHost, stream));
     XS_HIP(hipStreamSynchronize(stream));
+    lease.idle();
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
     for (int k = 0; k < count; ++k) {
@@ -1205,7 +1369,7 @@ xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int
         partition(*I);
         build_triplets(*I);
         // uncapped steps, reported by get_info
-        I->sched.emplace(sched_key(0, 0), make_schedule(*I, 0, 0, 0));
+        I->sched.emplace(sched_key(0, 0), make_schedule(*I, 0, 0, 0, false));
         *out = I;
         return XS_OK;
     });
@@ -1218,6 +1382,7 @@ void xs_instance_destroy(xs_instance *I) {
     for (auto &kv : I->dev) {
         (void)hipSetDevice(kv.first);
         (void)hipFree(kv.second.tri);
+        (void)hipFree(kv.second.gauge);
         for (auto &s : kv.second.sched) {
             (void)hipFree(s.second.rec);
             (void)hipFree(s.second.off);
@@ -1261,7 +1426,7 @@ xs_status xs_instance_get_schedule(const xs_instance *I, uint32_t step_cap, int3
         const uint32_t cap = std::min<uint32_t>(step_cap, 0xFFFFu);  // at least n: no limit
         auto it = I->sched.find(sched_key(cap, 0));
         if (it == I->sched.end())
-            it = I->sched.emplace(sched_key(cap, 0), make_schedule(*I, cap, 0, 0)).first;
+            it = I->sched.emplace(sched_key(cap, 0), make_schedule(*I, cap, 0, 0, false)).first;
         const xsh::HostSched &hs = it->second;
         std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
         std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());

@@ -293,7 +293,7 @@ __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t 
 
 // One task: the spin whose record is r, this thread's column; ra is the absolute LDS address of
 // the acceptance entry of the spin's position and the column's block.
-template <int CW, bool kAcc, bool MET>
+template <int CW, bool kAcc, bool MET, bool J0>
 __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
                                             uint32_t (&acc)[CW / 4]) {
     constexpr int G = CW / 4;
@@ -306,10 +306,11 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
     col_load<CW>(T.colbase + (r.z & 0xFFFFu), b2);
     col_load<CW>(T.colbase + (r.z >> 16), a3);
     col_load<CW>(T.colbase + (r.w & 0xFFFFu), b3);
+    // J0: every coupling is +1 in the tile's gauge, so the records carry no coupling bits
     const uint32_t meta = r.w >> 16;
-    const uint32_t j1 = 0u - ((meta >> 13) & 1u);
-    const uint32_t j2 = 0u - ((meta >> 14) & 1u);
-    const uint32_t j3 = 0u - (meta >> 15);
+    const uint32_t j1 = J0 ? 0u : 0u - ((meta >> 13) & 1u);
+    const uint32_t j2 = J0 ? 0u : 0u - ((meta >> 14) & 1u);
+    const uint32_t j3 = J0 ? 0u : 0u - (meta >> 15);
     // rb_shift is a multiple of G, so the column's G bits stay inside their byte
     if constexpr (MET) {
         const uint32_t v = *(const LDS_AS uint16_t *)(uintptr_t)ra;
@@ -332,7 +333,7 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
 // The steps of one sweep, a barrier before each (the first one also publishes the sweep's
 // acceptance bits and the previous sweep's last writes). Records and step bounds are
 // read-only, so each thread fetches its first record of a step before that step's barrier.
-template <int NT, int CW, bool GR, bool kAcc, bool MET = false>
+template <int NT, int CW, bool GR, bool kAcc, bool MET, bool J0>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
     constexpr uint32_t E = MET ? 2 : 1;  // bytes per acceptance entry
     // Step bounds are uniform and read-only: scalar loads of the step table.
@@ -346,12 +347,12 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
         const uint32_t ce_next = c + 1 < T.nsteps ? (uint32_t)so[c + 2] : ce;
         __syncthreads();
         const uint32_t ra = (T.lds0 + rb + E * (cs << T.lB)) + E * T.rbo;
-        if (T.tid < ntask) update_task<CW, kAcc, MET>(T, r0, ra, acc);
+        if (T.tid < ntask) update_task<CW, kAcc, MET, J0>(T, r0, ra, acc);
         // further rounds of the step (more tasks than threads): a uniform trip count
         const uint32_t rounds = (ntask - 1) / NT;
         for (uint32_t k = 1; k <= rounds; ++k)
             if (T.tid + k * NT < ntask)
-                update_task<CW, kAcc, MET>(T, rec_at<GR>(T, cs + T.tpos + k * stride),
+                update_task<CW, kAcc, MET, J0>(T, rec_at<GR>(T, cs + T.tpos + k * stride),
                                            ra + E * ((k * stride) << T.lB), acc);
         cs = ce;
         ce = ce_next;
@@ -360,7 +361,7 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
 
 // k >= 1 for any visited spin, over every spin of the current LDS state (no update): a zero
 // bit marks a clone whose configuration is a ground state.
-template <int NT, int CW, bool GR>
+template <int NT, int CW, bool GR, bool J0>
 __device__ __forceinline__ void unsat_any(const Tile &T, uint32_t (&acc)[CW / 4]) {
     constexpr int G = CW / 4;
     for (uint32_t q = T.tid; q < T.n << T.lcol; q += NT) {
@@ -374,9 +375,9 @@ __device__ __forceinline__ void unsat_any(const Tile &T, uint32_t (&acc)[CW / 4]
         col_load<CW>(T.colbase + (r.z >> 16), a3);
         col_load<CW>(T.colbase + (r.w & 0xFFFFu), b3);
         const uint32_t meta = r.w >> 16;
-        const uint32_t j1 = 0u - ((meta >> 13) & 1u);
-        const uint32_t j2 = 0u - ((meta >> 14) & 1u);
-        const uint32_t j3 = 0u - (meta >> 15);
+        const uint32_t j1 = J0 ? 0u : 0u - ((meta >> 13) & 1u);
+        const uint32_t j2 = J0 ? 0u : 0u - ((meta >> 14) & 1u);
+        const uint32_t j3 = J0 ? 0u : 0u - (meta >> 15);
 #pragma unroll
         for (int g = 0; g < G; ++g)
             qg_word<true>(x[g], a1[g], b1[g], a2[g], b2[g], a3[g], b3[g], j1, j2, j3, 0u, acc[g]);
@@ -416,11 +417,11 @@ __device__ __forceinline__ uint32_t record_hits(const Tile &T, uint32_t t, uint3
 
 // Ground-state check of the current LDS state, recording hits at sweep t. Returns nonzero in
 // every thread if some clone of the tile got a new hit. Ends synchronised.
-template <int NT, int CW, bool GR>
+template <int NT, int CW, bool GR, bool J0>
 __device__ __forceinline__ uint32_t check_state(const Tile &T, uint32_t t, uint32_t &hm) {
     uint32_t acc[CW / 4] = {};
     __syncthreads();  // state final, accumulators clear
-    unsat_any<NT, CW, GR>(T, acc);
+    unsat_any<NT, CW, GR, J0>(T, acc);
     reduce_acc<CW>(T, acc);
     if (T.tid == 0) lds_u32(T.flag) = 0;
     __syncthreads();
@@ -479,7 +480,7 @@ __device__ __forceinline__ void st_dev(uint32_t *p, uint32_t v) {
 //
 // MET (w0 > 0): a ground state can be left again, so no sweep is tested; the final pass tests
 // the end configuration only.
-template <int NT, int CW, bool GR, bool MET>
+template <int NT, int CW, bool GR, bool MET, bool J0>
 __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t0, uint32_t t1) {
     constexpr int G = CW / 4;        // groups per column
     constexpr int LG = G == 4 ? 2 : G == 2 ? 1 : 0;
@@ -541,7 +542,7 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
         __syncthreads();  // records and state visible to every thread
         accept_bits<NT, GR, true>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
-            sweep<NT, CW, GR, false, true>(T, (t & 1) ? T.rb1 : T.rb0, none);
+            sweep<NT, CW, GR, false, true, J0>(T, (t & 1) ? T.rb1 : T.rb0, none);
             if (t + 1 < t1) accept_bits<NT, GR, true>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
         __syncthreads();
@@ -556,7 +557,7 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
         lds_u32(T.acc + 4 * T.tid) = 0;
     }
     __syncthreads();  // records, state and accumulators visible to every thread
-    if (t0 == I->t_start) check_state<NT, CW, GR>(T, t0, hm);  // the run's start configuration
+    if (t0 == I->t_start) check_state<NT, CW, GR, J0>(T, t0, hm);  // the run's start configuration
 
     if (ld_dev(&I->track)) {
         // This instance keeps producing new ground-state clones: test every sweep.
@@ -564,22 +565,22 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
         accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
             uint32_t acc[G] = {};
-            sweep<NT, CW, GR, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+            sweep<NT, CW, GR, true, false, J0>(T, (t & 1) ? T.rb1 : T.rb0, acc);
             reduce_acc<CW>(T, acc);
             __syncthreads();
             if (T.tid < T.ngrp) record_hits(T, t, hm_t);
             if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
         hm = hm_t;
-        check_state<NT, CW, GR>(T, t1, hm);
+        check_state<NT, CW, GR, J0>(T, t1, hm);
     } else {
         uint32_t none[G] = {};  // unused: this loop tracks no ground states
         accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
         for (uint32_t t = t0; t < t1; ++t) {
-            sweep<NT, CW, GR, false>(T, (t & 1) ? T.rb1 : T.rb0, none);
+            sweep<NT, CW, GR, false, false, J0>(T, (t & 1) ? T.rb1 : T.rb0, none);
             if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
         }
-        if (check_state<NT, CW, GR>(T, t1, hm)) {
+        if (check_state<NT, CW, GR, J0>(T, t1, hm)) {
             // Replay from the chunk's start state with a per-sweep ground-state test.
             uint32_t hm_replay = 0;  // hits before this chunk; the end check's are redone
             if (T.tid < T.ngrp) {
@@ -592,7 +593,7 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
             accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
             for (uint32_t t = t0; t < t1; ++t) {
                 uint32_t acc[G] = {};
-                sweep<NT, CW, GR, true>(T, (t & 1) ? T.rb1 : T.rb0, acc);
+                sweep<NT, CW, GR, true, false, J0>(T, (t & 1) ? T.rb1 : T.rb0, acc);
                 reduce_acc<CW>(T, acc);
                 __syncthreads();
                 if (T.tid < T.ngrp) record_hits(T, t, hm_replay);
@@ -617,7 +618,7 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     const uint32_t t0 = ld_dev(&I->t_cur);
     const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
     if (t0 >= t1) return;
-    tile_chunk<NT, CW, GR, MET>(I, tile.y, t0, t1);
+    tile_chunk<NT, CW, GR, MET, false>(I, tile.y, t0, t1);
 }
 
 // ------------------------------------------------------------------------------ control
@@ -778,31 +779,40 @@ __global__ __launch_bounds__(NT) void qg_queue_run(InstDev *__restrict__ insts,
                                                    uint32_t gen) {
     __shared__ uint32_t s_item, s_push;
     for (;;) {
-        if (threadIdx.x == 0) {
-            s_item = queue_pop(Q, gen);
-            // acquire for the whole workgroup (the barrier below passes it on): the pusher's
-            // control fields and the tile's state and first hits from its last chunk
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
+        if (threadIdx.x == 0) s_item = queue_pop(Q, gen);
         __syncthreads();
         const uint32_t item = s_item;
         if (item == kNoItem) return;
+        // acquire, in every wave: the pusher's control fields and the tile's state and first
+        // hits from its last chunk (written by other workgroups, possibly on other XCDs)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const uint2 tile = tiles[item];
         InstDev *I = insts + tile.x;
         const uint32_t t0 = ld_dev(&I->t_cur);
         const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
-        const bool gr = I->grec != nullptr;
+        // the gauge is used with records in global memory only (the host sets it so)
+        const bool gr = I->grec != nullptr, j0 = I->gauge != nullptr;
         if (I->col_bytes == 16) {
-            if (gr) tile_chunk<NT, 16, true, MET>(I, tile.y, t0, t1);
-            else tile_chunk<NT, 16, false, MET>(I, tile.y, t0, t1);
+            if (gr) {
+                if (j0) tile_chunk<NT, 16, true, MET, true>(I, tile.y, t0, t1);
+                else tile_chunk<NT, 16, true, MET, false>(I, tile.y, t0, t1);
+            } else {
+                tile_chunk<NT, 16, false, MET, false>(I, tile.y, t0, t1);
+            }
         } else {
-            if (gr) tile_chunk<NT, 8, true, MET>(I, tile.y, t0, t1);
-            else tile_chunk<NT, 8, false, MET>(I, tile.y, t0, t1);
+            if (gr) {
+                if (j0) tile_chunk<NT, 8, true, MET, true>(I, tile.y, t0, t1);
+                else tile_chunk<NT, 8, true, MET, false>(I, tile.y, t0, t1);
+            } else {
+                tile_chunk<NT, 8, false, MET, false>(I, tile.y, t0, t1);
+            }
         }
-        __syncthreads();  // every thread's stores of this tile done (workgroup scope)
+        // Release this tile's state and first hits to the device before its arrival. Every
+        // wave fences its own stores: a wave's fence waits only for that wave's stores, and a
+        // workgroup barrier does not make other waves' stores complete.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
         if (threadIdx.x == 0) {
-            // release them to the device before the arrival
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             uint32_t push = kNoItem;
             if (atomicAdd(&I->arrived, 1u) + 1u == I->ntiles) push = queue_decide(I, Q, t1);
             s_push = push;
@@ -816,6 +826,26 @@ __global__ __launch_bounds__(NT) void qg_queue_run(InstDev *__restrict__ insts,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();  // s_item and s_push are rewritten for the next ticket
+    }
+}
+
+// ------------------------------------------------------------------------------ gauge
+
+// The state of instance I + blockIdx.y, if it runs in its gauge, flipped row by row where
+// g_i = 1: into the gauge before its chunks, back after them. One thread per 16 bytes.
+__global__ __launch_bounds__(256) void qg_gauge_flip(InstDev *I) {
+    I += blockIdx.y;
+    if (!I->gauge) return;
+    const uint32_t per_row = I->n_words >> 1;  // 16-byte pieces per row
+    const uint64_t total = (uint64_t)I->n * per_row;
+    const uint8_t *g = I->gauge;
+    for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; q < total;
+         q += (uint64_t)gridDim.x * 256) {
+        const uint32_t i = (uint32_t)(q / per_row);
+        if (!g[i]) continue;
+        uint64_t *w = I->state + (size_t)i * I->n_words + 2 * (q % per_row);
+        const uint4 v = gload16(w, 0);
+        gstore16(w, 0, make_uint4(~v.x, ~v.y, ~v.z, ~v.w));
     }
 }
 
@@ -977,6 +1007,14 @@ hipError_t launch_final(InstDev *d_insts, int count, uint32_t max_words, uint32_
     hipLaunchKernelGGL(qg_tts, g_clones, dim3(256), 0, s, d_insts);
     hipLaunchKernelGGL(qg_winner, g_clones, dim3(256), 0, s, d_insts);
     hipLaunchKernelGGL(qg_gather, g_spins, dim3(256), 0, s, d_insts);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_flip(InstDev *d_insts, int count, uint64_t max_pieces, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const uint32_t bx =
+        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(2048, (max_pieces + 255) / 256));
+    hipLaunchKernelGGL(qg_gauge_flip, dim3(bx, (uint32_t)count), dim3(256), 0, s, d_insts);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct DevSched {
 
 struct DeviceTables {
     uint2 *tri = nullptr;
+    uint8_t *gauge = nullptr;  // [n] gauge bits (0 or 1), uploaded on first use
     std::map<uint32_t, DevSched> sched;  // per (step cap, row slots)
 };
 
@@ -51,6 +52,10 @@ struct xs_instance {
     mutable std::map<uint32_t, xsh::HostSched> sched;  // per (step cap, row slots)
     std::vector<uint16_t> tri16;     // [n][4]: a, b, c, j
     int32_t max_class = 0;
+    // Gauge bits g (g_a ^ g_b ^ g_c = [J_t = -1] for every triplet), found on first use (under
+    // mu): state 0 = not tried, 1 = found, -1 = no such gauge (not every J_t can become +1).
+    mutable std::vector<uint8_t> gauge;
+    mutable int gauge_state = 0;
     mutable std::mutex mu;
     mutable std::map<int, xsh::DeviceTables> dev;  // per HIP device
 };

@@ -45,6 +45,11 @@ struct InstDev {
     uint32_t arrived;        // tiles that finished the current chunk
     uint32_t epoch_left;     // chunks this instance may still run in the current launch
     uint32_t ring_off;       // first ring slot of its tiles in the current launch (set-up only)
+    // Gauge (host decides j0 before the tables are attached; persistent launches only): with
+    // j0 = 1 the state holds x_i ^ g_i from the start of the chunks to their end (gauge[n] = g,
+    // 0 or 1) and every record's coupling bits are 0 (each J_t is +1 in that gauge).
+    const uint8_t *gauge;
+    uint32_t j0;
 };
 
 // Work queue of a persistent launch: tickets (head) are taken by workgroups, slots (tail) are
@@ -89,6 +94,10 @@ size_t chunk_lds_bytes(uint32_t n, uint32_t tile_blocks, bool rec_global, bool m
 // must be 8 or 16 and threads at least 8 * its tile_blocks; met as for launch_chunk.
 // d_order: instance indices in tile-list order; gen: tag of this launch (> 0, increasing).
 hipError_t launch_queue_clear(uint64_t *ring, uint32_t cap, hipStream_t s);
+// Flip the state rows with g_i = 1 of every descriptor that has a gauge table (count
+// consecutive descriptors; max_pieces bounds n * n_words / 2): the state enters its gauge
+// before the chunks of a persistent run and leaves it before the final pass.
+hipError_t launch_gauge_flip(InstDev *d_insts, int count, uint64_t max_pieces, hipStream_t s);
 hipError_t launch_queue_setup(InstDev *d_insts, int count, const uint32_t *d_order,
                               const uint2 *d_tiles, uint32_t n_tiles, QueueDev *d_q,
                               uint32_t gen, uint32_t epoch_chunks, hipStream_t s);
