@@ -55,8 +55,8 @@ HEADLINES = {
     "batched": dict(count=64, n=256, clones=65536, budget=50000, stop=True, config=2),
 }
 # HBM counter records per headline workload (FETCH_SIZE / WRITE_SIZE of the sweep kernel).
-TRAFFIC_RECORDS = {"steady": "qg_chunk_n1024x16_hbm_counters.json",
-                   "batched": "qg_chunk_n256x64_hbm_counters.json"}
+TRAFFIC_RECORDS = {"steady": "qg_queue_run_n1024x16_hbm_counters.json",
+                   "batched": "qg_queue_run_n256x64_hbm_counters.json"}
 
 
 def parse():
@@ -124,6 +124,8 @@ def parse():
     ap.add_argument("--p256-runs", type=int, default=32, help="paper256: runs per instance")
     ap.add_argument("--p256-cap", type=int, default=1000000,
                     help="paper256: sweep cap of every run")
+    ap.add_argument("--parts", default="batched,served,single",
+                    help="uneven: which of batched, served, single (one run at a time) to run")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
@@ -142,19 +144,20 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(args, wl, dims):
-    """HBM bytes per sweep launch from the committed FETCH_SIZE/WRITE_SIZE record of the
-    headline workload, if it was taken on the current kernel source and this workload's default
-    configuration; otherwise None."""
+def measured_traffic(args, wl, dims, updates_per_launch, kernel):
+    """HBM bytes per sweep launch: the committed FETCH_SIZE/WRITE_SIZE record of the headline
+    workload (HBM bytes per clone-spin update, from the scaled counters of whole launches)
+    times this launch's updates, if the record was taken on the current kernel source, the
+    same kernel and this workload's default configuration; otherwise None."""
     path = os.path.join(ROOT, "profiles", TRAFFIC_RECORDS[wl])
     H = HEADLINES[wl]
     if (not os.path.exists(path) or dims != (H["count"], H["n"], H["clones"]) or
             args.chunk != 100 or args.accept_thr0 or args.cap != 32):
         return None
     rec = json.load(open(path))
-    if kernel_source_sha256() != rec.get("kernel_source_sha256"):
+    if kernel_source_sha256() != rec.get("kernel_source_sha256") or rec.get("kernel") != kernel:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec["hbm_bytes_per_update"] * updates_per_launch
 
 
 def cpu_baseline(insts, args, target_s):
@@ -197,11 +200,13 @@ def pct(v, q):
 
 def workload_uneven(args, xorsat, torch):
     """512 planted instances of uneven N and clone count, each to its first ground state or
-    10^4 sweeps: one batched run, the server with every request queued at once, and one run
-    per instance in sequence. Results are bit-identical across the three (checked)."""
+    10^4 sweeps: one batched run (a first call, which also builds the schedules, then a warm
+    one), the server with every request queued at once, and one run per instance in sequence.
+    Results are bit-identical across the three (checked). --parts picks which run."""
     from paper_2102_09510_amd.instances import (THR_PAPER, gen_seed, planted_instance, run_seed,
                                                 uneven_sizes)
 
+    parts = set(args.parts.split(","))
     sizes = uneven_sizes(512)
     insts = [planted_instance(n, gen_seed(4, k)) for k, (n, _) in enumerate(sizes)]
     hs = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
@@ -210,70 +215,81 @@ def workload_uneven(args, xorsat, torch):
     def cfg(k):
         return xorsat.make_config(n_clones=sizes[k][1], seed=run_seed(4, k), instance_id=k,
                                   accept_thr=THR_PAPER, max_sweeps=budget, stop_on_first=True,
-                                  chunk_sweeps=args.chunk)
+                                  chunk_sweeps=args.chunk, per_chunk=args.per_chunk)
 
-    print(f"# uneven: {len(sizes)} instances, budget {budget}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch = xorsat.run_batch(hs, [cfg(k) for k in range(len(hs))], want_energy=False)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    upd = sum(o.clone_spin_updates for o in batch)
-    print(f"# batched run done in {t_batch:.2f} s", file=sys.stderr, flush=True)
-
-    srv = xorsat.Server(hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)))
-    t0 = time.perf_counter()
-    tickets = {srv.submit(hs[k], cfg(k), want_first_hit=False, want_energy=False): k
-               for k in range(len(hs))}
-    served = {}
-    while True:
-        active = srv.step()
+    print(f"# uneven: {len(sizes)} instances, budget {budget}, parts {sorted(parts)}",
+          file=sys.stderr, flush=True)
+    results = {}
+    out = {"metric": "clone-spin updates/ns and completion latency, uneven batch",
+           "config": {"workload": "512 planted instances, N uniform on {32..1024}, clones "
+                                  "uniform on {4096..65536}, to first ground state or "
+                                  f"{budget} sweeps"}}
+    upd = None
+    if "batched" in parts:
+        times = []
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            batch = xorsat.run_batch(hs, [cfg(k) for k in range(len(hs))], want_energy=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            print(f"# batched run {rep} done in {times[-1]:.2f} s", file=sys.stderr, flush=True)
+        upd = sum(o.clone_spin_updates for o in batch)
+        results["batched"] = batch
+        out["batched"] = {"seconds": round(times[1], 3),
+                          "updates_per_ns": round(upd / times[1] / 1e9, 1),
+                          "first_call_seconds": round(times[0], 3),
+                          "launch": "persistent work queue" if batch[0].persistent
+                          else "one per chunk",
+                          "completion_s_p50": round(times[1], 3),
+                          "completion_s_p99": round(times[1], 3)}
+    if "served" in parts:
+        srv = xorsat.Server(hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)))
+        t0 = time.perf_counter()
+        tickets = {srv.submit(hs[k], cfg(k), want_first_hit=False, want_energy=False): k
+                   for k in range(len(hs))}
+        served = {}
+        while True:
+            active = srv.step()
+            for c in srv.poll():
+                served[tickets[c.ticket]] = c
+            if active == 0:
+                break
         for c in srv.poll():
             served[tickets[c.ticket]] = c
-        if active == 0:
-            break
-    for c in srv.poll():
-        served[tickets[c.ticket]] = c
-    t_serve = time.perf_counter() - t0
-    srv.close()
-    print(f"# served run done in {t_serve:.2f} s", file=sys.stderr, flush=True)
-
-    single_done = []
-    t0 = time.perf_counter()
-    single = []
-    for k in range(len(hs)):
-        single.append(xorsat.run(hs[k], cfg(k), want_energy=False))
-        torch.cuda.synchronize()
-        single_done.append(time.perf_counter() - t0)
-    t_single = single_done[-1]
-    print(f"# one-at-a-time done in {t_single:.2f} s", file=sys.stderr, flush=True)
-    for k in range(len(hs)):
-        a, b, c = batch[k], served[k], single[k]
-        assert (a.tts_sweeps, a.winner_clone, a.end_sweep) == \
-            (b.tts_sweeps, b.winner_clone, b.end_sweep) == \
-            (c.tts_sweeps, c.winner_clone, c.end_sweep), k
-    tts = [o.tts_sweeps for o in batch if o.tts_sweeps >= 0]
-    lat_srv = [served[k].latency_s for k in range(len(hs))]
-    solved = [k for k in range(len(hs)) if batch[k].tts_sweeps >= 0]
-    return {"metric": "clone-spin updates/ns and completion latency, uneven batch",
-            "config": {"workload": "512 planted instances, N uniform on {32..1024}, clones "
-                                   "uniform on {4096..65536}, to first ground state or "
-                                   f"{budget} sweeps"},
-            "updates": upd,
-            "batched": {"seconds": round(t_batch, 3), "updates_per_ns": round(upd / t_batch / 1e9, 1)},
-            "served": {"seconds": round(t_serve, 3), "updates_per_ns": round(upd / t_serve / 1e9, 1),
-                       "latency_s_p50": pct(lat_srv, 50), "latency_s_p99": pct(lat_srv, 99),
-                       "solved_latency_s_p50": pct([lat_srv[k] for k in solved], 50),
-                       "solved_latency_s_p99": pct([lat_srv[k] for k in solved], 99)},
-            "one_at_a_time": {"seconds": round(t_single, 3),
-                              "updates_per_ns": round(upd / t_single / 1e9, 1),
-                              "latency_s_p50": pct(single_done, 50),
-                              "latency_s_p99": pct(single_done, 99),
-                              "solved_latency_s_p50": pct([single_done[k] for k in solved], 50),
-                              "solved_latency_s_p99": pct([single_done[k] for k in solved], 99)},
-            "tts_sweeps": {"solved": len(tts), "censored": len(hs) - len(tts),
-                           "p50": pct(tts, 50), "p99": pct(tts, 99)},
-            "identical_results": True}
+        t_serve = time.perf_counter() - t0
+        srv.close()
+        print(f"# served run done in {t_serve:.2f} s", file=sys.stderr, flush=True)
+        results["served"] = [served[k] for k in range(len(hs))]
+        upd_s = sum(c.clone_spin_updates for c in results["served"])
+        lat = [served[k].latency_s for k in range(len(hs))]
+        out["served"] = {"seconds": round(t_serve, 3),
+                         "updates_per_ns": round(upd_s / t_serve / 1e9, 1),
+                         "completion_s_p50": pct(lat, 50), "completion_s_p99": pct(lat, 99)}
+    if "single" in parts:
+        single_done, single = [], []
+        t0 = time.perf_counter()
+        for k in range(len(hs)):
+            single.append(xorsat.run(hs[k], cfg(k), want_energy=False))
+            torch.cuda.synchronize()
+            single_done.append(time.perf_counter() - t0)
+        t_single = single_done[-1]
+        print(f"# one-at-a-time done in {t_single:.2f} s", file=sys.stderr, flush=True)
+        results["single"] = single
+        upd_1 = sum(o.clone_spin_updates for o in single)
+        out["one_at_a_time"] = {"seconds": round(t_single, 3),
+                                "updates_per_ns": round(upd_1 / t_single / 1e9, 1),
+                                "completion_s_p50": pct(single_done, 50),
+                                "completion_s_p99": pct(single_done, 99)}
+    keys = {name: [(o.tts_sweeps, o.winner_clone, o.end_sweep) for o in res]
+            for name, res in results.items()}
+    assert len({tuple(v) for v in keys.values()}) <= 1, "results differ between parts"
+    first = next(iter(results.values()))
+    tts = [o.tts_sweeps for o in first if o.tts_sweeps >= 0]
+    out["tts_sweeps"] = {"solved": len(tts), "censored": len(hs) - len(tts),
+                         "p50": pct(tts, 50), "p99": pct(tts, 99)}
+    out["identical_results"] = len(results) > 1
+    return out
 
 
 def workload_serve(args, xorsat, torch):
@@ -848,7 +864,8 @@ def headline(args, xorsat, torch):
         "roofline": {"bound": "lds", "achieved": round(lds_tbs, 3),
                      "peak": round(LDS_PEAK_TBS, 2), "unit": "TB/s",
                      "frac": round(lds_tbs / LDS_PEAK_TBS, 4),
-                     "traffic": measured_traffic(args, wl, (count, n, clones)),
+                     "traffic": measured_traffic(args, wl, (count, n, clones), per_launch_updates,
+                                                 "qg_queue_run" if persistent else "qg_chunk"),
                      "bytes_per_update": ALGO_LDS_BYTES_PER_UPDATE,
                      "kernel": "qg_queue_run" if persistent else "qg_chunk",
                      "launches": round(full_launches, 2),

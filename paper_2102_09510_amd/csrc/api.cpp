@@ -946,6 +946,15 @@ xs_status plan_queue(std::vector<xs::InstDev> &h_io, const xs_instance *const *i
     uint32_t E = (uint32_t)std::max(1.0, std::min(64.0, 2.0 / (upd_chunk / 1e13 + 1e-12)));
     E = (uint32_t)std::min<size_t>(E, ring_budget / (8 * std::max<size_t>(n_tiles, 1)));
     if (E < 1 || n_tiles * E >= 0xFFFFFFFFull) return XS_OK;
+    // Epochs of equal length over the longest budget (100 chunks at most 11 per epoch: ten of
+    // ten, not nine of eleven and one of one).
+    uint64_t most_chunks = 1;
+    for (int k = 0; k < count; ++k)
+        if (!h[k].done)
+            most_chunks = std::max<uint64_t>(
+                most_chunks, (h[k].t_stop - h[k].t_cur + h[k].chunk - 1) / h[k].chunk);
+    const uint64_t epochs = (most_chunks + E - 1) / E;
+    E = (uint32_t)((most_chunks + epochs - 1) / epochs);
     int per_cu = 0, cus = 0;
     XS_HIP(xs::queue_blocks_per_cu((int)T, met, lds, &per_cu));
     XS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
