@@ -36,16 +36,15 @@ ALGO_LDS_BYTES_PER_UPDATE = 1.0
 # waves per CU reached 136 TB/s at 94 % LDS busy).
 LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
 # Secondary figure: VALU issue. 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s of
-# full-rate 32-bit VALU work. Algorithmic VALU instructions per clone-spin update: the rule and
-# the ground-state test take 9 three-input operations per 32-clone word; one Philox4x32-10 call
-# (10 rounds of 2 wide products and 2 three-input XORs) plus 8 threshold compares serve 8
-# groups = 256 clones: 9/32 + 48/256 = 0.469. The fraction below counts every one of them as a
-# full-rate operation (the rate of the 32x32->64 product is not measured here), so it is an
-# upper bound on VALU use.
+# full-rate 32-bit VALU work. Algorithmic VALU instructions per clone-spin update: the rule takes
+# 7 three-input operations per 32-clone word; one Philox4x32-10 call (10 rounds of 2 wide
+# products and 2 three-input XORs) plus 8 threshold compares serve 8 groups = 256 clones:
+# 7/32 + 48/256 = 0.406. The fraction below counts every one of them as a full-rate operation
+# (the rate of the 32x32->64 product is not measured here), so it is an upper bound on VALU use.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-ALGO_OPS_PER_UPDATE = 9 / 32 + (10 * (2 + 2) + 8) / 256
-# With w0 > 0 the rule also takes 9 operations per word (no ground-state test, one more
-# select) and every draw is compared with both thresholds.
+ALGO_OPS_PER_UPDATE = 7 / 32 + (10 * (2 + 2) + 8) / 256
+# With w0 > 0 the rule takes 9 operations per word and every draw is compared with both
+# thresholds.
 ALGO_OPS_PER_UPDATE_W0 = 9 / 32 + (10 * (2 + 2) + 16) / 256
 
 # Headline workloads: (instances, N, clones, default sweeps per step, stop at first ground
