@@ -1,7 +1,8 @@
 """GPU <-> oracle parity at the launch shapes the throughput numbers come from.
 
-* The batched N = 256 workload's kernel (tiles of eight 256-clone blocks, 512 threads, 16-byte
-  columns, records in LDS) inside a batch, over several chunks.
+* The batched N = 256 workload's kernel (tiles of four 256-clone blocks, 256 threads, 16-byte
+  columns, records in global memory, coupling gauge; and eight-block tiles with records in LDS)
+  inside a batch, over several chunks.
 * The steady-state N = 1024 workload's kernel (the library's default shape for 2^20 clones, rows
   placed), over several chunks.
 * An uneven batch of many instances (N from 32 to 1024, mixed clone counts, mixed stop rules),
@@ -87,11 +88,17 @@ def check_instance(inst, h, cfg, out, start_state, groups, what):
     return ref
 
 
-def test_batched_n256_timed_shape_resumed_near_solution():
+@pytest.mark.parametrize("shape", [(4, 256, 16, 1), (8, 512, 16, 2)],
+                         ids=["default-4blk-global-records-gauge", "8blk-lds-records"])
+def test_batched_n256_timed_shape_resumed_near_solution(shape):
     """The batched N = 256 workload's kernel: three instances of 65,536 clones in one batch with
-    tile_blocks = 8, wg_threads = 512, col_bytes = 16, records in LDS; 200 sweeps in chunks of 50
-    from sweep 1000 (budget runs) and a stop-on-first run that ends after its first chunk."""
+    the default shape (tile_blocks = 4, wg_threads = 256, col_bytes = 16, records in global
+    memory, so the persistent launch runs them in their coupling gauge), and with eight-block
+    tiles of 512 threads and records in LDS; 200 sweeps in chunks of 50 from sweep 1000 (budget
+    runs, the resumed states flipped into the gauge and back) and a stop-on-first run that ends
+    after its first chunk."""
     torch = _torch()
+    B, T, C, G = shape
     n, nc = 256, 65536  # tiles of 2,048 clones: 64 groups per tile, 32 tiles per instance
     rng = np.random.default_rng(256)
     insts, hs, cfgs, starts, picks = [], [], [], [], []
@@ -114,10 +121,12 @@ def test_batched_n256_timed_shape_resumed_near_solution():
         cfgs.append(xorsat.make_config(
             n_clones=nc, seed=0xC2 + k, instance_id=k, accept_thr=THR_PAPER, max_sweeps=200,
             start_sweep=1000, resume=True, stop_on_first=(k == 1), chunk_sweeps=50,
-            tile_blocks=8, wg_threads=512, col_bytes=16, rec_global=2))
+            tile_blocks=B, wg_threads=T, col_bytes=C, rec_global=G))
     outs = xorsat.run_batch(hs, cfgs, states=[torch.from_numpy(s.copy()).cuda() for s in starts])
     for k, out in enumerate(outs):
-        assert (out.tile_blocks, out.wg_threads, out.col_bytes, out.rec_global) == (8, 512, 16, 0)
+        assert (out.tile_blocks, out.wg_threads, out.col_bytes, out.rec_global) == \
+            (B, T, C, 1 if G == 1 else 0)
+        assert out.persistent == 1
         if k == 1:
             assert out.end_sweep == 1050 and out.tts_sweeps < 1050
         else:
