@@ -181,18 +181,19 @@ def test_chunk_length_changes_only_end_sweep():
 
 
 def test_graph_replay_equals_eager_launches():
-    """Untimed runs replay the chunk loop from a captured hipGraph (groups of up to 64 chunks,
-    replayed many times with host synchronisations between replays); timed runs launch every
-    chunk eagerly. Both give the same outputs, in a budget run and in a stop-on-first batch."""
+    """The launch-per-chunk loop (XS_PER_CHUNK): untimed runs replay it from a captured hipGraph
+    (groups of up to 64 chunks, replayed many times with host synchronisations between
+    replays); timed runs launch every chunk eagerly. Both give the same outputs, in a budget run
+    and in a stop-on-first batch."""
     torch = _torch()
     inst = planted_instance(64, 4242)
     h = xorsat.Instance(inst.tri, inst.J)
     insts = [planted_instance(n, 4300 + n) for n in (40, 72, 96)]
     hs = [xorsat.Instance(i.tri, i.J) for i in insts]
     budget = xorsat.make_config(n_clones=4096, seed=5, instance_id=2, max_sweeps=12000,
-                                stop_on_first=False, chunk_sweeps=25)
+                                stop_on_first=False, chunk_sweeps=25, per_chunk=True)
     batch = [xorsat.make_config(n_clones=2048, seed=11 + k, instance_id=k, max_sweeps=60000,
-                                chunk_sweeps=10) for k in range(3)]
+                                chunk_sweeps=10, per_chunk=True) for k in range(3)]
     outs = {}
     for timed in (False, True):
         xorsat.profile_enable(timed)
@@ -202,6 +203,7 @@ def test_graph_replay_equals_eager_launches():
             xorsat.profile_enable(False)
     xorsat.profile_read(reset=True)  # leave no timing totals to later tests
     for a, b in zip(outs[False], outs[True]):
+        assert (a.persistent, b.persistent) == (0, 0)
         assert torch.equal(a.state, b.state)
         assert torch.equal(a.first_hit, b.first_hit)
         assert torch.equal(a.energy, b.energy)
