@@ -257,3 +257,47 @@ def test_persistent_queue_launch_equals_launch_per_chunk():
         clones = np.unique(group_sample(cfg.n_clones, groups))
         check_clones(inst.tri, inst.J, operm, cfg, out.sweeps_done, clones, fh,
                      out.energy.cpu().numpy(), out.state, what=f"queue instance {k}")
+
+
+def test_persistent_queue_over_several_epochs_and_timed():
+    """A run longer than one persistent launch (300 chunks of 10 sweeps: five epochs of 60
+    chunks) and a stop-on-first batch, each with launch timing on and off, against the
+    launch-per-chunk loop: all equal, and sampled clones equal the oracle."""
+    torch = _torch()
+    inst = planted_instance(96, 4_200_001)
+    h = xorsat.Instance(inst.tri, inst.J)
+    kw = dict(n_clones=4096, seed=0x51, instance_id=3, accept_thr=THR_PAPER, max_sweeps=3000,
+              stop_on_first=False, chunk_sweeps=10)
+    others = [planted_instance(n, 4_200_100 + n) for n in (40, 72, 200)]
+    ho = [xorsat.Instance(i.tri, i.J) for i in others]
+    kb = [dict(n_clones=8192, seed=0x61 + k, instance_id=k, max_sweeps=40000, chunk_sweeps=7)
+          for k in range(3)]
+    print("# queue over several epochs, timed and untimed", flush=True)
+    runs = {}
+    for name, per_chunk, timed in (("queue", False, False), ("queue-timed", False, True),
+                                   ("per-chunk", True, False)):
+        xorsat.profile_enable(timed)
+        try:
+            runs[name] = [xorsat.run(h, xorsat.make_config(per_chunk=per_chunk, **kw))] + \
+                xorsat.run_batch(ho, [xorsat.make_config(per_chunk=per_chunk, **c) for c in kb])
+        finally:
+            xorsat.profile_enable(False)
+    xorsat.profile_read(reset=True)
+    assert all(o.persistent == 1 for o in runs["queue"] + runs["queue-timed"])
+    assert all(o.persistent == 0 for o in runs["per-chunk"])
+    for name in ("queue-timed", "per-chunk"):
+        for a, b in zip(runs["queue"], runs[name]):
+            assert torch.equal(a.state, b.state), name
+            assert torch.equal(a.first_hit, b.first_hit), name
+            assert torch.equal(a.energy, b.energy), name
+            assert (a.tts_sweeps, a.winner_clone, a.end_sweep) == \
+                (b.tts_sweeps, b.winner_clone, b.end_sweep), name
+    out = runs["queue"][0]
+    assert out.end_sweep == 3000
+    operm, _ = oracle.colour(inst.tri, h.colour_cap)
+    cfg = xorsat.make_config(**kw)
+    clones = np.r_[0:32, 2048:2080, 4064:4096]
+    check_clones(inst.tri, inst.J, operm, cfg, out.sweeps_done, clones,
+                 out.first_hit.cpu().numpy(), out.energy.cpu().numpy(), out.state,
+                 what="several epochs")
+    assert all(o.tts_sweeps >= 0 for o in runs["queue"][1:3])  # N = 40, 72 solve
