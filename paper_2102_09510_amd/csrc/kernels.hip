@@ -172,8 +172,6 @@ __global__ __launch_bounds__(256) void qg_init(InstDev *I) {
 // keeps them all as ds_* instructions.
 extern __shared__ __align__(16) uint8_t xs_lds[];
 
-// Address space of read-only global data that uniform accesses load through the scalar cache.
-#define CONSTANT __attribute__((address_space(4)))
 // Global address space: loads through it are global_load (vector memory counter only), not
 // flat loads, which also count against the LDS counter and so make every LDS wait -- the one
 // before a step's barrier among them -- wait for them too.
@@ -206,6 +204,8 @@ struct Tile {
     uint32_t rb0, rb1;   // acceptance bytes, double-buffered by sweep parity
     uint32_t acc;        // per-group accumulators [8*B] (uint32)
     uint32_t flag;       // workgroup flag (uint32)
+    uint32_t stp;        // step bounds (u16, n_steps + 1 of them and the last again), staged
+                         // from the step table
     uint32_t meta;       // spin index of each position (u16): the low 13 bits of the record's
                          // meta half-word in LDS, or an array of the indices alone (GR)
     uint32_t colbase;    // st + this thread's column
@@ -336,16 +336,18 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
 template <int NT, int CW, bool GR, bool kAcc, bool MET, bool J0>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
     constexpr uint32_t E = MET ? 2 : 1;  // bytes per acceptance entry
-    // Step bounds are uniform and read-only: scalar loads of the step table.
-    const CONSTANT int32_t *so = (const CONSTANT int32_t *)T.step_off;
+    // Step bounds come from the tile's LDS copy of the step table, read (the same address in
+    // every lane) right after each barrier: an LDS read returns in order with the task's reads,
+    // where a scalar load would have to complete before the barrier.
+    const LDS_AS uint16_t *so = (const LDS_AS uint16_t *)(uintptr_t)(T.lds0 + T.stp);
     const uint32_t stride = NT >> T.lcol;  // positions between a thread's tasks of one step
-    uint32_t cs = 0, ce = (uint32_t)so[1];
+    uint32_t cs = 0, ce = so[1];
     for (uint32_t c = 0; c < T.nsteps; ++c) {
         const uint32_t ntask = (ce - cs) << T.lcol;
         uint4 r0;  // read only by threads with a task
         if (T.tid < ntask) r0 = rec_at<GR>(T, cs + T.tpos);
-        const uint32_t ce_next = c + 1 < T.nsteps ? (uint32_t)so[c + 2] : ce;
         __syncthreads();
+        const uint32_t ce_next = so[c + 2];  // the table repeats its last bound once
         const uint32_t ra = (T.lds0 + rb + E * (cs << T.lB)) + E * T.rbo;
         if (T.tid < ntask) update_task<CW, kAcc, MET, J0>(T, r0, ra, acc);
         // further rounds of the step (more tasks than threads): a uniform trip count
@@ -355,7 +357,7 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
                 update_task<CW, kAcc, MET, J0>(T, rec_at<GR>(T, cs + T.tpos + k * stride),
                                            ra + E * ((k * stride) << T.lB), acc);
         cs = ce;
-        ce = ce_next;
+        ce = __builtin_amdgcn_readfirstlane(ce_next);  // uniform: taken where first needed
     }
 }
 
@@ -507,6 +509,7 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
     T.acc = T.rb1 + rbb;
     T.flag = T.acc + 4 * T.ngrp;
     T.meta = GR ? T.flag + 16 : 14u;  // GR: after the flag; else the top half of each record's w
+    T.stp = T.flag + 16 + (GR ? (uint32_t)align16(2 * (size_t)T.n) : 0u);
     T.colbase = T.st + T.col * CW;
     T.rb_sel = (T.col << LG) >> 3;
     T.rb_shift = (T.col << LG) & 7;
@@ -522,6 +525,10 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
     T.nsteps = I->n_steps;
 
     // Records: LDS rows -> byte offsets of the rows in this tile (GR: done by the host).
+    // Step bounds into LDS (at most n + 1 of them), the last one repeated once.
+    for (uint32_t c = T.tid; c <= T.nsteps + 1; c += NT)
+        *reinterpret_cast<uint16_t *>(xs_lds + T.stp + 2 * c) =
+            (uint16_t)((const GLOBAL_AS int32_t *)T.step_off)[min(c, T.nsteps)];
     // GR: the spin index of every position (for the acceptance pass) into its own LDS array.
     for (uint32_t p = T.tid; GR && p < T.n; p += NT)
         *reinterpret_cast<uint16_t *>(xs_lds + T.meta + 2 * p) =
@@ -918,7 +925,8 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 
 size_t chunk_lds_bytes(uint32_t n, uint32_t B, bool rec_global, bool met) {
     return (rec_global ? align16(2 * (size_t)n) : lds_rec_bytes(n)) + (size_t)n * B * 32 +
-           2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16;
+           2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16 +
+           align16(2 * ((size_t)n + 2));
 }
 
 hipError_t launch_init(InstDev *d_inst, const InstDev &h, hipStream_t s) {
