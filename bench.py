@@ -287,7 +287,7 @@ def workload_uneven(args, xorsat, torch):
     tts = [o.tts_sweeps for o in first if o.tts_sweeps >= 0]
     out["tts_sweeps"] = {"solved": len(tts), "censored": len(hs) - len(tts),
                          "p50": pct(tts, 50), "p99": pct(tts, 99)}
-    out["identical_results"] = len(results) > 1
+    out["identical_results"] = True if len(results) > 1 else None  # None: one part, nothing to compare
     return out
 
 
