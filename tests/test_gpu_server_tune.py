@@ -175,6 +175,8 @@ def test_server_back_pressure():
 
 
 def test_autotune_is_result_neutral():
+    """A tuned batch runs the tuned launch knobs, equals the same batch at fixed knobs bit for
+    bit, and every clone of two of its runs equals the oracle."""
     torch = _torch()
     inst = planted_instance(128, 17)
     h = xorsat.Instance(inst.tri, inst.J)
@@ -189,6 +191,15 @@ def test_autotune_is_result_neutral():
         assert all((o.tile_blocks, o.wg_threads, o.col_bytes) ==
                    (res["tile_blocks"], res["wg_threads"], res["col_bytes"]) for o in tuned)
         assert all(o.rec_global == (res["rec_global"] == 1) for o in tuned)
+        perm, _ = h.partition()
+        operm, _ = oracle.colour(inst.tri, h.colour_cap)
+        assert np.array_equal(perm, operm)
+        for k in (0, 3):
+            o = tuned[k]
+            check_run_reduction(o.first_hit.cpu().numpy(), o.tts_sweeps, o.winner_clone)
+            check_clones(inst.tri, inst.J, operm, cfgs[k], o.sweeps_done, np.arange(8192),
+                         o.first_hit.cpu().numpy(), o.energy.cpu().numpy(), o.state,
+                         what=f"tuned run {k}")
         for k, c in enumerate(cfgs):
             c.tile_blocks, c.wg_threads, c.col_bytes, c.rec_global = 1, 64, 16, 2
         plain = xorsat.run_batch([h] * 4, cfgs)
