@@ -105,7 +105,7 @@ struct xs_server {
     std::vector<Request *> resident;
     std::deque<xs_server_completion> completed;
     xs_server_stats stats{};
-    uint8_t *scratch = nullptr;  // descriptors | tiles | active counter
+    uint8_t *scratch = nullptr;  // descriptors | tiles | active counter | finished descriptors
     size_t scratch_bytes = 0;
     DevicePool pool;             // the resident requests' device memory
 
@@ -233,11 +233,13 @@ struct xs_server {
             if (st != XS_OK) return st;
             const size_t off_tiles = align256(sizeof(xs::InstDev) * R);
             const size_t off_active = off_tiles + align256(sizeof(uint2) * tiles.size());
-            st = ensure_scratch(off_active + 256);
+            const size_t off_fin = off_active + 256;
+            st = ensure_scratch(off_fin + align256(sizeof(xs::InstDev) * R));
             if (st != XS_OK) return st;
             xs::InstDev *d_inst = reinterpret_cast<xs::InstDev *>(scratch);
             uint2 *d_tiles = reinterpret_cast<uint2 *>(scratch + off_tiles);
             uint32_t *d_active = reinterpret_cast<uint32_t *>(scratch + off_active);
+            xs::InstDev *d_fin = reinterpret_cast<xs::InstDev *>(scratch + off_fin);
             XS_HIP(hipMemcpyAsync(d_inst, h.data(), sizeof(xs::InstDev) * R,
                                   hipMemcpyHostToDevice, stream));
             XS_HIP(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(uint2) * tiles.size(),
@@ -255,19 +257,31 @@ struct xs_server {
             XS_HIP(hipMemcpyAsync(h.data(), d_inst, sizeof(xs::InstDev) * R,
                                   hipMemcpyDeviceToHost, stream));
             XS_HIP(hipStreamSynchronize(stream));
-            bool any_done = false;
+            // The requests that ended in this chunk get their final pass (energies, TTS, winner,
+            // solved spins) together: their descriptors are gathered into one array, so one
+            // launch of each final kernel covers all of them, however many end at once.
+            std::vector<int> fin;
+            uint32_t fin_words = 0, fin_n = 0;
             for (int k = 0; k < R; ++k) {
                 stats.clone_spin_updates +=
                     (uint64_t)h[k].n_words * 64 * h[k].n * (h[k].t_cur - t_before[k]);
                 if (h[k].done) {
-                    XS_HIP(xs::launch_final(d_inst + k, 1, h[k].n_words, h[k].n, stream));
-                    any_done = true;
+                    fin.push_back(k);
+                    fin_words = std::max(fin_words, h[k].n_words);
+                    fin_n = std::max(fin_n, h[k].n);
                 }
             }
-            if (any_done) {
-                XS_HIP(hipMemcpyAsync(h.data(), d_inst, sizeof(xs::InstDev) * R,
+            if (!fin.empty()) {
+                const int F = (int)fin.size();
+                std::vector<xs::InstDev> hf(F);
+                for (int i = 0; i < F; ++i) hf[i] = h[fin[i]];
+                XS_HIP(hipMemcpyAsync(d_fin, hf.data(), sizeof(xs::InstDev) * F,
+                                      hipMemcpyHostToDevice, stream));
+                XS_HIP(xs::launch_final(d_fin, F, fin_words, fin_n, stream));
+                XS_HIP(hipMemcpyAsync(hf.data(), d_fin, sizeof(xs::InstDev) * F,
                                       hipMemcpyDeviceToHost, stream));
                 XS_HIP(hipStreamSynchronize(stream));
+                for (int i = 0; i < F; ++i) h[fin[i]] = hf[i];
             }
             std::vector<Request *> still;
             std::vector<std::pair<Request *, xs_run_result>> ended;
