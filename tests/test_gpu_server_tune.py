@@ -112,6 +112,46 @@ def test_server_results_equal_alone():
     srv.close()
 
 
+ENDING_TOGETHER = [  # (n, clones): mixed sizes, so the gathered final pass spans unlike grids
+    (48, 256), (96, 1024), (200, 4096), (512, 512), (1024, 2048), (2048, 16384), (33, 768),
+    (64, 1024), (300, 8192), (128, 256), (1500, 1024), (80, 2048),
+]
+
+
+def test_server_requests_ending_in_the_same_step():
+    """Twelve requests of unlike N and clone count with the same budget and chunk, submitted
+    together, end in the same step and share one final pass: each equals its run alone bit for
+    bit and the oracle on sampled clones."""
+    _torch()
+    made = []
+    for k, (n, nc) in enumerate(ENDING_TOGETHER):
+        inst = planted_instance(n, 8100 + k)
+        h = xorsat.Instance(inst.tri, inst.J)
+        cfg = xorsat.make_config(n_clones=nc, seed=4400 + k, instance_id=k, max_sweeps=40,
+                                 stop_on_first=False, chunk_sweeps=20)
+        made.append((inst, h, cfg))
+    srv = xorsat.Server(hbm_budget_bytes=1 << 30)
+    tickets = {srv.submit(h, cfg, want_state=True): k for k, (_, h, cfg) in enumerate(made)}
+    per_step = []
+    for _ in range(10):
+        active = srv.step()
+        per_step.append(srv.poll())
+        if active == 0:
+            break
+    assert [len(p) for p in per_step] == [0, len(made)]
+    for c in per_step[-1]:
+        k = tickets[c.ticket]
+        inst, h, cfg = made[k]
+        assert c.status == 0 and c.end_sweep == 40
+        oracle_check_completion(k, c, inst, h, cfg)
+        out, st, fh, en = _alone(h, cfg)
+        assert (c.tts_sweeps, c.winner_clone) == (out.tts_sweeps, out.winner_clone), k
+        assert np.array_equal(c.outputs["state"], st), k
+        assert np.array_equal(c.outputs["first_hit"], fh), k
+        assert np.array_equal(c.outputs["energy"], en), k
+    srv.close()
+
+
 def test_server_admission_by_footprint_and_cancel():
     _torch()
     made = [_make(k, s) for k, s in enumerate(REQS[:3])]
