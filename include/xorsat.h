@@ -61,6 +61,10 @@ typedef int32_t xs_status;
                                  then a decision kernel) instead of the persistent work-queue
                                  launch; speed only. A batch runs per chunk if any of its
                                  configs sets it. */
+#define XS_ONE_SWEEP_STEPS 0x10u /* run every sweep on its own steps: no overlap of the end of
+                                 one sweep with the start of the next (which chunks without
+                                 ground-state tracking otherwise use where the schedule has
+                                 such a form); speed only, the results are identical. */
 
 typedef struct xs_instance xs_instance;
 
@@ -108,6 +112,16 @@ xs_status xs_instance_get_partition(const xs_instance *inst, int32_t *perm, int3
  * n + 1 entries. Host arrays owned by the caller. */
 xs_status xs_instance_get_schedule(const xs_instance *inst, uint32_t step_cap, int32_t *order,
                                    int32_t *step_off, int32_t *n_steps);
+/* The cross-sweep body of the schedule for steps of at most step_cap spins (1 .. 65535), which
+ * chunks without ground-state tracking run when records are read from global memory. Sweep t
+ * of spin j runs in step s(j) of iteration t + late[j], where s(j) is the step of j's position
+ * in order[n] (steps step_off[0 .. *n_steps]); iteration k runs its steps in order, and the
+ * iterations of a chunk [t0, t1) are t0 .. t1. Running them reproduces the sequential sweeps
+ * exactly (rules in the source of make_body). XS_ENOTFOUND if the instance has no body for
+ * this cap (its sweeps then run one after another). step_off needs room for n + 1 entries and
+ * late for n (0 or 1, per spin). Host arrays owned by the caller. */
+xs_status xs_instance_get_body(const xs_instance *inst, uint32_t step_cap, int32_t *order,
+                               int32_t *step_off, uint8_t *late, int32_t *n_steps);
 
 /*
  * Run configuration. The dynamics (Section "The quasi-greedy algorithm"): a sweep visits the
@@ -127,7 +141,8 @@ typedef struct {
     uint64_t seed;         /* Philox key */
     uint32_t n_clones;     /* > 0, multiple of XS_CLONE_QUANTUM, <= XS_MAX_CLONES */
     uint32_t accept_thr;   /* w1 threshold, 0 .. 65536 */
-    uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS | XS_PER_CHUNK */
+    uint32_t flags;        /* XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS | XS_PER_CHUNK |
+                              XS_ONE_SWEEP_STEPS */
     uint32_t max_sweeps;   /* sweep budget of this call (0 = only check the start state) */
     uint32_t start_sweep;  /* absolute index of the first sweep (for resumed runs) */
     uint32_t chunk_sweeps; /* sweeps between stop checks, K (0 = 100, as in the paper) */

@@ -253,6 +253,75 @@ std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int
     return row;
 }
 
+// Cross-sweep body. Successive sweeps may overlap: the update of spin j in sweep t runs at
+// step t * II + tau(j) of the run, for offsets tau(j) in [0, 2 II), i.e. in step tau(j) mod II
+// of iteration t + tau(j) div II (a "late" spin runs in the iteration after its sweep's). The
+// iterations then reproduce the sequential sweeps exactly when, for every two spins i and j
+// that share a triplet: (1) tau(i) < tau(j) if i comes before j in the update order (sweep t
+// of j reads sweep t of i); (2) tau(i) < II + tau(j) if i comes after j (sweep t + 1 of j reads
+// sweep t of i, and writes j only after sweep t of i has read it); (3) tau(i) != tau(j) mod II
+// (they never share a step); and (4) no step holds more than cap spins. Updates of one spin in
+// successive sweeps are II steps apart, and (1)-(2) order every pair of updates that touch a
+// common spin as the sequential sweeps do (pairs more than one sweep apart: |tau(i) - tau(j)| <
+// 2 II). tau comes from placing the updates of successive sweeps each as early as these rules
+// allow, into the first step with room (the single-sweep rule of make_schedule, across
+// sweeps): once every spin's step moves by the same II from one sweep to the next, and did so
+// the sweep before too, tau is that sweep's steps less their minimum. The result is checked
+// against (1)-(4) and kept only if II is below the single-sweep step count.
+bool make_body(const xs_instance &I, uint32_t cap, int plain_steps,
+               const std::vector<int32_t> &inc, const std::vector<int32_t> &pos,
+               std::vector<int32_t> &tau, int &ii) {
+    const int n = I.n;
+    constexpr int kSweeps = 12;
+    std::vector<int32_t> prev(n, -1), cur(n), prev2(n, -1), fill;
+    for (int t = 0; t < kSweeps; ++t) {
+        for (int p = 0; p < n; ++p) {
+            const int v = I.perm[p];
+            int s = prev[v] + 1;
+            for (int q = 0; q < 3; ++q) {
+                const int tr = inc[3 * v + q];
+                for (int z = 0; z < 3; ++z) {
+                    const int u = I.tri[3 * tr + z];
+                    if (u == v) continue;
+                    s = std::max(s, pos[u] < p ? cur[u] + 1 : prev[u] + 1);
+                }
+            }
+            while (cap && s < (int)fill.size() && fill[s] >= (int)cap) ++s;
+            if (s >= (int)fill.size()) fill.resize(s + 1, 0);
+            ++fill[s];
+            cur[v] = s;
+        }
+        if (t + 1 < kSweeps) {
+            prev2.swap(prev);
+            prev = cur;
+        }
+    }
+    // cur: last sweep, prev: the one before, prev2: the one before that
+    ii = cur[0] - prev[0];
+    for (int v = 0; v < n; ++v)
+        if (cur[v] - prev[v] != ii || prev[v] - prev2[v] != ii) return false;
+    if (ii <= 0 || ii >= plain_steps) return false;
+    const int base = *std::min_element(prev.begin(), prev.end());
+    tau.assign(n, 0);
+    std::vector<int32_t> width(ii, 0);
+    for (int v = 0; v < n; ++v) {
+        tau[v] = prev[v] - base;
+        if (tau[v] >= 2 * ii) return false;
+        if (++width[tau[v] % ii] > (int)cap && cap) return false;
+    }
+    for (int v = 0; v < n; ++v)
+        for (int q = 0; q < 3; ++q) {
+            const int tr = inc[3 * v + q];
+            for (int z = 0; z < 3; ++z) {
+                const int u = I.tri[3 * tr + z];
+                if (u == v) continue;
+                if (tau[u] % ii == tau[v] % ii) return false;
+                if (pos[u] < pos[v] ? !(tau[u] < tau[v]) : !(tau[u] < ii + tau[v])) return false;
+            }
+        }
+    return true;
+}
+
 // Execution schedule of the update order. The update of a spin reads its own value and those of
 // the spins it shares a triplet with, and writes only its own, so two updates commute unless
 // their spins share a triplet. Each spin is placed in a step after every earlier spin (in update
@@ -264,9 +333,10 @@ std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int
 // at most c) and far fewer when the class cap, not a shared triplet, closed the classes; the
 // cap fits the steps to the threads of a launch. B > 0: the LDS rows are placed for tiles of B
 // blocks read in CW-byte columns. j0: the records' coupling bits are 0 (runs in the gauge of
-// solve_gauge, where every coupling is +1).
+// solve_gauge, where every coupling is +1). body: also build the cross-sweep body (make_body)
+// where one exists; the rows are then placed for the body's steps, which untracked chunks run.
 xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uint32_t CW,
-                             bool j0) {
+                             bool j0, bool body) {
     const int n = I.n;
     std::vector<int32_t> inc(3 * (size_t)n), deg(n, 0), pos(n), step(n, 0), fill;
     for (int t = 0; t < n; ++t)
@@ -300,6 +370,21 @@ xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uin
     std::vector<int32_t> next(hs.off.begin(), hs.off.end() - 1);
     hs.order.assign(n, 0);
     for (int p = 0; p < n; ++p) hs.order[next[step[I.perm[p]]]++] = I.perm[p];
+    // The body: spins grouped by tau mod II (in update order within a step).
+    std::vector<int32_t> tau;
+    int ii = 0;
+    if (body && make_body(I, cap, steps, inc, pos, tau, ii)) {
+        std::vector<int32_t> bfill(ii, 0);
+        for (int v = 0; v < n; ++v) ++bfill[tau[v] % ii];
+        hs.boff.assign(ii + 1, 0);
+        for (int l = 0; l < ii; ++l) hs.boff[l + 1] = hs.boff[l] + bfill[l];
+        std::vector<int32_t> bnext(hs.boff.begin(), hs.boff.end() - 1);
+        hs.border.assign(n, 0);
+        for (int p = 0; p < n; ++p) {
+            const int v = I.perm[p];
+            hs.border[bnext[tau[v] % ii]++] = v;
+        }
+    }
     // Roles of every spin: itself, then for each of its three triplets (ascending triplet index)
     // the two other spins; and its coupling bits (bit q: triplet q has J = -1).
     std::vector<int32_t> roles(7 * (size_t)n);
@@ -315,19 +400,34 @@ xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uin
         }
     }
     const RowModel model = row_model(B, CW);
-    if (!model.sets.empty() && n >= 2 * (int)model.S) hs.rowmap = place_rows(hs, roles, n, model);
-    // Records in schedule order: the LDS rows of the spin and of its six partners, then
-    // meta = spin | coupling bits << 13.
-    hs.rec.assign(8 * (size_t)n, 0);
-    for (int p = 0; p < n; ++p) {
-        const int i = hs.order[p];
-        uint16_t *r = &hs.rec[8 * (size_t)p];
-        for (int k = 0; k < 7; ++k) {
-            const int32_t u = roles[7 * (size_t)i + k];
-            r[k] = hs.rowmap.empty() ? (uint16_t)u : hs.rowmap[u];
+    if (!model.sets.empty() && n >= 2 * (int)model.S) {
+        if (hs.border.empty()) {
+            hs.rowmap = place_rows(hs, roles, n, model);
+        } else {
+            xsh::HostSched view;  // the body's steps, which the hot loop runs
+            view.order = hs.border;
+            view.off = hs.boff;
+            hs.rowmap = place_rows(view, roles, n, model);
         }
-        r[7] = (uint16_t)(i | (jbits[i] << 13));
     }
+    // Records in schedule order: the LDS rows of the spin and of its six partners, then
+    // meta = spin | coupling bits << 13 (body records: | late << 12).
+    auto records = [&](const std::vector<int32_t> &order, std::vector<uint16_t> &rec,
+                       bool mark_late) {
+        rec.assign(8 * (size_t)n, 0);
+        for (int p = 0; p < n; ++p) {
+            const int i = order[p];
+            uint16_t *r = &rec[8 * (size_t)p];
+            for (int k = 0; k < 7; ++k) {
+                const int32_t u = roles[7 * (size_t)i + k];
+                r[k] = hs.rowmap.empty() ? (uint16_t)u : hs.rowmap[u];
+            }
+            const uint16_t late = mark_late && tau[i] >= ii ? 1u << 12 : 0u;
+            r[7] = (uint16_t)(i | late | (jbits[i] << 13));
+        }
+    };
+    records(hs.order, hs.rec, false);
+    if (!hs.border.empty()) records(hs.border, hs.brec, true);
     return hs;
 }
 
@@ -421,10 +521,17 @@ uint32_t step_cap(const xs::InstDev &d) {
     return d.wg_threads * d.col_bytes / (32u * d.tile_blocks);
 }
 
-// Schedules are kept per (step cap, placement layout); caps stay below 2^16. Layout 0: rows not
-// placed; else tile blocks | column bytes << 8.
-uint32_t sched_key(uint32_t cap, uint32_t layout, bool j0 = false) {
-    return cap | layout << 16 | (j0 ? 1u << 31 : 0u);
+// Schedules are kept per (step cap, placement layout, coupling gauge, body); caps stay below
+// 2^16. Layout 0: rows not placed; else tile blocks | column bytes << 8 (below bit 30).
+uint32_t sched_key(uint32_t cap, uint32_t layout, bool j0 = false, bool body = false) {
+    return cap | layout << 16 | (body ? 1u << 30 : 0u) | (j0 ? 1u << 31 : 0u);
+}
+
+// The cross-sweep body runs where records are read from global memory and w0 = 0 (ground
+// states are absorbing and chunks without tracking are checked at their end), unless the run
+// asks for one sweep at a time.
+bool wants_body(const xs::InstDev &d) {
+    return d.rec_global && d.thr0 == 0 && !(d.flags & XS_ONE_SWEEP_STEPS);
 }
 uint32_t place_layout(uint32_t B, uint32_t CW) { return B < 8 ? B | CW << 8 : 0u; }
 
@@ -439,14 +546,16 @@ const xsh::HostSched &host_sched(const xs_instance *I, const xs::InstDev &d, uin
     // The row placement costs a few µs of host time per spin and saves about 5 % of the
     // sweep time; a run too short to pay that back uses the unplaced schedule unless the
     // placed one already exists. Either gives the same results.
+    const bool body = wants_body(d);
     const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
     if (layout && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
-        !I->sched.count(sched_key(cap, layout, d.j0 != 0)))
+        !I->sched.count(sched_key(cap, layout, d.j0 != 0, body)))
         layout = 0;
-    const uint32_t key = sched_key(cap, layout, d.j0 != 0);
+    const uint32_t key = sched_key(cap, layout, d.j0 != 0, body);
     auto hit = I->sched.find(key);
     if (hit == I->sched.end())
-        hit = I->sched.emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8, d.j0 != 0))
+        hit = I->sched
+                  .emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8, d.j0 != 0, body))
                   .first;
     *key_out = key;
     return hit->second;
@@ -454,11 +563,11 @@ const xsh::HostSched &host_sched(const xs_instance *I, const xs::InstDev &d, uin
 
 // Records with the byte offsets of the rows in a tile of B blocks (32 * B bytes per row), as
 // the kernels that read records from global memory take them.
-std::vector<uint32_t> grec_image(const xsh::HostSched &hs, int n, uint32_t B) {
+std::vector<uint32_t> grec_image(const std::vector<uint16_t> &rec, int n, uint32_t B) {
     const uint32_t rowb = 32u * B;
     std::vector<uint32_t> g(4 * (size_t)n);
     for (int p = 0; p < n; ++p) {
-        const uint16_t *r = &hs.rec[8 * (size_t)p];
+        const uint16_t *r = &rec[8 * (size_t)p];
         g[4 * p + 0] = (r[0] * rowb) | ((r[1] * rowb) << 16);
         g[4 * p + 1] = (r[2] * rowb) | ((r[3] * rowb) << 16);
         g[4 * p + 2] = (r[4] * rowb) | ((r[5] * rowb) << 16);
@@ -511,13 +620,36 @@ xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *i
         if (!d.rec_global) continue;
         auto it = ds.grec.find(d.tile_blocks);
         if (it == ds.grec.end()) {
-            const std::vector<uint32_t> g = grec_image(hs, I->n, d.tile_blocks);
+            const std::vector<uint32_t> g = grec_image(hs.rec, I->n, d.tile_blocks);
             DevAlloc dp;
             XS_HIP(hipMalloc(&dp.p, 16 * (size_t)I->n));
             XS_HIP(hipMemcpy(dp.p, g.data(), 16 * (size_t)I->n, hipMemcpyHostToDevice));
             it = ds.grec.emplace(d.tile_blocks, dp.release<uint4>()).first;
         }
         d.grec = it->second;
+        d.bgrec = nullptr;
+        d.bstep_off = nullptr;
+        d.n_bsteps = 0;
+        if (hs.border.empty() || !wants_body(d)) continue;
+        if (!ds.boff) {
+            const size_t bytes = sizeof(int32_t) * hs.boff.size();
+            DevAlloc off;
+            XS_HIP(hipMalloc(&off.p, bytes));
+            XS_HIP(hipMemcpy(off.p, hs.boff.data(), bytes, hipMemcpyHostToDevice));
+            ds.boff = off.release<int32_t>();
+            ds.bsteps = (uint32_t)hs.boff.size() - 1;
+        }
+        auto bt = ds.bgrec.find(d.tile_blocks);
+        if (bt == ds.bgrec.end()) {
+            const std::vector<uint32_t> g = grec_image(hs.brec, I->n, d.tile_blocks);
+            DevAlloc dp;
+            XS_HIP(hipMalloc(&dp.p, 16 * (size_t)I->n));
+            XS_HIP(hipMemcpy(dp.p, g.data(), 16 * (size_t)I->n, hipMemcpyHostToDevice));
+            bt = ds.bgrec.emplace(d.tile_blocks, dp.release<uint4>()).first;
+        }
+        d.bgrec = bt->second;
+        d.bstep_off = ds.boff;
+        d.n_bsteps = ds.bsteps;
     }
     return XS_OK;
 }
@@ -572,7 +704,8 @@ xs_status validate_run(const xs_instance *I, const xs_run_config *cfg, const xs_
     if (cfg->accept_thr0 && (cfg->flags & XS_STOP_ON_FIRST))
         return fail(XS_EINVAL, "XS_STOP_ON_FIRST needs accept_thr0 = 0 (with w0 > 0 a ground "
                                "state is not absorbing and no sweep is tested)");
-    if (cfg->flags & ~(XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS | XS_PER_CHUNK))
+    if (cfg->flags &
+        ~(XS_STOP_ON_FIRST | XS_RESUME | XS_PLACE_ROWS | XS_PER_CHUNK | XS_ONE_SWEEP_STEPS))
         return fail(XS_EINVAL, "unknown flags 0x%x", cfg->flags);
     if ((uint64_t)cfg->start_sweep + cfg->max_sweeps >= 0xFFFFFFFFull)
         return fail(XS_EINVAL, "start_sweep + max_sweeps must stay below 2^32 - 1");
@@ -1066,8 +1199,8 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
     const size_t off_tables = a256(total);
     std::vector<uint8_t> image;
     struct TabOff {
-        size_t tri, rec, off, rowmap, grec, gauge;
-        uint32_t steps;
+        size_t tri, rec, off, rowmap, grec, gauge, boff, bgrec;
+        uint32_t steps, bsteps;
     };
     std::vector<TabOff> tab_of(count);
     if (fixed) {
@@ -1098,9 +1231,17 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             o.rowmap = hs.rowmap.empty() ? SIZE_MAX : put(hs.rowmap.data(), 2 * n);
             o.gauge = h[k].j0 ? put(I->gauge.data(), n) : SIZE_MAX;
             o.grec = SIZE_MAX;
+            o.boff = o.bgrec = SIZE_MAX;
+            o.bsteps = 0;
             if (h[k].rec_global) {
-                const std::vector<uint32_t> g = grec_image(hs, I->n, h[k].tile_blocks);
+                const std::vector<uint32_t> g = grec_image(hs.rec, I->n, h[k].tile_blocks);
                 o.grec = put(g.data(), 16 * n);
+                if (!hs.border.empty() && wants_body(h[k])) {
+                    const std::vector<uint32_t> gb = grec_image(hs.brec, I->n, h[k].tile_blocks);
+                    o.bgrec = put(gb.data(), 16 * n);
+                    o.boff = put(hs.boff.data(), sizeof(int32_t) * hs.boff.size());
+                    o.bsteps = (uint32_t)hs.boff.size() - 1;
+                }
             }
             o.steps = (uint32_t)hs.off.size() - 1;
         }
@@ -1133,6 +1274,10 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
             d.grec = o.grec == SIZE_MAX ? nullptr : reinterpret_cast<const uint4 *>(tb + o.grec);
             d.gauge = o.gauge == SIZE_MAX ? nullptr : reinterpret_cast<const uint8_t *>(tb + o.gauge);
             d.n_steps = o.steps;
+            d.bgrec = o.bgrec == SIZE_MAX ? nullptr : reinterpret_cast<const uint4 *>(tb + o.bgrec);
+            d.bstep_off =
+                o.boff == SIZE_MAX ? nullptr : reinterpret_cast<const int32_t *>(tb + o.boff);
+            d.n_bsteps = o.bsteps;
         }
         if (!image.empty())
             XS_HIP(hipMemcpyAsync(tb, image.data(), image.size(), hipMemcpyHostToDevice, stream));
@@ -1380,7 +1525,7 @@ xs_status xs_instance_create(int32_t n, int32_t m, const int32_t *tri, const int
         partition(*I);
         build_triplets(*I);
         // uncapped steps, reported by get_info
-        I->sched.emplace(sched_key(0, 0), make_schedule(*I, 0, 0, 0, false));
+        I->sched.emplace(sched_key(0, 0), make_schedule(*I, 0, 0, 0, false, false));
         *out = I;
         return XS_OK;
     });
@@ -1399,6 +1544,8 @@ void xs_instance_destroy(xs_instance *I) {
             (void)hipFree(s.second.off);
             (void)hipFree(s.second.rowmap);
             for (auto &g : s.second.grec) (void)hipFree(g.second);
+            (void)hipFree(s.second.boff);
+            for (auto &g : s.second.bgrec) (void)hipFree(g.second);
         }
     }
     if (cur >= 0 && !I->dev.empty()) (void)hipSetDevice(cur);
@@ -1437,11 +1584,32 @@ xs_status xs_instance_get_schedule(const xs_instance *I, uint32_t step_cap, int3
         const uint32_t cap = std::min<uint32_t>(step_cap, 0xFFFFu);  // at least n: no limit
         auto it = I->sched.find(sched_key(cap, 0));
         if (it == I->sched.end())
-            it = I->sched.emplace(sched_key(cap, 0), make_schedule(*I, cap, 0, 0, false)).first;
+            it = I->sched.emplace(sched_key(cap, 0), make_schedule(*I, cap, 0, 0, false, false)).first;
         const xsh::HostSched &hs = it->second;
         std::memcpy(order, hs.order.data(), sizeof(int32_t) * hs.order.size());
         std::memcpy(step_off, hs.off.data(), sizeof(int32_t) * hs.off.size());
         *n_steps = (int32_t)hs.off.size() - 1;
+        return XS_OK;
+    });
+}
+
+xs_status xs_instance_get_body(const xs_instance *I, uint32_t step_cap, int32_t *order,
+                               int32_t *step_off, uint8_t *late, int32_t *n_steps) {
+    return guarded([&]() -> xs_status {
+        if (!I || !order || !step_off || !late || !n_steps) return fail(XS_EINVAL, "null argument");
+        if (step_cap == 0 || step_cap > 0xFFFFu)
+            return fail(XS_EINVAL, "step_cap %u outside [1, 65535]", step_cap);
+        std::lock_guard<std::mutex> lock(I->mu);
+        const uint32_t key = sched_key(step_cap, 0, false, true);
+        auto it = I->sched.find(key);
+        if (it == I->sched.end())
+            it = I->sched.emplace(key, make_schedule(*I, step_cap, 0, 0, false, true)).first;
+        const xsh::HostSched &hs = it->second;
+        if (hs.border.empty()) return fail(XS_ENOTFOUND, "no cross-sweep body for this cap");
+        std::memcpy(order, hs.border.data(), sizeof(int32_t) * hs.border.size());
+        std::memcpy(step_off, hs.boff.data(), sizeof(int32_t) * hs.boff.size());
+        for (int p = 0; p < I->n; ++p) late[hs.border[p]] = (hs.brec[8 * (size_t)p + 7] >> 12) & 1;
+        *n_steps = (int32_t)hs.boff.size() - 1;
         return XS_OK;
     });
 }

@@ -139,6 +139,12 @@ __device__ __forceinline__ uint32_t met_word(uint32_t x, uint32_t a1, uint32_t b
 constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
 __host__ __device__ constexpr size_t lds_rec_bytes(uint32_t n) { return size_t(16) * n; }
+// Acceptance-bit buffers of a tile: sweeps alternate between two, and tiles with records in
+// global memory and w0 = 0 keep a third for the cross-sweep body, whose iteration k reads the
+// bits of sweeps k and k - 1 while the bits of sweep k + 1 are drawn into the third.
+__host__ __device__ constexpr uint32_t accept_buffers(bool rec_global, bool met) {
+    return rec_global && !met ? 3u : 2u;
+}
 
 // ------------------------------------------------------------------------------ init
 
@@ -361,6 +367,36 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
     }
 }
 
+// One iteration k of the cross-sweep body (records in global memory, w0 = 0): its steps, a
+// barrier before each (the first one also publishes the acceptance bits of sweep k and the
+// writes of iteration k - 1). A spin marked late (record meta bit 12) is updated for sweep
+// k - 1 with that sweep's acceptance bits (buffer rb_prev), the others for sweep k (rb_cur).
+// EDGE: the first iteration of a chunk (first = true) runs only the spins that are not late,
+// for its first sweep; the last one only the late spins, for its last sweep.
+template <int NT, int CW, bool J0, bool EDGE>
+__device__ __forceinline__ void body_iter(const Tile &T, uint32_t rb_cur, uint32_t rb_prev,
+                                          bool first) {
+    const LDS_AS uint16_t *so = (const LDS_AS uint16_t *)(uintptr_t)(T.lds0 + T.stp);
+    const uint32_t dprev = rb_prev - rb_cur;  // modulo 2^32: added only to late tasks
+    uint32_t none[CW / 4] = {};
+    uint32_t cs = 0, ce = so[1];
+    for (uint32_t c = 0; c < T.nsteps; ++c) {
+        const uint32_t ntask = (ce - cs) << T.lcol;  // at most NT: body steps hold one round
+        uint4 r0;
+        if (T.tid < ntask) r0 = rec_at<true>(T, cs + T.tpos);
+        __syncthreads();
+        const uint32_t ce_next = so[c + 2];
+        const uint32_t ra = (T.lds0 + rb_cur + (cs << T.lB)) + T.rbo;
+        if (T.tid < ntask) {
+            const uint32_t late = (r0.w >> 28) & 1u;
+            if (!EDGE || (late != 0) != first)
+                update_task<CW, false, false, J0>(T, r0, ra + late * dprev, none);
+        }
+        cs = ce;
+        ce = __builtin_amdgcn_readfirstlane(ce_next);
+    }
+}
+
 // k >= 1 for any visited spin, over every spin of the current LDS state (no update): a zero
 // bit marks a clone whose configuration is a ground state.
 template <int NT, int CW, bool GR, bool J0>
@@ -469,6 +505,24 @@ __device__ __forceinline__ void st_dev(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Make the tile run a step table: its records, step bounds (staged into LDS, at most n + 1 of
+// them, the last one repeated once) and, with records in global memory, the spin index of every
+// position (for the acceptance pass) in its own LDS array. The caller synchronises before the
+// staged arrays are read.
+template <int NT, bool GR>
+__device__ __forceinline__ void stage_table(Tile &T, const uint4 *grec, const int32_t *off,
+                                            uint32_t nsteps) {
+    T.grec = grec;
+    T.step_off = off;
+    T.nsteps = nsteps;
+    for (uint32_t c = T.tid; c <= nsteps + 1; c += NT)
+        *reinterpret_cast<uint16_t *>(xs_lds + T.stp + 2 * c) =
+            (uint16_t)((const GLOBAL_AS int32_t *)off)[min(c, nsteps)];
+    for (uint32_t p = T.tid; GR && p < T.n; p += NT)  // spin < 2048: meta bits 0-10
+        *reinterpret_cast<uint16_t *>(xs_lds + T.meta + 2 * p) =
+            (uint16_t)((((const GLOBAL_AS uint32_t *)grec)[4 * p + 3] >> 16) & 0x7FFu);
+}
+
 // Sweeps [t0, t1) (one chunk) of one workgroup tile: the tile of blocks blk0 .. blk0 + B - 1
 // of instance I, its rows staged in LDS and written back at the end. The caller passes
 // t0 < t1.
@@ -506,7 +560,7 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
     const uint32_t rbb = (uint32_t)align16((size_t)T.n * T.B * (MET ? 2 : 1));
     T.rb0 = T.st + T.n * T.rowb;
     T.rb1 = T.rb0 + rbb;
-    T.acc = T.rb1 + rbb;
+    T.acc = T.rb0 + accept_buffers(GR, MET) * rbb;
     T.flag = T.acc + 4 * T.ngrp;
     T.meta = GR ? T.flag + 16 : 14u;  // GR: after the flag; else the top half of each record's w
     T.stp = T.flag + 16 + (GR ? (uint32_t)align16(2 * (size_t)T.n) : 0u);
@@ -524,15 +578,19 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
     T.iid = I->inst_id;
     T.nsteps = I->n_steps;
 
+    // Untracked chunks of an instance with a cross-sweep body run the body's iterations;
+    // chunks that test every sweep and replays run the plain steps. The track flag can be set
+    // by another tile of the instance meanwhile, so one thread reads it for the workgroup
+    // (check_state's first barrier comes before the flag word is reused).
+    if (T.tid == 0) lds_u32(T.flag) = MET ? 0u : ld_dev(&I->track);
+    __syncthreads();
+    const bool track = lds_u32(T.flag) != 0;
+    const bool body = GR && !MET && I->bgrec != nullptr && !track;
+    if (body)
+        stage_table<NT, GR>(T, I->bgrec, I->bstep_off, I->n_bsteps);
+    else
+        stage_table<NT, GR>(T, T.grec, T.step_off, T.nsteps);
     // Records: LDS rows -> byte offsets of the rows in this tile (GR: done by the host).
-    // Step bounds into LDS (at most n + 1 of them), the last one repeated once.
-    for (uint32_t c = T.tid; c <= T.nsteps + 1; c += NT)
-        *reinterpret_cast<uint16_t *>(xs_lds + T.stp + 2 * c) =
-            (uint16_t)((const GLOBAL_AS int32_t *)T.step_off)[min(c, T.nsteps)];
-    // GR: the spin index of every position (for the acceptance pass) into its own LDS array.
-    for (uint32_t p = T.tid; GR && p < T.n; p += NT)
-        *reinterpret_cast<uint16_t *>(xs_lds + T.meta + 2 * p) =
-            (uint16_t)((((const GLOBAL_AS uint32_t *)T.grec)[4 * p + 3] >> 16) & 0x1FFFu);
     for (uint32_t p = T.tid; !GR && p < T.n; p += NT) {
         const uint4 r = gload16(I->rec, p);
         const uint32_t rowb = T.rowb;
@@ -566,7 +624,7 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
     __syncthreads();  // records, state and accumulators visible to every thread
     if (t0 == I->t_start) check_state<NT, CW, GR, J0>(T, t0, hm);  // the run's start configuration
 
-    if (ld_dev(&I->track)) {
+    if (track) {
         // This instance keeps producing new ground-state clones: test every sweep.
         uint32_t hm_t = hm;
         accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
@@ -582,13 +640,34 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
         check_state<NT, CW, GR, J0>(T, t1, hm);
     } else {
         uint32_t none[G] = {};  // unused: this loop tracks no ground states
-        accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
-        for (uint32_t t = t0; t < t1; ++t) {
-            sweep<NT, CW, GR, false, false, J0>(T, (t & 1) ? T.rb1 : T.rb0, none);
-            if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+        if constexpr (GR && !MET) {
+            if (body) {
+                // Iterations t0 .. t1 of the body: iteration k draws the bits of sweep k into
+                // buffer k mod 3 and runs sweep k's spins that are not late with sweep k - 1's
+                // late ones; the first runs sweep t0's early spins alone, the last sweep
+                // t1 - 1's late spins alone, so the chunk ends with the state at exactly t1.
+                const uint32_t rbb = T.rb1 - T.rb0;
+                auto rbuf = [&](uint32_t k) { return T.rb0 + (k % 3u) * rbb; };
+                accept_bits<NT, GR, false>(T, t0, rbuf(t0));
+                body_iter<NT, CW, J0, true>(T, rbuf(t0), rbuf(t0), true);
+                for (uint32_t k = t0 + 1; k < t1; ++k) {
+                    accept_bits<NT, GR, false>(T, k, rbuf(k));
+                    body_iter<NT, CW, J0, false>(T, rbuf(k), rbuf(k - 1), false);
+                }
+                body_iter<NT, CW, J0, true>(T, rbuf(t1 - 1), rbuf(t1 - 1), false);
+            }
+        }
+        if (!body) {
+            accept_bits<NT, GR, false>(T, t0, (t0 & 1) ? T.rb1 : T.rb0);
+            for (uint32_t t = t0; t < t1; ++t) {
+                sweep<NT, CW, GR, false, false, J0>(T, (t & 1) ? T.rb1 : T.rb0, none);
+                if (t + 1 < t1) accept_bits<NT, GR, false>(T, t + 1, (t & 1) ? T.rb0 : T.rb1);
+            }
         }
         if (check_state<NT, CW, GR, J0>(T, t1, hm)) {
-            // Replay from the chunk's start state with a per-sweep ground-state test.
+            // Replay from the chunk's start state with a per-sweep ground-state test, on the
+            // plain steps (check_state ends synchronised, so the tables can be restaged).
+            if (body) stage_table<NT, GR>(T, I->grec, I->step_off, I->n_steps);
             uint32_t hm_replay = 0;  // hits before this chunk; the end check's are redone
             if (T.tid < T.ngrp) {
                 const int32_t *fh = I->first_hit + ((size_t)(T.blk0 * 8 + T.tid) << 5);
@@ -925,8 +1004,8 @@ __global__ __launch_bounds__(256) void qg_gather(InstDev *I) {
 
 size_t chunk_lds_bytes(uint32_t n, uint32_t B, bool rec_global, bool met) {
     return (rec_global ? align16(2 * (size_t)n) : lds_rec_bytes(n)) + (size_t)n * B * 32 +
-           2 * align16((size_t)n * B * (met ? 2 : 1)) + (size_t)B * 8 * 4 + 16 +
-           align16(2 * ((size_t)n + 2));
+           accept_buffers(rec_global, met) * align16((size_t)n * B * (met ? 2 : 1)) +
+           (size_t)B * 8 * 4 + 16 + align16(2 * ((size_t)n + 2));
 }
 
 hipError_t launch_init(InstDev *d_inst, const InstDev &h, hipStream_t s) {

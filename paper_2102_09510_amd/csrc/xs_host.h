@@ -21,6 +21,10 @@ struct DevSched {
     uint16_t *rowmap = nullptr;        // [n] LDS row of each spin (null: identity)
     uint32_t steps = 0;
     std::map<uint32_t, uint4 *> grec;  // records as row offsets, per tile_blocks
+    // cross-sweep body (HostSched::border): step offsets and records as row offsets
+    int32_t *boff = nullptr;           // [bsteps + 1], null: no body
+    uint32_t bsteps = 0;
+    std::map<uint32_t, uint4 *> bgrec;  // per tile_blocks
 };
 
 struct DeviceTables {
@@ -36,6 +40,11 @@ struct HostSched {
     std::vector<uint16_t> rec;     // [n][8] records in schedule order
     std::vector<uint16_t> rowmap;  // [n] LDS row of each spin (empty: identity)
     int32_t max_step = 0;
+    // Cross-sweep body (empty: none): the steps of one iteration of overlapped sweeps. Spins in
+    // body order, its step offsets, and records as `rec` whose meta bit 12 marks a spin whose
+    // update runs one iteration after its sweep's (see make_body).
+    std::vector<int32_t> border, boff;
+    std::vector<uint16_t> brec;
 };
 
 

@@ -50,6 +50,13 @@ struct InstDev {
     // 0 or 1) and every record's coupling bits are 0 (each J_t is +1 in that gauge).
     const uint8_t *gauge;
     uint32_t j0;
+    // Cross-sweep body (records in global memory, w0 = 0 only; null: none): records with row
+    // offsets for this tiling in body order (meta bit 12: the spin's update runs in the
+    // iteration after its sweep's) and the step offsets of one iteration (n_bsteps steps).
+    // Untracked chunks run iterations of the body; tracked sweeps and replays the plain steps.
+    const uint4 *bgrec;
+    const int32_t *bstep_off;
+    uint32_t n_bsteps;
 };
 
 // Work queue of a persistent launch: tickets (head) are taken by workgroups, slots (tail) are

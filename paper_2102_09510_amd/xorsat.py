@@ -19,10 +19,12 @@ XS_OK = 0
 XS_STATUS = {0: "XS_OK", 1: "XS_EINVAL", 2: "XS_ENOMEM", 3: "XS_EDEVICE", 4: "XS_EAGAIN",
              5: "XS_ENOTFOUND", 6: "XS_ECANCELED"}
 XS_STATUS_CODES = {v: k for k, v in XS_STATUS.items()}
+XS_ENOTFOUND = 5
 XS_STOP_ON_FIRST = 0x1
 XS_RESUME = 0x2
 XS_PLACE_ROWS = 0x4
 XS_PER_CHUNK = 0x8
+XS_ONE_SWEEP_STEPS = 0x10
 XS_MAX_N = 2048
 XS_CLONE_QUANTUM = 256
 XS_MAX_CLONES = 0x7FFFFF00
@@ -31,7 +33,7 @@ XS_NOALLOC_SCRATCH_BYTES = 8 << 20
 # Every function the header declares, for the export check.
 EXPORTS = ["xs_abi_version", "xs_status_str", "xs_last_error", "xs_instance_create",
            "xs_instance_destroy", "xs_instance_get_info", "xs_instance_get_partition",
-           "xs_instance_get_schedule",
+           "xs_instance_get_schedule", "xs_instance_get_body",
            "xs_run", "xs_run_batch", "xs_run_batch_noalloc", "xs_run_batch_async", "xs_wait",
            "xs_profile_enable", "xs_profile_read",
            "xs_autotune", "xs_tune_save", "xs_tune_load", "xs_tune_clear",
@@ -145,6 +147,8 @@ def load():
     lib.xs_instance_get_partition.restype = i32
     lib.xs_instance_get_schedule.argtypes = [P, ctypes.c_uint32, P, P, P]
     lib.xs_instance_get_schedule.restype = i32
+    lib.xs_instance_get_body.argtypes = [P, ctypes.c_uint32, P, P, P, P]
+    lib.xs_instance_get_body.restype = i32
     lib.xs_run.argtypes = [P, ctypes.POINTER(RunConfig), ctypes.POINTER(RunBuffers), P,
                            ctypes.POINTER(RunResult)]
     lib.xs_run.restype = i32
@@ -231,6 +235,20 @@ class Instance:
                                                off.ctypes.data, ctypes.byref(steps)))
         return order, off[: steps.value + 1].copy()
 
+    def body(self, step_cap: int):
+        """The cross-sweep body for steps of at most step_cap spins: (order, step_off, late), or
+        None if the instance has none for that cap."""
+        order = np.zeros(self.n, dtype=np.int32)
+        off = np.zeros(self.n + 1, dtype=np.int32)
+        late = np.zeros(self.n, dtype=np.uint8)
+        steps = ctypes.c_int32()
+        st = load().xs_instance_get_body(self._h, step_cap, order.ctypes.data, off.ctypes.data,
+                                         late.ctypes.data, ctypes.byref(steps))
+        if st == XS_ENOTFOUND:
+            return None
+        _check(st)
+        return order, off[: steps.value + 1].copy(), late
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().xs_instance_destroy(self._h)
@@ -267,12 +285,13 @@ def make_config(*, n_clones: int, seed: int, instance_id: int = 0, accept_thr: i
                 start_sweep: int = 0, chunk_sweeps: int = 0, tile_blocks: int = 0,
                 wg_threads: int = 0, col_bytes: int = 0, rec_global: int = 0,
                 accept_thr0: int = 0, place_rows: bool = False,
-                per_chunk: bool = False) -> RunConfig:
+                per_chunk: bool = False, one_sweep_steps: bool = False) -> RunConfig:
     """accept_thr0 > 0 selects the rule with w0 = accept_thr0 / 65536 (no ground-state
     tracking: first_hit marks only clones whose end configuration is a ground state).
     place_rows builds the LDS row placement even for a short run (speed only)."""
     flags = ((XS_STOP_ON_FIRST if stop_on_first else 0) | (XS_RESUME if resume else 0) |
-             (XS_PLACE_ROWS if place_rows else 0) | (XS_PER_CHUNK if per_chunk else 0))
+             (XS_PLACE_ROWS if place_rows else 0) | (XS_PER_CHUNK if per_chunk else 0) |
+             (XS_ONE_SWEEP_STEPS if one_sweep_steps else 0))
     return RunConfig(ctypes.sizeof(RunConfig), instance_id, seed & (2**64 - 1), n_clones,
                      accept_thr, flags, max_sweeps, start_sweep, chunk_sweeps, tile_blocks,
                      wg_threads, col_bytes, rec_global, accept_thr0, 0)

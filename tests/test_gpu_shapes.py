@@ -301,3 +301,38 @@ def test_persistent_queue_over_several_epochs_and_timed():
                  out.first_hit.cpu().numpy(), out.energy.cpu().numpy(), out.state,
                  what="several epochs")
     assert all(o.tts_sweeps >= 0 for o in runs["queue"][1:3])  # N = 40, 72 solve
+
+
+@pytest.mark.parametrize("n,nc,shape", [(1024, 1 << 18, STEADY_SHAPE), (256, 65536, (4, 256, 16, 1))])
+def test_cross_sweep_body_equals_one_sweep_at_a_time(n, nc, shape):
+    """Untracked chunks run the cross-sweep body (the end of a sweep overlapped with the start
+    of the next); XS_ONE_SWEEP_STEPS runs the same chunks one sweep after another. From the same
+    near-solution starts, over chunks of 25 sweeps (hits inside the first chunk, so its replay
+    follows a body chunk, and in later chunks), both give bit-identical states, first hits and
+    energies, and sampled groups match the oracle."""
+    torch = _torch()
+    rng = np.random.default_rng(n + 7)
+    inst = planted_instance(n, 3_100_000 + n)
+    h = xorsat.Instance(inst.tri, inst.J)
+    B, T, C, G = shape
+    assert h.body(T * C // (32 * B)) is not None, "this shape's steps have a cross-sweep body"
+    gf = {16 * (3 + 5 * t) + t: f for t, f in enumerate((2, 8, 24, 48))}
+    st, _ = near_solution_state(inst, nc, rng, gf)
+    outs = []
+    for one in (False, True):
+        cfg = xorsat.make_config(n_clones=nc, seed=0xB0D + n, instance_id=3, accept_thr=THR_PAPER,
+                                 max_sweeps=100, start_sweep=500, resume=True,
+                                 stop_on_first=False, chunk_sweeps=25, one_sweep_steps=one,
+                                 tile_blocks=B, wg_threads=T, col_bytes=C, rec_global=G)
+        outs.append((cfg, xorsat.run(h, cfg, state=torch.from_numpy(st.copy()).cuda())))
+    (cfg, a), (_, b) = outs
+    for o in (a, b):
+        assert (o.tile_blocks, o.wg_threads, o.col_bytes, o.rec_global) == shape
+    assert a.end_sweep == b.end_sweep == 600
+    fh = a.first_hit.cpu().numpy()
+    assert ((fh > 500) & (fh < 525)).any() and (fh >= 525).any()
+    assert np.array_equal(a.state.cpu().numpy(), b.state.cpu().numpy())
+    assert np.array_equal(fh, b.first_hit.cpu().numpy())
+    assert np.array_equal(a.energy.cpu().numpy(), b.energy.cpu().numpy())
+    assert (a.tts_sweeps, a.winner_clone) == (b.tts_sweeps, b.winner_clone)
+    check_instance(inst, h, cfg, a, st, sorted(gf) + [5, nc // 32 - 2], f"n={n}")

@@ -86,3 +86,51 @@ def test_shuffled_order_changes_trajectories():
     b = oracle.run(inst.tri, inst.J, rev, **kw)
     assert not np.array_equal(a["final_spins"], b["final_spins"])
     h.close()
+
+
+@pytest.mark.parametrize("n,cap,step_cap,must", [(256, 32, 32, True), (512, 32, 64, True),
+                                                 (1024, 32, 64, True), (2048, 32, 64, False),
+                                                 (1024, 32, 96, False), (300, 7, 40, False),
+                                                 (96, 32, 16, False)])
+def test_body_replays_the_sequential_sweeps(n, cap, step_cap, must):
+    """Symbolic replay of the cross-sweep body over a chunk of sweeps [3, 10): iterations 3 .. 10,
+    each running its steps in order, a step's updates reading before any of them writes. Every
+    update must read the version of each spin that the sequential sweeps give it (its own and
+    its later partners' from the previous sweep, its earlier partners' from the current one),
+    no two updates of a step may touch each other's spin, and every update runs exactly once.
+    The body is also shorter than the plain schedule and within the step cap."""
+    inst = planted_instance(n, 4300 + n)
+    h = xorsat.Instance(inst.tri, inst.J, colour_cap=cap)
+    body = h.body(step_cap)
+    if body is None:
+        assert not must, "the headline shapes have a body"
+        h.close()
+        return
+    order, off, late = body
+    ii = len(off) - 1
+    perm, _ = h.partition()
+    _, plain_off = h.schedule(step_cap)
+    assert ii < len(plain_off) - 1
+    assert sorted(order.tolist()) == list(range(n))
+    assert np.diff(off).max() <= step_cap and set(np.unique(late)) <= {0, 1}
+    pos = np.empty(n, dtype=np.int64)
+    pos[perm] = np.arange(n)
+    partners = _partners(inst.tri, n)
+    t0, t1 = 3, 10
+    ver = np.full(n, t0 - 1)
+    runs = np.zeros(n, dtype=np.int64)
+    for k in range(t0, t1 + 1):
+        for s in range(ii):
+            tasks = [(int(j), k - int(late[j])) for j in order[off[s]:off[s + 1]]
+                     if t0 <= k - int(late[j]) < t1]
+            spins = {j for j, _ in tasks}
+            for j, t in tasks:
+                assert ver[j] == t - 1, (j, t)
+                for u in partners[j]:
+                    assert u not in spins, (j, u)
+                    assert ver[u] == (t if pos[u] < pos[j] else t - 1), (j, u, t)
+            for j, t in tasks:
+                ver[j] = t
+                runs[j] += 1
+    assert np.all(ver == t1 - 1) and np.all(runs == t1 - t0)
+    h.close()
