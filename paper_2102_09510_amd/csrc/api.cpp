@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cstdarg>
@@ -11,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -253,6 +255,89 @@ std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int
     return row;
 }
 
+// The rules of a body, checked for offsets tau and iteration length ii (see make_body).
+bool body_valid(const xs_instance &I, uint32_t cap, const std::vector<int32_t> &inc,
+                const std::vector<int32_t> &pos, const std::vector<int32_t> &tau, int ii) {
+    const int n = I.n;
+    std::vector<int32_t> width(ii, 0);
+    for (int v = 0; v < n; ++v) {
+        if (tau[v] < 0 || tau[v] >= 2 * ii) return false;
+        if (++width[tau[v] % ii] > (int)cap && cap) return false;
+        for (int q = 0; q < 3; ++q) {
+            const int tr = inc[3 * v + q];
+            for (int z = 0; z < 3; ++z) {
+                const int u = I.tri[3 * tr + z];
+                if (u == v) continue;
+                if (tau[u] % ii == tau[v] % ii) return false;
+                if (pos[u] < pos[v] ? !(tau[u] < tau[v]) : !(tau[u] < ii + tau[v])) return false;
+            }
+        }
+    }
+    return true;
+}
+
+// A body of a given length ii by modulo scheduling, for shapes where the sweep-by-sweep
+// placement of make_body does not settle into one: spins are placed in update order, each at
+// the earliest offset its placed partners allow (after its earlier partners, at most ii - 1
+// before its later ones) whose step (offset mod ii) has room and holds none of its partners;
+// passes repeat while a later partner's move raised some spin's earliest offset. Offsets only
+// grow, so a pass limit ends it; the result is normalised to start at 0 and checked.
+bool modulo_body(const xs_instance &I, uint32_t cap, const std::vector<int32_t> &inc,
+                 const std::vector<int32_t> &pos, int ii, std::vector<int32_t> &tau) {
+    const int n = I.n;
+    constexpr int kPasses = 24;
+    tau.assign(n, -1);
+    std::vector<int32_t> fill(ii, 0);
+    auto earliest = [&](int v) {
+        int s = 0;
+        for (int q = 0; q < 3; ++q) {
+            const int tr = inc[3 * v + q];
+            for (int z = 0; z < 3; ++z) {
+                const int u = I.tri[3 * tr + z];
+                if (u == v || tau[u] < 0) continue;
+                s = std::max(s, pos[u] < pos[v] ? tau[u] + 1 : tau[u] + 1 - ii);
+            }
+        }
+        return s;
+    };
+    auto fits = [&](int v, int s) {
+        if (cap && fill[s % ii] >= (int)cap) return false;
+        for (int q = 0; q < 3; ++q) {
+            const int tr = inc[3 * v + q];
+            for (int z = 0; z < 3; ++z) {
+                const int u = I.tri[3 * tr + z];
+                if (u != v && tau[u] >= 0 && tau[u] % ii == s % ii) return false;
+            }
+        }
+        return true;
+    };
+    for (int pass = 0; pass < kPasses; ++pass) {
+        bool moved = false;
+        for (int p = 0; p < n; ++p) {
+            const int v = I.perm[p];
+            const int lb = earliest(v);
+            if (tau[v] >= lb) continue;
+            if (tau[v] >= 0) --fill[tau[v] % ii];
+            tau[v] = -1;
+            int s = lb;
+            while (!fits(v, s)) {
+                if (s - lb > 2 * ii) return false;  // no step of the iteration fits
+                ++s;
+            }
+            tau[v] = s;
+            ++fill[s % ii];
+            moved = true;
+        }
+        if (!moved) {
+            const int base = *std::min_element(tau.begin(), tau.end());
+            const int shift = base - ((base % ii) + ii) % ii;  // keep residues: subtract a multiple of ii
+            for (int v = 0; v < n; ++v) tau[v] -= shift;
+            return body_valid(I, cap, inc, pos, tau, ii);
+        }
+    }
+    return false;
+}
+
 // Cross-sweep body. Successive sweeps may overlap: the update of spin j in sweep t runs at
 // step t * II + tau(j) of the run, for offsets tau(j) in [0, 2 II), i.e. in step tau(j) mod II
 // of iteration t + tau(j) div II (a "late" spin runs in the iteration after its sweep's). The
@@ -266,8 +351,9 @@ std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int
 // 2 II). tau comes from placing the updates of successive sweeps each as early as these rules
 // allow, into the first step with room (the single-sweep rule of make_schedule, across
 // sweeps): once every spin's step moves by the same II from one sweep to the next, and did so
-// the sweep before too, tau is that sweep's steps less their minimum. The result is checked
-// against (1)-(4) and kept only if II is below the single-sweep step count.
+// the sweep before too, tau is that sweep's steps less their minimum. Otherwise modulo_body
+// looks for the shortest II below the single-sweep step count directly. The result is checked
+// against (1)-(4) (body_valid) and kept only if II is below the single-sweep step count.
 bool make_body(const xs_instance &I, uint32_t cap, int plain_steps,
                const std::vector<int32_t> &inc, const std::vector<int32_t> &pos,
                std::vector<int32_t> &tau, int &ii) {
@@ -298,28 +384,28 @@ bool make_body(const xs_instance &I, uint32_t cap, int plain_steps,
     }
     // cur: last sweep, prev: the one before, prev2: the one before that
     ii = cur[0] - prev[0];
-    for (int v = 0; v < n; ++v)
-        if (cur[v] - prev[v] != ii || prev[v] - prev2[v] != ii) return false;
-    if (ii <= 0 || ii >= plain_steps) return false;
-    const int base = *std::min_element(prev.begin(), prev.end());
-    tau.assign(n, 0);
-    std::vector<int32_t> width(ii, 0);
-    for (int v = 0; v < n; ++v) {
-        tau[v] = prev[v] - base;
-        if (tau[v] >= 2 * ii) return false;
-        if (++width[tau[v] % ii] > (int)cap && cap) return false;
+    bool periodic = ii > 0 && ii < plain_steps;
+    for (int v = 0; v < n && periodic; ++v)
+        periodic = cur[v] - prev[v] == ii && prev[v] - prev2[v] == ii;
+    if (periodic) {
+        const int base = *std::min_element(prev.begin(), prev.end());
+        tau.assign(n, 0);
+        for (int v = 0; v < n; ++v) tau[v] = prev[v] - base;
+        if (body_valid(I, cap, inc, pos, tau, ii)) return true;
     }
-    for (int v = 0; v < n; ++v)
-        for (int q = 0; q < 3; ++q) {
-            const int tr = inc[3 * v + q];
-            for (int z = 0; z < 3; ++z) {
-                const int u = I.tri[3 * tr + z];
-                if (u == v) continue;
-                if (tau[u] % ii == tau[v] % ii) return false;
-                if (pos[u] < pos[v] ? !(tau[u] < tau[v]) : !(tau[u] < ii + tau[v])) return false;
-            }
-        }
-    return true;
+    // No period of one sweep: modulo schedules of decreasing length, from one step below the
+    // single-sweep count down to the width bound, keeping the last that works (a failure ends
+    // the search: shorter ones rarely work where a longer one did not, and each try costs
+    // passes over the spins).
+    const int lo = std::max(1, cap ? (n + (int)cap - 1) / (int)cap : 1);
+    std::vector<int32_t> t;
+    int found = 0;
+    for (int k = plain_steps - 1; k >= lo && modulo_body(I, cap, inc, pos, k, t); --k) {
+        tau = t;
+        found = k;
+    }
+    ii = found;
+    return found > 0;
 }
 
 // Execution schedule of the update order. The update of a spin reads its own value and those of
@@ -535,30 +621,101 @@ bool wants_body(const xs::InstDev &d) {
 }
 uint32_t place_layout(uint32_t B, uint32_t CW) { return B < 8 ? B | CW << 8 : 0u; }
 
-// Clone-sweeps (clones x sweeps left) from which a run builds the row placement.
+// Clone-sweeps (clones x sweeps left) from which a run builds the row placement. The search
+// costs a few µs of host time per spin and saves about 5 % of the sweep time, both in
+// proportion to N, so the break-even is a clone-sweep count; batches build their instances'
+// schedules on several host threads at once, which divides the cost (host_threads()).
 constexpr uint64_t kPlaceMinWork = 1ull << 32;
+
+// Host threads that build the schedules of a batch.
+uint32_t host_threads() {
+    const uint32_t hc = std::thread::hardware_concurrency();
+    return std::max(1u, std::min(hc ? hc : 1u, 16u));
+}
+
+// What a descriptor's schedule is made of (see host_sched).
+struct SchedParams {
+    uint32_t key, cap, layout;
+    bool j0, body;
+};
+
+// The schedule a descriptor's launch uses: its step cap, row placement and body. The row
+// placement is used if it exists or the run is long enough to pay for building it (runs of a
+// batch share the host threads, `builders` of them); either gives the same results. Caller
+// holds I->mu.
+SchedParams sched_params(const xs_instance *I, const xs::InstDev &d, uint32_t builders) {
+    SchedParams sp;
+    sp.cap = step_cap(d);
+    sp.layout = place_layout(d.tile_blocks, d.col_bytes);
+    sp.j0 = d.j0 != 0;
+    sp.body = wants_body(d);
+    const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
+    if (sp.layout && work < kPlaceMinWork / std::max(builders, 1u) &&
+        !(d.flags & XS_PLACE_ROWS) && !I->sched.count(sched_key(sp.cap, sp.layout, sp.j0, sp.body)))
+        sp.layout = 0;
+    sp.key = sched_key(sp.cap, sp.layout, sp.j0, sp.body);
+    return sp;
+}
 
 // The host schedule a descriptor's launch uses (built on first use; caller holds I->mu), and
 // its key in the instance's caches.
-const xsh::HostSched &host_sched(const xs_instance *I, const xs::InstDev &d, uint32_t *key_out) {
-    const uint32_t cap = step_cap(d);
-    uint32_t layout = place_layout(d.tile_blocks, d.col_bytes);
-    // The row placement costs a few µs of host time per spin and saves about 5 % of the
-    // sweep time; a run too short to pay that back uses the unplaced schedule unless the
-    // placed one already exists. Either gives the same results.
-    const bool body = wants_body(d);
-    const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
-    if (layout && work < kPlaceMinWork && !(d.flags & XS_PLACE_ROWS) &&
-        !I->sched.count(sched_key(cap, layout, d.j0 != 0, body)))
-        layout = 0;
-    const uint32_t key = sched_key(cap, layout, d.j0 != 0, body);
-    auto hit = I->sched.find(key);
+const xsh::HostSched &host_sched(const xs_instance *I, const xs::InstDev &d, uint32_t *key_out,
+                                 uint32_t builders = 1) {
+    const SchedParams sp = sched_params(I, d, builders);
+    auto hit = I->sched.find(sp.key);
     if (hit == I->sched.end())
         hit = I->sched
-                  .emplace(key, make_schedule(*I, cap, layout & 0xFF, layout >> 8, d.j0 != 0, body))
+                  .emplace(sp.key, make_schedule(*I, sp.cap, sp.layout & 0xFF, sp.layout >> 8,
+                                                 sp.j0, sp.body))
                   .first;
-    *key_out = key;
+    *key_out = sp.key;
     return hit->second;
+}
+
+// Build the missing schedules of a batch's descriptors on several host threads (each instance
+// and key once). make_schedule reads only fields an instance never changes after creation, so
+// the builds run without the instance's lock; the results are inserted under it. Returns the
+// number of builders the batch may count on (1 when at most one schedule is missing).
+uint32_t prebuild_schedules(const std::vector<xs::InstDev> &h, const xs_instance *const *insts,
+                            int count) {
+    const uint32_t threads = host_threads();
+    struct Job {
+        const xs_instance *I;
+        SchedParams sp;
+        xsh::HostSched hs;
+    };
+    std::vector<Job> jobs;
+    for (int k = 0; k < count; ++k) {
+        const xs_instance *I = insts[k];
+        std::lock_guard<std::mutex> lock(I->mu);
+        const SchedParams sp = sched_params(I, h[k], threads);
+        if (I->sched.count(sp.key)) continue;
+        bool dup = false;
+        for (const Job &j : jobs) dup |= j.I == I && j.sp.key == sp.key;
+        if (!dup) jobs.push_back(Job{I, sp, {}});
+    }
+    if (jobs.size() < 2) return 1;
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t j; (j = next.fetch_add(1)) < jobs.size();) {
+            Job &b = jobs[j];
+            b.hs = make_schedule(*b.I, b.sp.cap, b.sp.layout & 0xFF, b.sp.layout >> 8, b.sp.j0,
+                                 b.sp.body);
+        }
+    };
+    std::vector<std::thread> pool;
+    try {
+        for (uint32_t t = 1; t < std::min<size_t>(threads, jobs.size()); ++t) pool.emplace_back(work);
+    } catch (const std::system_error &) {
+        // fewer threads: the caller's thread builds what the others do not
+    }
+    work();
+    for (std::thread &t : pool) t.join();
+    for (Job &j : jobs) {
+        std::lock_guard<std::mutex> lock(j.I->mu);
+        j.I->sched.emplace(j.sp.key, std::move(j.hs));
+    }
+    return threads;
 }
 
 // Records with the byte offsets of the rows in a tile of B blocks (32 * B bytes per row), as
@@ -578,12 +735,13 @@ std::vector<uint32_t> grec_image(const std::vector<uint16_t> &rec, int n, uint32
 
 xs_status attach_tables(std::vector<xs::InstDev> &h, const xs_instance *const *insts, int count,
                         int device) {
+    const uint32_t builders = prebuild_schedules(h, insts, count);
     for (int k = 0; k < count; ++k) {
         xs::InstDev &d = h[k];
         const xs_instance *I = insts[k];
         std::lock_guard<std::mutex> lock(I->mu);
         uint32_t key = 0;
-        const xsh::HostSched &hs = host_sched(I, d, &key);
+        const xsh::HostSched &hs = host_sched(I, d, &key, builders);
         xsh::DevSched &ds = I->dev[device].sched[key];
         if (!ds.rec) {
             const size_t n = (size_t)I->n, off_bytes = sizeof(int32_t) * hs.off.size();
