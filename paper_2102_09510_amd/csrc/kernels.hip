@@ -140,8 +140,8 @@ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
 __host__ __device__ constexpr size_t lds_rec_bytes(uint32_t n) { return size_t(16) * n; }
 // Acceptance-bit buffers of a tile: sweeps alternate between two, and tiles with records in
-// global memory and w0 = 0 keep a third for the cross-sweep body, whose iteration k reads the
-// bits of sweeps k and k - 1 while the bits of sweep k + 1 are drawn into the third.
+// global memory and w0 = 0 keep a third for the cross-sweep body, whose iterations draw into
+// a buffer two iterations after its last reads.
 __host__ __device__ constexpr uint32_t accept_buffers(bool rec_global, bool met) {
     return rec_global && !met ? 3u : 2u;
 }
@@ -279,21 +279,25 @@ __device__ __forceinline__ uint32_t draws_below(uint4 o, uint32_t thr) {
 // Acceptance bits of sweep t: one Philox call per (position, block) gives the eight 16-bit draws
 // of the block's eight groups. MET: a 16-bit entry, the w1 byte and above it the w0 byte of the
 // same draws. A thread keeps one block (NT is a multiple of B) and strides over positions.
-template <int NT, bool GR, bool MET>
-__device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t rb) {
+// BODY (the cross-sweep body): a spin marked late (bit 12 of its staged meta) is updated in the
+// iteration after its sweep's, so its bits go to buffer rb_late, the one that iteration reads.
+template <int NT, bool GR, bool MET, bool BODY = false>
+__device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t rb,
+                                            uint32_t rb_late = 0) {
     const uint32_t b = T.tid & (T.B - 1);
     const uint64_t pz = (uint64_t)0xCD9E8D57u * (T.blk0 + b);
     const uint32_t t_k0 = t ^ T.key0, id_k1 = T.iid ^ T.key1;
     for (uint32_t p = T.tid >> T.lB; p < T.n; p += NT >> T.lB) {
         const uint32_t q = (p << T.lB) + b;
         const uint32_t v = *(const LDS_AS uint16_t *)(uintptr_t)(T.lds0 + T.meta + (GR ? 2 : 16) * p);
-        const uint32_t i = GR ? v : v & 0x1FFFu;  // GR: the array holds the spin index only
+        const uint32_t i = GR ? v & 0x7FFu : v & 0x1FFFu;  // spins < 2048 with records in global memory
         const uint4 o = philox10_draw(i, pz, t_k0, id_k1, T.key0, T.key1);
+        const uint32_t r = BODY && (v & 0x1000u) ? rb_late : rb;
         if constexpr (MET)
-            *reinterpret_cast<uint16_t *>(xs_lds + rb + 2 * q) =
+            *reinterpret_cast<uint16_t *>(xs_lds + r + 2 * q) =
                 (uint16_t)(draws_below(o, T.thr) | draws_below(o, T.thr0) << 8);
         else
-            xs_lds[rb + q] = (uint8_t)draws_below(o, T.thr);
+            xs_lds[r + q] = (uint8_t)draws_below(o, T.thr);
     }
 }
 
@@ -367,31 +371,26 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
     }
 }
 
-// One iteration k of the cross-sweep body (records in global memory, w0 = 0): its steps, a
-// barrier before each (the first one also publishes the acceptance bits of sweep k and the
-// writes of iteration k - 1). A spin marked late (record meta bit 12) is updated for sweep
-// k - 1 with that sweep's acceptance bits (buffer rb_prev), the others for sweep k (rb_cur).
-// EDGE: the first iteration of a chunk (first = true) runs only the spins that are not late,
-// for its first sweep; the last one only the late spins, for its last sweep.
-template <int NT, int CW, bool J0, bool EDGE>
-__device__ __forceinline__ void body_iter(const Tile &T, uint32_t rb_cur, uint32_t rb_prev,
-                                          bool first) {
+// The first or last iteration of a chunk run on the cross-sweep body (records in global memory,
+// w0 = 0): the body's steps, a barrier before each, as in sweep(), but the first iteration
+// (first = true) runs only the spins that are not late (record meta bit 12), for the chunk's
+// first sweep, and the last only the late ones, for its last sweep. Every task reads the
+// acceptance bits of its position in buffer rb (the acceptance pass puts a late spin's bits
+// where the iteration after its sweep's reads them).
+template <int NT, int CW, bool J0>
+__device__ __forceinline__ void body_edge(const Tile &T, uint32_t rb, bool first) {
     const LDS_AS uint16_t *so = (const LDS_AS uint16_t *)(uintptr_t)(T.lds0 + T.stp);
-    const uint32_t dprev = rb_prev - rb_cur;  // modulo 2^32: added only to late tasks
     uint32_t none[CW / 4] = {};
-    uint32_t cs = 0, ce = so[1];
+    uint32_t cs = 0, ce = __builtin_amdgcn_readfirstlane(so[1]);
     for (uint32_t c = 0; c < T.nsteps; ++c) {
         const uint32_t ntask = (ce - cs) << T.lcol;  // at most NT: body steps hold one round
         uint4 r0;
         if (T.tid < ntask) r0 = rec_at<true>(T, cs + T.tpos);
         __syncthreads();
         const uint32_t ce_next = so[c + 2];
-        const uint32_t ra = (T.lds0 + rb_cur + (cs << T.lB)) + T.rbo;
-        if (T.tid < ntask) {
-            const uint32_t late = (r0.w >> 28) & 1u;
-            if (!EDGE || (late != 0) != first)
-                update_task<CW, false, false, J0>(T, r0, ra + late * dprev, none);
-        }
+        const uint32_t ra = (T.lds0 + rb + (cs << T.lB)) + T.rbo;
+        if (T.tid < ntask && ((r0.w >> 28) & 1u) != (first ? 1u : 0u))
+            update_task<CW, false, false, J0>(T, r0, ra, none);
         cs = ce;
         ce = __builtin_amdgcn_readfirstlane(ce_next);
     }
@@ -518,9 +517,9 @@ __device__ __forceinline__ void stage_table(Tile &T, const uint4 *grec, const in
     for (uint32_t c = T.tid; c <= nsteps + 1; c += NT)
         *reinterpret_cast<uint16_t *>(xs_lds + T.stp + 2 * c) =
             (uint16_t)((const GLOBAL_AS int32_t *)off)[min(c, nsteps)];
-    for (uint32_t p = T.tid; GR && p < T.n; p += NT)  // spin < 2048: meta bits 0-10
+    for (uint32_t p = T.tid; GR && p < T.n; p += NT)  // spin (bits 0-10) and late bit (12)
         *reinterpret_cast<uint16_t *>(xs_lds + T.meta + 2 * p) =
-            (uint16_t)((((const GLOBAL_AS uint32_t *)grec)[4 * p + 3] >> 16) & 0x7FFu);
+            (uint16_t)((((const GLOBAL_AS uint32_t *)grec)[4 * p + 3] >> 16) & 0x1FFFu);
 }
 
 // Sweeps [t0, t1) (one chunk) of one workgroup tile: the tile of blocks blk0 .. blk0 + B - 1
@@ -642,19 +641,21 @@ __device__ __forceinline__ void tile_chunk(InstDev *I, uint32_t blk0, uint32_t t
         uint32_t none[G] = {};  // unused: this loop tracks no ground states
         if constexpr (GR && !MET) {
             if (body) {
-                // Iterations t0 .. t1 of the body: iteration k draws the bits of sweep k into
-                // buffer k mod 3 and runs sweep k's spins that are not late with sweep k - 1's
-                // late ones; the first runs sweep t0's early spins alone, the last sweep
-                // t1 - 1's late spins alone, so the chunk ends with the state at exactly t1.
+                // Iterations t0 .. t1 of the body: iteration k draws the bits of sweep k (those
+                // of early spins into buffer k mod 3, of late ones into buffer k + 1 mod 3) and
+                // runs sweep k's early spins with sweep k - 1's late ones, all reading buffer
+                // k mod 3; the first runs sweep t0's early spins alone, the last sweep t1 - 1's
+                // late spins alone, so the chunk ends with the state at exactly t1. A buffer is
+                // drawn into two iterations after its last reads.
                 const uint32_t rbb = T.rb1 - T.rb0;
                 auto rbuf = [&](uint32_t k) { return T.rb0 + (k % 3u) * rbb; };
-                accept_bits<NT, GR, false>(T, t0, rbuf(t0));
-                body_iter<NT, CW, J0, true>(T, rbuf(t0), rbuf(t0), true);
+                accept_bits<NT, GR, false, true>(T, t0, rbuf(t0), rbuf(t0 + 1));
+                body_edge<NT, CW, J0>(T, rbuf(t0), true);
                 for (uint32_t k = t0 + 1; k < t1; ++k) {
-                    accept_bits<NT, GR, false>(T, k, rbuf(k));
-                    body_iter<NT, CW, J0, false>(T, rbuf(k), rbuf(k - 1), false);
+                    accept_bits<NT, GR, false, true>(T, k, rbuf(k), rbuf(k + 1));
+                    sweep<NT, CW, GR, false, false, J0>(T, rbuf(k), none);
                 }
-                body_iter<NT, CW, J0, true>(T, rbuf(t1 - 1), rbuf(t1 - 1), false);
+                body_edge<NT, CW, J0>(T, rbuf(t1), false);
             }
         }
         if (!body) {
