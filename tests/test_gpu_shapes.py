@@ -336,3 +336,36 @@ def test_cross_sweep_body_equals_one_sweep_at_a_time(n, nc, shape):
     assert np.array_equal(a.energy.cpu().numpy(), b.energy.cpu().numpy())
     assert (a.tts_sweeps, a.winner_clone) == (b.tts_sweeps, b.winner_clone)
     check_instance(inst, h, cfg, a, st, sorted(gf) + [5, nc // 32 - 2], f"n={n}")
+
+
+@pytest.mark.parametrize("n,shape,nc", [
+    (48, (4, 64, 16, 1), 2048), (64, (1, 64, 8, 1), 1024), (64, (4, 64, 16, 1), 1024),
+    (200, (1, 256, 8, 1), 2048), (300, (1, 256, 8, 1), 1024), (200, (4, 64, 16, 1), 1024)])
+def test_cross_sweep_body_every_clone(n, shape, nc):
+    """Small instances with records in global memory, in shapes whose step cap has a cross-sweep
+    body (64-thread workgroups run the launch-per-chunk kernel, 256-thread ones the persistent
+    launch): every clone against the oracle over 61 sweeps in chunks of 7 (many clones reach a
+    ground state, so replays and tracked chunks follow body chunks), and bit-identical to one
+    sweep at a time."""
+    _torch()
+    B, T, C, G = shape
+    inst = planted_instance(n, 5100 + n)
+    h = xorsat.Instance(inst.tri, inst.J)
+    assert h.body(T * C // (32 * B)) is not None
+    outs = []
+    for one in (False, True):
+        cfg = xorsat.make_config(n_clones=nc, seed=n + 17, instance_id=n, accept_thr=THR_PAPER,
+                                 max_sweeps=61, stop_on_first=False, chunk_sweeps=7,
+                                 one_sweep_steps=one, tile_blocks=B, wg_threads=T, col_bytes=C,
+                                 rec_global=G)
+        outs.append((cfg, xorsat.run(h, cfg)))
+    (cfg, a), (_, b) = outs
+    assert (a.tile_blocks, a.wg_threads, a.col_bytes, a.rec_global) == shape
+    assert a.end_sweep == 61
+    for x, y in ((a.state, b.state), (a.first_hit, b.first_hit), (a.energy, b.energy)):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    operm, _ = oracle.colour(inst.tri, h.colour_cap)
+    fh = a.first_hit.cpu().numpy()
+    check_run_reduction(fh, a.tts_sweeps, a.winner_clone)
+    check_clones(inst.tri, inst.J, operm, cfg, a.sweeps_done, np.arange(nc), fh,
+                 a.energy.cpu().numpy(), a.state, what=f"n={n} shape={shape}")
