@@ -350,16 +350,20 @@ bool modulo_body(const xs_instance &I, uint32_t cap, const std::vector<int32_t> 
 // common spin as the sequential sweeps do (pairs more than one sweep apart: |tau(i) - tau(j)| <
 // 2 II). tau comes from placing the updates of successive sweeps each as early as these rules
 // allow, into the first step with room (the single-sweep rule of make_schedule, across
-// sweeps): once every spin's step moves by the same II from one sweep to the next, and did so
-// the sweep before too, tau is that sweep's steps less their minimum. Otherwise modulo_body
-// looks for the shortest II below the single-sweep step count directly. The result is checked
-// against (1)-(4) (body_valid) and kept only if II is below the single-sweep step count.
+// sweeps), for up to forty sweeps: once every spin's step moves by the same II from one
+// sweep to the next over three sweeps, tau is one of them less its minimum; a pattern that
+// only nearly settles is tried with the largest shift of its last sweeps (and one more) as
+// II; otherwise modulo_body looks for an II below the single-sweep step count directly. The
+// result is checked against (1)-(4) (body_valid) and kept only if II is below the
+// single-sweep step count.
 bool make_body(const xs_instance &I, uint32_t cap, int plain_steps,
                const std::vector<int32_t> &inc, const std::vector<int32_t> &pos,
                std::vector<int32_t> &tau, int &ii) {
     const int n = I.n;
-    constexpr int kSweeps = 12;
-    std::vector<int32_t> prev(n, -1), cur(n), prev2(n, -1), fill;
+    constexpr int kSweeps = 40, kTail = 8;
+    std::vector<int32_t> prev(n, -1), cur(n), fill;
+    std::vector<std::vector<int32_t>> last;  // steps of the last kTail sweeps
+    std::vector<int32_t> first_step;         // first step of each sweep
     for (int t = 0; t < kSweeps; ++t) {
         for (int p = 0; p < n; ++p) {
             const int v = I.perm[p];
@@ -377,26 +381,45 @@ bool make_body(const xs_instance &I, uint32_t cap, int plain_steps,
             ++fill[s];
             cur[v] = s;
         }
-        if (t + 1 < kSweeps) {
-            prev2.swap(prev);
-            prev = cur;
+        last.push_back(cur);
+        if ((int)last.size() > kTail) last.erase(last.begin());
+        prev = cur;
+        // settled: every spin moved by the same shift over each of the last three sweeps
+        if (last.size() >= 4) {
+            const size_t m = last.size();
+            const int d = last[m - 1][0] - last[m - 2][0];
+            bool same = true;
+            for (size_t k = m - 3; k < m && same; ++k)
+                for (int v = 0; v < n && same; ++v) same = last[k][v] - last[k - 1][v] == d;
+            if (same) break;
         }
     }
-    // cur: last sweep, prev: the one before, prev2: the one before that
-    ii = cur[0] - prev[0];
-    bool periodic = ii > 0 && ii < plain_steps;
-    for (int v = 0; v < n && periodic; ++v)
-        periodic = cur[v] - prev[v] == ii && prev[v] - prev2[v] == ii;
-    if (periodic) {
-        const int base = *std::min_element(prev.begin(), prev.end());
+    // A settled pattern: every spin moves by the same II over the last three sweeps. Else, the
+    // last sweep's offsets with the largest (then one more) shift seen over the last sweeps.
+    auto take = [&](const std::vector<int32_t> &steps, int len) {
+        const int base = *std::min_element(steps.begin(), steps.end());
         tau.assign(n, 0);
-        for (int v = 0; v < n; ++v) tau[v] = prev[v] - base;
-        if (body_valid(I, cap, inc, pos, tau, ii)) return true;
+        for (int v = 0; v < n; ++v) tau[v] = steps[v] - base;
+        ii = len;
+        return len > 0 && len < plain_steps && body_valid(I, cap, inc, pos, tau, len);
+    };
+    const int m = (int)last.size();
+    if (m >= 3) {
+        const std::vector<int32_t> &a = last[m - 3], &b = last[m - 2], &c = last[m - 1];
+        const int d = c[0] - b[0];
+        bool periodic = true;
+        for (int v = 0; v < n && periodic; ++v) periodic = c[v] - b[v] == d && b[v] - a[v] == d;
+        if (periodic && take(b, d)) return true;
     }
-    // No period of one sweep: modulo schedules of decreasing length, from one step below the
-    // single-sweep count down to the width bound, keeping the last that works (a failure ends
-    // the search: shorter ones rarely work where a longer one did not, and each try costs
-    // passes over the spins).
+    int most = 0;
+    for (int k = 1; k < m; ++k)
+        for (int v = 0; v < n; ++v) most = std::max(most, last[k][v] - last[k - 1][v]);
+    for (int len = most; len <= most + 1; ++len)
+        for (int k = m - 1; k >= std::max(0, m - 4); --k)
+            if (take(last[k], len)) return true;
+    // Modulo schedules of decreasing length, from one step below the single-sweep count down
+    // to the width bound, keeping the last that works (a failure ends the search: shorter ones
+    // rarely work where a longer one did not, and each try costs passes over the spins).
     const int lo = std::max(1, cap ? (n + (int)cap - 1) / (int)cap : 1);
     std::vector<int32_t> t;
     int found = 0;
