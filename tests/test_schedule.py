@@ -91,7 +91,9 @@ def test_shuffled_order_changes_trajectories():
 @pytest.mark.parametrize("n,cap,step_cap,must", [(256, 32, 32, True), (512, 32, 64, True),
                                                  (1024, 32, 64, True), (2048, 32, 64, False),
                                                  (1024, 32, 96, False), (1024, 32, 128, False),
-                                                 (2048, 32, 128, False), (300, 7, 40, False),
+                                                 (2048, 32, 128, False), (544, 32, 64, False),
+                                                 (640, 32, 64, False), (900, 32, 64, False),
+                                                 (300, 7, 40, False),
                                                  (96, 32, 16, False)])
 def test_body_replays_the_sequential_sweeps(n, cap, step_cap, must):
     """Symbolic replay of the cross-sweep body over a chunk of sweeps [3, 10): iterations 3 .. 10,
