@@ -1179,6 +1179,29 @@ struct ScratchLease {
     }
 };
 
+// Batches run an instance whose tiles read their records from global memory in its gauge
+// where one exists (every coupling +1, three fewer operations per task: measured 3-7 % faster
+// at N = 512-1024; with records in LDS the gauged kernel measured slower, so those keep the
+// couplings). Finding the gauge costs up to n^3/128 word operations, once per instance: done
+// for n <= 512, for runs of 2^36 clone-spin updates or more, or with XS_PLACE_ROWS; otherwise
+// a gauge found earlier is used.
+void choose_gauge(std::vector<xs::InstDev> &h, const xs_instance *const *insts,
+                  const xs_run_config *cfgs, int count) {
+    for (int k = 0; k < count; ++k) {
+        const xs_instance *I = insts[k];
+        xs::InstDev &d = h[k];
+        d.j0 = 0;
+        if (!d.rec_global) continue;
+        std::lock_guard<std::mutex> lock(I->mu);
+        if (I->gauge_state == 0) {
+            const double upd = 64.0 * d.n_words * d.n * (double)(d.t_stop - d.t_cur);
+            if (I->n <= 512 || upd >= 68719476736.0 || (cfgs[k].flags & XS_PLACE_ROWS))
+                I->gauge_state = solve_gauge(*I, I->gauge) ? 1 : -1;
+        }
+        d.j0 = I->gauge_state == 1 ? 1u : 0u;
+    }
+}
+
 // A batch run as persistent work-queue launches (qg_queue_run): one launch per epoch of up to
 // epoch_chunks chunks of every unfinished instance, instead of a launch per chunk and launch
 // shape.
@@ -1291,24 +1314,7 @@ xs_status plan_queue(std::vector<xs::InstDev> &h_io, const xs_instance *const *i
         for (uint32_t b0 = 0; b0 < nb; b0 += d.tile_blocks) qp.tiles.push_back(make_uint2(k, b0));
         d.wg_threads = T;
     }
-    // Persistent launches run an instance whose tiles read their records from global memory
-    // in its gauge where one exists (every coupling +1, three fewer operations per task:
-    // measured 3-7 % faster at N = 512-1024; with records in LDS the gauged kernel measured
-    // slower, so those keep the couplings). Finding the gauge costs up to n^3/128 word
-    // operations, once per instance: done for n <= 512, for runs of 2^36 clone-spin updates or
-    // more, or with XS_PLACE_ROWS; otherwise a gauge found earlier is used.
-    for (int k = 0; k < count; ++k) {
-        const xs_instance *I = insts[k];
-        xs::InstDev &d = h[k];
-        if (!d.rec_global) continue;
-        std::lock_guard<std::mutex> lock(I->mu);
-        if (I->gauge_state == 0) {
-            const double upd = 64.0 * d.n_words * d.n * (double)(d.t_stop - d.t_cur);
-            if (I->n <= 512 || upd >= 68719476736.0 || (cfgs[k].flags & XS_PLACE_ROWS))
-                I->gauge_state = solve_gauge(*I, I->gauge) ? 1 : -1;
-        }
-        d.j0 = I->gauge_state == 1 ? 1u : 0u;
-    }
+    choose_gauge(h, insts, cfgs, count);
     qp.threads = T;
     qp.met = met;
     qp.lds = lds;
@@ -1349,7 +1355,10 @@ xs_status run_batch(int32_t count, const xs_instance *const *insts, const xs_run
         st = plan_queue(h, insts, cfgs, count, device, fixed ? opt.fixed_bytes / 2 : SIZE_MAX,
                         qp);
         if (st != XS_OK) return st;
-        if (qp.on) tiles.swap(qp.tiles);
+        if (qp.on)
+            tiles.swap(qp.tiles);
+        else
+            choose_gauge(h, insts, cfgs, count);  // the launch per chunk runs gauges too
         if (!fixed) {
             st = attach_tables(h, insts, count, device);
             if (st != XS_OK) return st;

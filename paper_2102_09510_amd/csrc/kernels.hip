@@ -705,7 +705,11 @@ __global__ __launch_bounds__(NT) void qg_chunk(InstDev *__restrict__ insts,
     const uint32_t t0 = ld_dev(&I->t_cur);
     const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
     if (t0 >= t1) return;
-    tile_chunk<NT, CW, GR, MET, false>(I, tile.y, t0, t1);
+    // the gauge is used with records in global memory only (the host sets it so)
+    if (GR && I->gauge)
+        tile_chunk<NT, CW, GR, MET, true>(I, tile.y, t0, t1);
+    else
+        tile_chunk<NT, CW, GR, MET, false>(I, tile.y, t0, t1);
 }
 
 // ------------------------------------------------------------------------------ control
@@ -829,15 +833,17 @@ __device__ uint32_t queue_pop(QueueDev *Q, uint32_t gen) {
     }
 }
 
-// The last tile of an instance's chunk [.., t1): advance the instance, end it at its budget or
-// (stop-on-first) once a ground state was seen, and reserve slots for its next chunk while it
-// may run more in this launch. Returns the first reserved slot, or kNoItem.
-__device__ uint32_t queue_decide(InstDev *I, QueueDev *Q, uint32_t t1) {
+// The last tile of an instance's item (nrun chunks ending at t1) to arrive: advance the
+// instance, end it at its budget or (stop-on-first) once a ground state was seen, and reserve
+// slots for its next item while it may run more chunks in this launch. Returns the first
+// reserved slot, or kNoItem.
+__device__ uint32_t queue_decide(InstDev *I, QueueDev *Q, uint32_t t1, uint32_t nrun) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every tile's hits
     st_dev(&I->arrived, 0u);
     st_dev(&I->t_cur, t1);
     const bool stop = t1 >= I->t_stop || ((I->flags & XS_STOP_ON_FIRST) && ld_dev(&I->hit));
-    const uint32_t left = ld_dev(&I->epoch_left) - 1u;
+    const uint32_t el = ld_dev(&I->epoch_left);
+    const uint32_t left = el > nrun ? el - nrun : 0u;
     st_dev(&I->epoch_left, left);
     if (stop) {
         st_dev(&I->done, 1u);
@@ -876,22 +882,37 @@ __global__ __launch_bounds__(NT) void qg_queue_run(InstDev *__restrict__ insts,
         const uint2 tile = tiles[item];
         InstDev *I = insts + tile.x;
         const uint32_t t0 = ld_dev(&I->t_cur);
-        const uint32_t t1 = min(t0 + I->chunk, I->t_stop);
+        // An instance that does not stop at its first ground state runs to its budget whatever
+        // its tiles find, and its tiles never wait for each other: a tile runs all the chunks
+        // the instance may still run in this launch back to back, as one item with one
+        // arrival. With stop-on-first every tile must end at the same chunk, so an item is one
+        // chunk and the last arrival decides.
+        const uint32_t nrun =
+            (I->flags & XS_STOP_ON_FIRST) ? 1u : max(ld_dev(&I->epoch_left), 1u);
+        const uint32_t t1 = (uint32_t)min((uint64_t)t0 + (uint64_t)nrun * I->chunk,
+                                          (uint64_t)I->t_stop);
         // the gauge is used with records in global memory only (the host sets it so)
         const bool gr = I->grec != nullptr, j0 = I->gauge != nullptr;
-        if (I->col_bytes == 16) {
-            if (gr) {
-                if (j0) tile_chunk<NT, 16, true, MET, true>(I, tile.y, t0, t1);
-                else tile_chunk<NT, 16, true, MET, false>(I, tile.y, t0, t1);
+        for (uint32_t tc = t0; tc < t1; tc += I->chunk) {
+            const uint32_t te = min(tc + I->chunk, t1);
+            // (the previous chunk's write-back read the LDS, so wait for it before the next
+            // chunk stages its tables; each chunk stages the rows again: keeping them in LDS
+            // measured 1.3 % slower)
+            if (tc != t0) __syncthreads();
+            if (I->col_bytes == 16) {
+                if (gr) {
+                    if (j0) tile_chunk<NT, 16, true, MET, true>(I, tile.y, tc, te);
+                    else tile_chunk<NT, 16, true, MET, false>(I, tile.y, tc, te);
+                } else {
+                    tile_chunk<NT, 16, false, MET, false>(I, tile.y, tc, te);
+                }
             } else {
-                tile_chunk<NT, 16, false, MET, false>(I, tile.y, t0, t1);
-            }
-        } else {
-            if (gr) {
-                if (j0) tile_chunk<NT, 8, true, MET, true>(I, tile.y, t0, t1);
-                else tile_chunk<NT, 8, true, MET, false>(I, tile.y, t0, t1);
-            } else {
-                tile_chunk<NT, 8, false, MET, false>(I, tile.y, t0, t1);
+                if (gr) {
+                    if (j0) tile_chunk<NT, 8, true, MET, true>(I, tile.y, tc, te);
+                    else tile_chunk<NT, 8, true, MET, false>(I, tile.y, tc, te);
+                } else {
+                    tile_chunk<NT, 8, false, MET, false>(I, tile.y, tc, te);
+                }
             }
         }
         // Release this tile's state and first hits to the device before its arrival. Every
@@ -901,7 +922,7 @@ __global__ __launch_bounds__(NT) void qg_queue_run(InstDev *__restrict__ insts,
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t push = kNoItem;
-            if (atomicAdd(&I->arrived, 1u) + 1u == I->ntiles) push = queue_decide(I, Q, t1);
+            if (atomicAdd(&I->arrived, 1u) + 1u == I->ntiles) push = queue_decide(I, Q, t1, nrun);
             s_push = push;
         }
         __syncthreads();
