@@ -46,7 +46,8 @@ def test_header_constants_match_the_binding():
     text = open(os.path.join(ROOT, "include", "xorsat.h")).read()
     defs = {m.group(1): int(m.group(2), 0)
             for m in re.finditer(r"#define\s+(XS_[A-Z_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text)}
-    for name in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_PER_CHUNK", "XS_MAX_N",
+    for name in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_PER_CHUNK",
+                 "XS_ONE_SWEEP_STEPS", "XS_MAX_N",
                  "XS_CLONE_QUANTUM", "XS_MAX_CLONES", "XS_TUNE_MAX_TRIALS",
                  "XS_NOALLOC_SCRATCH_BYTES"):
         assert defs[name] == getattr(xorsat, name), name
@@ -55,10 +56,36 @@ def test_header_constants_match_the_binding():
     # The largest clone count is a whole number of quanta whose last index is below INT32_MAX.
     assert defs["XS_MAX_CLONES"] % defs["XS_CLONE_QUANTUM"] == 0
     assert defs["XS_MAX_CLONES"] - 1 < 2**31 - 1 < defs["XS_MAX_CLONES"] + defs["XS_CLONE_QUANTUM"]
-    flags = [defs[k] for k in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_PER_CHUNK")]
-    assert len(set(flags)) == 4 and all(f & (f - 1) == 0 for f in flags)
+    flags = [defs[k] for k in ("XS_STOP_ON_FIRST", "XS_RESUME", "XS_PLACE_ROWS", "XS_PER_CHUNK",
+                               "XS_ONE_SWEEP_STEPS")]
+    assert len(set(flags)) == 5 and all(f & (f - 1) == 0 for f in flags)
     cfg = xorsat.make_config(n_clones=256, seed=1, stop_on_first=False, place_rows=True)
     assert cfg.flags == xorsat.XS_PLACE_ROWS
+    cfg = xorsat.make_config(n_clones=256, seed=1, stop_on_first=False, one_sweep_steps=True)
+    assert cfg.flags == xorsat.XS_ONE_SWEEP_STEPS
+
+
+def test_body_query_validation():
+    """xs_instance_get_body: step caps outside [1, 65535] are XS_EINVAL; an instance whose
+    schedule has no cross-sweep body for a cap gives XS_ENOTFOUND (None from the binding)."""
+    import numpy as np
+    from paper_2102_09510_amd.instances import planted_instance
+    inst = planted_instance(20, 5120)
+    h = xorsat.Instance(inst.tri, inst.J)
+    lib = xorsat.load()
+    buf = np.zeros(h.n + 1, dtype=np.int32)
+    late = np.zeros(h.n, dtype=np.uint8)
+    steps = ctypes.c_int32()
+    for cap in (0, 65536):
+        st = lib.xs_instance_get_body(h.handle, cap, buf.ctypes.data, buf.ctypes.data,
+                                      late.ctypes.data, ctypes.byref(steps))
+        assert st == xorsat.XS_STATUS_CODES["XS_EINVAL"], cap
+    assert h.body(64) is None  # five colour classes: no shorter overlapped schedule
+    big = planted_instance(1024, 5121)
+    hb = xorsat.Instance(big.tri, big.J)
+    order, off, lt = hb.body(64)
+    assert sorted(order.tolist()) == list(range(1024)) and off[-1] == 1024
+    assert len(off) - 1 < len(hb.schedule(64)[1]) - 1 and lt.max() == 1
 
 
 def test_struct_layouts():
