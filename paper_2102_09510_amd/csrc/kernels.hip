@@ -340,11 +340,52 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
     col_store<CW>(self, y);
 }
 
+// The steps of one sweep when every step holds exactly P = NT >> lcol positions (n = steps x
+// P, as the cross-sweep body at its width bound gives): each thread has one task per step, at
+// position c * P + tpos, so no step bound is read and no thread is idle; the step's records
+// start at a uniform address.
+template <int NT, int CW, bool GR, bool kAcc, bool MET, bool J0>
+__device__ __forceinline__ void sweep_full(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
+    constexpr uint32_t E = MET ? 2 : 1;
+    const uint32_t P = NT >> T.lcol;
+    const uint32_t ra0 = T.lds0 + rb + E * T.rbo;
+    if constexpr (GR) {
+        // This thread's record of each step, fetched one step ahead into two registers used in
+        // turn (no copy at the loop's back edge, so a step waits only for the older fetch); a
+        // fetch beyond the last step reads the last step's record again.
+        const GLOBAL_AS u32x4 *rp = (const GLOBAL_AS u32x4 *)T.grec + T.tpos;
+        const uint32_t last = T.nsteps - 1;
+        auto fetch = [&](uint32_t c) { return rp[(c < last ? c : last) * P]; };
+        u32x4 a = fetch(0);
+        for (uint32_t c = 0; c < T.nsteps; c += 2) {
+            const u32x4 b = fetch(c + 1);
+            __syncthreads();
+            update_task<CW, kAcc, MET, J0>(T, make_uint4(a.x, a.y, a.z, a.w),
+                                           ra0 + E * ((c * P) << T.lB), acc);
+            if (c + 1 >= T.nsteps) break;
+            a = fetch(c + 2);
+            __syncthreads();
+            update_task<CW, kAcc, MET, J0>(T, make_uint4(b.x, b.y, b.z, b.w),
+                                           ra0 + E * (((c + 1) * P) << T.lB), acc);
+        }
+    } else {
+        for (uint32_t c = 0; c < T.nsteps; ++c) {
+            const uint4 r0 = lds_rec(c * P + T.tpos);
+            __syncthreads();
+            update_task<CW, kAcc, MET, J0>(T, r0, ra0 + E * ((c * P) << T.lB), acc);
+        }
+    }
+}
+
 // The steps of one sweep, a barrier before each (the first one also publishes the sweep's
 // acceptance bits and the previous sweep's last writes). Records and step bounds are
 // read-only, so each thread fetches its first record of a step before that step's barrier.
 template <int NT, int CW, bool GR, bool kAcc, bool MET, bool J0>
 __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc)[CW / 4]) {
+    if (T.n == T.nsteps * (NT >> T.lcol)) {  // every step full
+        sweep_full<NT, CW, GR, kAcc, MET, J0>(T, rb, acc);
+        return;
+    }
     constexpr uint32_t E = MET ? 2 : 1;  // bytes per acceptance entry
     // Step bounds come from the tile's LDS copy of the step table, read (the same address in
     // every lane) right after each barrier: an LDS read returns in order with the task's reads,
