@@ -775,7 +775,7 @@ def headline(args, xorsat, torch):
     clones = args.clones or H["clones"]
     budget = args.budget if args.budget is not None else H["budget"]
     stop = H["stop"] and args.accept_thr0 == 0
-    place = args.place_rows or wl == "steady"
+    place = args.place_rows or wl in ("steady", "batched")
     chunk = args.chunk or 100
     insts = [planted_instance(n, gen_seed(H["config"], k)) for k in range(count)]
     handles = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]

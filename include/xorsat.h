@@ -52,11 +52,12 @@ typedef int32_t xs_status;
 #define XS_STOP_ON_FIRST 0x1u /* stop at the end of the first chunk after which some clone
                                  is in a ground state (E = -N) */
 #define XS_RESUME 0x2u        /* state already holds the start configuration (checkpoint)     */
-#define XS_PLACE_ROWS 0x4u    /* build the LDS row placement of tiles under eight blocks even
-                                 for a short run (speed only; a host cost of a few µs per spin,
-                                 once per instance and tiling, kept for later runs). Without
-                                 it, runs of fewer than 2^32 clone-sweeps use the placement
-                                 only if it already exists. */
+#define XS_PLACE_ROWS 0x4u    /* build the LDS row placement of tiles under eight blocks with
+                                 its full search, even for a short run (speed only; a host
+                                 cost of about 0.4 ms per spin, once per instance and tiling,
+                                 kept for later runs). Without it, runs of fewer than 2^32
+                                 clone-sweeps use a placement only if one already exists, and
+                                 longer runs build one with a search sized to the run. */
 #define XS_PER_CHUNK 0x8u     /* launch every chunk separately (one launch per launch shape,
                                  then a decision kernel) instead of the persistent work-queue
                                  launch; speed only. A batch runs per chunk if any of its

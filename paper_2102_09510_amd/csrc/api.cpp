@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/xorsat.h"
+#include "place.h"
 #include "xs_host.h"
 
 namespace {
@@ -83,176 +84,6 @@ void partition(xs_instance &I) {
         I.max_class = std::max(I.max_class, size);
         ++pass;
     }
-}
-
-// LDS passes of a row access (measured on gfx950 with a probe of lane pairs and bank
-// conflicts): ds_read_b64 serves lanes 0-31 and 32-63 in two passes; ds_read_b128 serves four
-// passes of 16 lanes, lanes with the same l >> 5 and the same parity of the bits of
-// (l >> 2) & 7 together; a ds_read_b32 is taken as one pass. Within a pass, lanes that read
-// different rows of 32 * B < 256 bytes collide when they read the same column of rows equal
-// modulo S = 8 / B. RowModel lists, for a tile of B blocks read in CW-byte columns, the sets of
-// positions (relative to the first position of a wave, which takes P consecutive positions of
-// a step) whose rows must differ modulo S for the access to be free of conflicts.
-struct RowModel {
-    uint32_t S = 1, P = 1;
-    std::vector<std::vector<uint8_t>> sets;
-};
-
-RowModel row_model(uint32_t B, uint32_t CW) {
-    RowModel m;
-    if (B == 0 || B >= 8) return m;
-    m.S = 8 / B;
-    const uint32_t ncol = 32 * B / CW;
-    m.P = 64 / ncol;
-    std::map<std::pair<uint32_t, uint32_t>, std::vector<uint8_t>> by;  // (pass, column)
-    for (uint32_t l = 0; l < 64; ++l) {
-        const uint32_t pos = l / ncol, col = l % ncol;
-        uint32_t pass = 0;
-        if (CW == 16) pass = (l >> 5) * 2 + (__builtin_popcount((l >> 2) & 7) & 1);
-        else if (CW == 8) pass = l >> 5;
-        auto &v = by[{pass, col}];
-        if (std::find(v.begin(), v.end(), (uint8_t)pos) == v.end()) v.push_back((uint8_t)pos);
-    }
-    for (auto &kv : by)
-        if (kv.second.size() > 1 &&
-            std::find(m.sets.begin(), m.sets.end(), kv.second) == m.sets.end())
-            m.sets.push_back(kv.second);
-    return m;
-}
-
-// LDS row placement for one-, two- and four-block tiles. Each role (own row, the six partners)
-// of each position set of each wave's share of a step (RowModel) is a group of rows that should
-// fall on different residues modulo S. Starting from row = spin, a local search picks a random
-// group with an excess (rows on its fullest residue minus one), and trades the residues of one
-// of its rows on the fullest residue and a random row on its emptiest one when that does not
-// raise the summed excess of the groups the two rows are in; the rows of each residue are then
-// numbered in spin order, so the map is a permutation of [0, n) (the residue counts never
-// change). The search is seeded, so the map is a fixed function of the schedule.
-std::vector<uint16_t> place_rows(const xsh::HostSched &hs, const std::vector<int32_t> &roles,
-                                 int n, const RowModel &m) {
-    const uint32_t S = m.S;
-    // groups: per step, per wave's share, per position set, per role
-    std::vector<int32_t> goff(1, 0), grow;
-    for (size_t st = 0; st + 1 < hs.off.size(); ++st)
-        for (int g = hs.off[st]; g < hs.off[st + 1]; g += (int)m.P)
-            for (const auto &set : m.sets)
-                for (int k = 0; k < 7; ++k) {
-                    const size_t first = grow.size();
-                    for (uint8_t d : set) {
-                        const int p = g + d;
-                        if (p >= hs.off[st + 1]) continue;
-                        const int32_t r = roles[7 * (size_t)hs.order[p] + k];
-                        if (std::find(grow.begin() + first, grow.end(), r) == grow.end())
-                            grow.push_back(r);  // a row read twice in one pass is a broadcast
-                    }
-                    if (grow.size() - first < 2) {
-                        grow.resize(first);  // one row alone cannot collide
-                        continue;
-                    }
-                    goff.push_back((int32_t)grow.size());
-                }
-    const size_t ng = goff.size() - 1;
-    if (ng == 0) {
-        std::vector<uint16_t> row(n);
-        for (int r = 0; r < n; ++r) row[r] = (uint16_t)r;
-        return row;
-    }
-    std::vector<int32_t> moff(n + 1, 0), memb;  // groups of each row
-    for (size_t q = 0; q < ng; ++q)
-        for (int32_t j = goff[q]; j < goff[q + 1]; ++j) ++moff[grow[j] + 1];
-    for (int r = 0; r < n; ++r) moff[r + 1] += moff[r];
-    memb.assign(moff[n], 0);
-    {
-        std::vector<int32_t> fillp(moff.begin(), moff.end() - 1);
-        for (size_t q = 0; q < ng; ++q)
-            for (int32_t j = goff[q]; j < goff[q + 1]; ++j) memb[fillp[grow[j]]++] = (int32_t)q;
-    }
-    // residue of each row; per group, the number of its rows on each residue (one byte each)
-    std::vector<uint8_t> col(n);
-    std::vector<uint64_t> cnt(ng, 0);
-    for (int r = 0; r < n; ++r) col[r] = (uint8_t)(r % S);
-    for (size_t q = 0; q < ng; ++q)
-        for (int32_t j = goff[q]; j < goff[q + 1]; ++j) cnt[q] += 1ull << (8 * col[grow[j]]);
-    auto most = [](uint64_t c) {
-        uint64_t m = 0;
-        for (int k = 0; k < 64; k += 8) m = std::max(m, (c >> k) & 0xFF);
-        return (int)m;
-    };
-    std::vector<uint8_t> top(ng);  // the fullest residue's count of each group
-    for (size_t q = 0; q < ng; ++q) top[q] = (uint8_t)most(cnt[q]);
-    // Change of a group's fullest count when one of its rows moves from residue f to t.
-    auto shift = [](uint64_t c, int m, int f, int t) {
-        const int nt = (int)((c >> (8 * t)) & 0xFF) + 1;
-        if (nt > m) return 1;
-        if ((int)((c >> (8 * f)) & 0xFF) < m || nt == m) return 0;
-        const uint64_t x = c ^ (0x0101010101010101ull * (uint64_t)m);  // zero bytes: count m
-        const uint64_t z = ~(((x & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full) | x) &
-                           0x8080808080808080ull;
-        return __builtin_popcountll(z) == 1 ? -1 : 0;
-    };
-    // Row r moving from residue `from` to `to`, in its groups that do not also hold row
-    // `other` (there the two rows trade residues and the counts stay): the change of the cost,
-    // and with `apply` the new counts.
-    auto move = [&](int r, int other, int from, int to, bool apply) {
-        int d = 0;
-        const uint64_t step = (1ull << (8 * to)) - (1ull << (8 * from));
-        const int32_t *o = memb.data() + moff[other], *oe = memb.data() + moff[other + 1];
-        for (int32_t j = moff[r]; j < moff[r + 1]; ++j) {
-            const int32_t q = memb[j];
-            while (o < oe && *o < q) ++o;
-            if (o < oe && *o == q) continue;
-            const int e = shift(cnt[q], top[q], from, to);
-            d += e;
-            if (apply) {
-                cnt[q] += step;
-                top[q] = (uint8_t)(top[q] + e);
-            }
-        }
-        return d;
-    };
-    uint64_t rng = 0x9E3779B97F4A7C15ull ^ (uint64_t)n;
-    auto next = [&]() {  // xorshift64*
-        rng ^= rng >> 12;
-        rng ^= rng << 25;
-        rng ^= rng >> 27;
-        return (uint32_t)((rng * 0x2545F4914F6CDD1Dull) >> 32);
-    };
-    // rows of each residue, and each row's place in its list
-    std::vector<std::vector<int32_t>> of(S);
-    std::vector<int32_t> at(n);
-    for (int r = 0; r < n; ++r) {
-        at[r] = (int32_t)of[col[r]].size();
-        of[col[r]].push_back(r);
-    }
-    // Proposals: a row on the fullest residue of a random group that has an excess, traded
-    // with a random row of the emptiest residue of that group.
-    for (int it = 0; it < 8 * n; ++it) {
-        const size_t q = next() % ng;
-        const uint64_t c = cnt[q];
-        const int mx = top[q];
-        if (mx <= 1) continue;
-        int hi = -1, lo = 0;
-        for (uint32_t k = 0; k < S; ++k) {
-            const int v = (int)((c >> (8 * k)) & 0xFF);
-            if (hi < 0 && v == mx) hi = (int)k;
-            if (v < (int)((c >> (8 * lo)) & 0xFF)) lo = (int)k;
-        }
-        int a = -1;
-        for (int32_t j = goff[q]; j < goff[q + 1] && a < 0; ++j)
-            if (col[grow[j]] == hi) a = grow[j];
-        const int b = of[lo][next() % of[lo].size()];
-        if (move(a, b, hi, lo, false) + move(b, a, lo, hi, false) > 0) continue;
-        move(a, b, hi, lo, true);
-        move(b, a, lo, hi, true);
-        col[a] = (uint8_t)lo;
-        col[b] = (uint8_t)hi;
-        std::swap(of[hi][at[a]], of[lo][at[b]]);
-        std::swap(at[a], at[b]);
-    }
-    std::vector<uint16_t> row(n);
-    std::vector<int> rank(S, 0);
-    for (int r = 0; r < n; ++r) row[r] = (uint16_t)(col[r] + S * rank[col[r]]++);
-    return row;
 }
 
 // The rules of a body, checked for offsets tau and iteration length ii (see make_body).
@@ -445,7 +276,7 @@ bool make_body(const xs_instance &I, uint32_t cap, int plain_steps,
 // solve_gauge, where every coupling is +1). body: also build the cross-sweep body (make_body)
 // where one exists; the rows are then placed for the body's steps, which untracked chunks run.
 xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uint32_t CW,
-                             bool j0, bool body) {
+                             bool j0, bool body, int effort = 0) {
     const int n = I.n;
     std::vector<int32_t> inc(3 * (size_t)n), deg(n, 0), pos(n), step(n, 0), fill;
     for (int t = 0; t < n; ++t)
@@ -508,15 +339,25 @@ xsh::HostSched make_schedule(const xs_instance &I, uint32_t cap, uint32_t B, uin
             if (I.J[t] < 0 && !j0) jbits[i] |= (uint16_t)(1u << q);
         }
     }
+    // Rows placed for the steps the hot loop runs (the body's, where there is one); the
+    // placement also re-orders those steps' spins and each spin's partner slots (coupling bits
+    // follow their triplets), none of which changes a result.
     const RowModel model = row_model(B, CW);
     if (!model.sets.empty() && n >= 2 * (int)model.S) {
-        if (hs.border.empty()) {
-            hs.rowmap = place_rows(hs, roles, n, model);
-        } else {
-            xsh::HostSched view;  // the body's steps, which the hot loop runs
-            view.order = hs.border;
-            view.off = hs.boff;
-            hs.rowmap = place_rows(view, roles, n, model);
+        std::vector<int32_t> &ord = hs.border.empty() ? hs.order : hs.border;
+        const Placement pl =
+            place_rows(ord, hs.border.empty() ? hs.off : hs.boff, roles, n, model, effort);
+        hs.rowmap = pl.row;
+        ord = pl.order;
+        for (int i = 0; i < n; ++i) {
+            const int sl = pl.slots[i];
+            if (!sl) continue;
+            int32_t *r = &roles[7 * (size_t)i];
+            const int32_t was[7] = {r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+            for (int k = 1; k < 7; ++k) r[k] = was[slot_source(sl, k)];
+            const uint16_t jb = jbits[i];
+            jbits[i] = 0;
+            for (int q = 0; q < 3; ++q) jbits[i] |= (uint16_t)(((jb >> kTripOrder[sl % 6][q]) & 1u) << q);
         }
     }
     // Records in schedule order: the LDS rows of the spin and of its six partners, then
@@ -632,8 +473,10 @@ uint32_t step_cap(const xs::InstDev &d) {
 
 // Schedules are kept per (step cap, placement layout, coupling gauge, body); caps stay below
 // 2^16. Layout 0: rows not placed; else tile blocks | column bytes << 8 (below bit 30).
-uint32_t sched_key(uint32_t cap, uint32_t layout, bool j0 = false, bool body = false) {
-    return cap | layout << 16 | (body ? 1u << 30 : 0u) | (j0 ? 1u << 31 : 0u);
+uint32_t sched_key(uint32_t cap, uint32_t layout, bool j0 = false, bool body = false,
+                   bool full = false) {
+    return cap | layout << 16 | (full ? 1u << 29 : 0u) | (body ? 1u << 30 : 0u) |
+           (j0 ? 1u << 31 : 0u);
 }
 
 // The cross-sweep body runs where records are read from global memory and w0 = 0 (ground
@@ -645,10 +488,13 @@ bool wants_body(const xs::InstDev &d) {
 uint32_t place_layout(uint32_t B, uint32_t CW) { return B < 8 ? B | CW << 8 : 0u; }
 
 // Clone-sweeps (clones x sweeps left) from which a run builds the row placement. The search
-// costs a few µs of host time per spin and saves about 5 % of the sweep time, both in
-// proportion to N, so the break-even is a clone-sweep count; batches build their instances'
-// schedules on several host threads at once, which divides the cost (host_threads()).
+// costs about 0.5 µs of host time per spin and unit of effort (place_rows) and saves 5-10 % of
+// the sweep time, both in proportion to N, so its effort is set from the clone-sweeps: a run
+// spends at most about a tenth of its sweep time on it, and a run that asks for the placement
+// (XS_PLACE_ROWS) gets the full effort. Batches build their instances' schedules on several host
+// threads at once, which divides the cost (host_threads()).
 constexpr uint64_t kPlaceMinWork = 1ull << 32;
+constexpr int kPlaceEffort = 800;
 
 // Host threads that build the schedules of a batch.
 uint32_t host_threads() {
@@ -660,6 +506,7 @@ uint32_t host_threads() {
 struct SchedParams {
     uint32_t key, cap, layout;
     bool j0, body;
+    int effort;  // of the row placement search
 };
 
 // The schedule a descriptor's launch uses: its step cap, row placement and body. The row
@@ -673,10 +520,22 @@ SchedParams sched_params(const xs_instance *I, const xs::InstDev &d, uint32_t bu
     sp.j0 = d.j0 != 0;
     sp.body = wants_body(d);
     const uint64_t work = (uint64_t)d.n_words * 64u * (d.t_stop - d.t_cur);
-    if (sp.layout && work < kPlaceMinWork / std::max(builders, 1u) &&
-        !(d.flags & XS_PLACE_ROWS) && !I->sched.count(sched_key(sp.cap, sp.layout, sp.j0, sp.body)))
-        sp.layout = 0;
-    sp.key = sched_key(sp.cap, sp.layout, sp.j0, sp.body);
+    const uint32_t nb = std::max(builders, 1u);
+    bool full = false;
+    sp.effort = 0;
+    if (sp.layout) {
+        // a full placement serves every later run; a run that asks for one builds it
+        full = (d.flags & XS_PLACE_ROWS) ||
+               I->sched.count(sched_key(sp.cap, sp.layout, sp.j0, sp.body, true));
+        if (full)
+            sp.effort = kPlaceEffort;
+        else if (work >= kPlaceMinWork / nb ||
+                 I->sched.count(sched_key(sp.cap, sp.layout, sp.j0, sp.body)))
+            sp.effort = (int)std::min<uint64_t>(std::max<uint64_t>(work * nb >> 29, 8), kPlaceEffort);
+        else
+            sp.layout = 0;
+    }
+    sp.key = sched_key(sp.cap, sp.layout, sp.j0, sp.body, full);
     return sp;
 }
 
@@ -689,7 +548,7 @@ const xsh::HostSched &host_sched(const xs_instance *I, const xs::InstDev &d, uin
     if (hit == I->sched.end())
         hit = I->sched
                   .emplace(sp.key, make_schedule(*I, sp.cap, sp.layout & 0xFF, sp.layout >> 8,
-                                                 sp.j0, sp.body))
+                                                 sp.j0, sp.body, sp.effort))
                   .first;
     *key_out = sp.key;
     return hit->second;
@@ -723,7 +582,7 @@ uint32_t prebuild_schedules(const std::vector<xs::InstDev> &h, const xs_instance
         for (size_t j; (j = next.fetch_add(1)) < jobs.size();) {
             Job &b = jobs[j];
             b.hs = make_schedule(*b.I, b.sp.cap, b.sp.layout & 0xFF, b.sp.layout >> 8, b.sp.j0,
-                                 b.sp.body);
+                                 b.sp.body, b.sp.effort);
         }
     };
     std::vector<std::thread> pool;
