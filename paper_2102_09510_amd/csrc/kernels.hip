@@ -351,11 +351,33 @@ __device__ __forceinline__ void sweep_full(const Tile &T, uint32_t rb, uint32_t 
     const uint32_t ra0 = T.lds0 + rb + E * T.rbo;
     if constexpr (GR) {
         // This thread's record of each step, fetched one step ahead into two registers used in
-        // turn (no copy at the loop's back edge, so a step waits only for the older fetch); a
-        // fetch beyond the last step reads the last step's record again.
+        // turn (no copy at the loop's back edge); a fetch beyond the last step reads the last
+        // step's record again. The step's records start at a uniform offset and this thread's
+        // lies a fixed offset further. With 8-byte columns the fetch is a raw buffer load over
+        // the tile's records (scalar resource and step offset, the thread's offset in a vector
+        // register that never changes), so no vector instruction forms a record address;
+        // resource word 3 = 0x00020000 (32-bit data format, no swizzle, as raw loads on this
+        // architecture family take it), the range the tile's n = steps x P records (a load
+        // beyond it would read zeros). With 16-byte columns the plain load measured faster.
+        const uint64_t gp = (uint64_t)(uintptr_t)T.grec;
+        // (readfirstlane returns a signed int: each half is taken as unsigned before widening,
+        // or a low half with bit 31 set would fill the high half with ones)
+        const uint32_t g_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(gp >> 32));
+        const uint32_t g_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gp);
+        const uint64_t g0 = (uint64_t)g_hi << 32 | g_lo;
+        const uint32_t stride = (uint32_t)__builtin_amdgcn_readfirstlane(P) * (uint32_t)sizeof(u32x4);
+        const uint32_t last = (uint32_t)__builtin_amdgcn_readfirstlane(T.nsteps) - 1;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(uintptr_t)g0, (short)0, (int)((last + 1) * stride), 0x00020000);
+        const int voff = (int)(T.tpos * (uint32_t)sizeof(u32x4));
         const GLOBAL_AS u32x4 *rp = (const GLOBAL_AS u32x4 *)T.grec + T.tpos;
-        const uint32_t last = T.nsteps - 1;
-        auto fetch = [&](uint32_t c) { return rp[(c < last ? c : last) * P]; };
+        auto fetch = [&](uint32_t c) -> u32x4 {
+            const uint32_t cc = c < last ? c : last;
+            if constexpr (CW == 8)
+                return __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (int)(cc * stride), 0);
+            else
+                return rp[cc * P];
+        };
         u32x4 a = fetch(0);
         for (uint32_t c = 0; c < T.nsteps; c += 2) {
             const u32x4 b = fetch(c + 1);
