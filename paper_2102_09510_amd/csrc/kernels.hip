@@ -287,17 +287,29 @@ __device__ __forceinline__ void accept_bits(const Tile &T, uint32_t t, uint32_t 
     const uint32_t b = T.tid & (T.B - 1);
     const uint64_t pz = (uint64_t)0xCD9E8D57u * (T.blk0 + b);
     const uint32_t t_k0 = t ^ T.key0, id_k1 = T.iid ^ T.key1;
-    for (uint32_t p = T.tid >> T.lB; p < T.n; p += NT >> T.lB) {
-        const uint32_t q = (p << T.lB) + b;
-        const uint32_t v = *(const LDS_AS uint16_t *)(uintptr_t)(T.lds0 + T.meta + (GR ? 2 : 16) * p);
+    const uint32_t base = T.lds0 + rb, dlate = rb_late - rb;  // absolute LDS addresses
+    constexpr uint32_t MS = GR ? 2 : 16, E = MET ? 2 : 1;  // bytes per meta, per entry
+    // position p: its meta at mp, its entry at ea (base + E * q, q = (p << lB) + b)
+    auto one = [&](uint32_t mp, uint32_t ea) {
+        const uint32_t v = *(const LDS_AS uint16_t *)(uintptr_t)mp;
         const uint32_t i = GR ? v & 0x7FFu : v & 0x1FFFu;  // spins < 2048 with records in global memory
         const uint4 o = philox10_draw(i, pz, t_k0, id_k1, T.key0, T.key1);
-        const uint32_t r = BODY && (v & 0x1000u) ? rb_late : rb;
+        // a late spin's bits go dlate = rb_late - rb further: bit 12 sign-extracted as a mask
+        if constexpr (BODY) ea += (uint32_t)__builtin_amdgcn_sbfe((int)v, 12, 1) & dlate;
         if constexpr (MET)
-            *reinterpret_cast<uint16_t *>(xs_lds + r + 2 * q) =
+            *(LDS_AS uint16_t *)(uintptr_t)ea =
                 (uint16_t)(draws_below(o, T.thr) | draws_below(o, T.thr0) << 8);
         else
-            xs_lds[r + q] = (uint8_t)draws_below(o, T.thr);
+            *(LDS_AS uint8_t *)(uintptr_t)ea = (uint8_t)draws_below(o, T.thr);
+    };
+    const uint32_t ps = NT >> T.lB, p0 = T.tid >> T.lB;  // positions per pass, the first
+    const uint32_t m0 = T.lds0 + T.meta + MS * p0, e0 = base + E * ((p0 << T.lB) + b);
+    if ((T.n & (ps - 1)) == 0) {
+        // every thread has n / ps positions: a uniform count and running addresses
+        const uint32_t k1 = (uint32_t)__builtin_amdgcn_readfirstlane(T.n >> (__builtin_ctz(NT) - T.lB));
+        for (uint32_t k = 0; k < k1; ++k) one(m0 + k * (MS * ps), e0 + k * (E * NT));
+    } else {
+        for (uint32_t p = p0, k = 0; p < T.n; p += ps, ++k) one(m0 + k * (MS * ps), e0 + k * (E * NT));
     }
 }
 
