@@ -352,6 +352,31 @@ __device__ __forceinline__ void update_task(const Tile &T, uint4 r, uint32_t ra,
     col_store<CW>(self, y);
 }
 
+// This thread's records as a raw buffer over the tile's n records (global memory): a scalar
+// resource, and this thread's position offset (tpos records) in a vector register that never
+// changes, so a step's fetch needs only a scalar offset and no vector instruction. Resource
+// word 3 = 0x00020000 (32-bit data format, no swizzle, as raw loads on this architecture family
+// take it); a fetch past the n records reads zeros, never faults.
+struct RecBuf {
+    __amdgpu_buffer_rsrc_t rs;
+    int voff;
+};
+__device__ __forceinline__ RecBuf rec_buf(const Tile &T) {
+    const uint64_t gp = (uint64_t)(uintptr_t)T.grec;
+    // (readfirstlane returns a signed int: each half is taken as unsigned before widening, or a
+    // low half with bit 31 set would fill the high half with ones)
+    const uint32_t g_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(gp >> 32));
+    const uint32_t g_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gp);
+    const uint32_t nb = (uint32_t)__builtin_amdgcn_readfirstlane(T.n) * (uint32_t)sizeof(u32x4);
+    return RecBuf{__builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)((uint64_t)g_hi << 32 | g_lo),
+                                                    (short)0, (int)nb, 0x00020000),
+                  (int)(T.tpos * (uint32_t)sizeof(u32x4))};
+}
+// The record of position p0 + tpos (p0 uniform).
+__device__ __forceinline__ u32x4 rec_fetch(const RecBuf &R, uint32_t p0) {
+    return __builtin_amdgcn_raw_buffer_load_b128(R.rs, R.voff, (int)(p0 * (uint32_t)sizeof(u32x4)), 0);
+}
+
 // The steps of one sweep when every step holds exactly P = NT >> lcol positions (n = steps x
 // P, as the cross-sweep body at its width bound gives): each thread has one task per step, at
 // position c * P + tpos, so no step bound is read and no thread is idle; the step's records
@@ -364,29 +389,16 @@ __device__ __forceinline__ void sweep_full(const Tile &T, uint32_t rb, uint32_t 
     if constexpr (GR) {
         // This thread's record of each step, fetched one step ahead into two registers used in
         // turn (no copy at the loop's back edge); a fetch beyond the last step reads the last
-        // step's record again. The step's records start at a uniform offset and this thread's
-        // lies a fixed offset further. With 8-byte columns the fetch is a raw buffer load over
-        // the tile's records (scalar resource and step offset, the thread's offset in a vector
-        // register that never changes), so no vector instruction forms a record address;
-        // resource word 3 = 0x00020000 (32-bit data format, no swizzle, as raw loads on this
-        // architecture family take it), the range the tile's n = steps x P records (a load
-        // beyond it would read zeros). With 16-byte columns the plain load measured faster.
-        const uint64_t gp = (uint64_t)(uintptr_t)T.grec;
-        // (readfirstlane returns a signed int: each half is taken as unsigned before widening,
-        // or a low half with bit 31 set would fill the high half with ones)
-        const uint32_t g_hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(gp >> 32));
-        const uint32_t g_lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gp);
-        const uint64_t g0 = (uint64_t)g_hi << 32 | g_lo;
-        const uint32_t stride = (uint32_t)__builtin_amdgcn_readfirstlane(P) * (uint32_t)sizeof(u32x4);
+        // step's record again. With 8-byte columns through the raw buffer (rec_buf); with
+        // 16-byte columns the plain load measured faster.
+        const RecBuf R = rec_buf(T);
         const uint32_t last = (uint32_t)__builtin_amdgcn_readfirstlane(T.nsteps) - 1;
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(uintptr_t)g0, (short)0, (int)((last + 1) * stride), 0x00020000);
-        const int voff = (int)(T.tpos * (uint32_t)sizeof(u32x4));
+        const uint32_t Pu = (uint32_t)__builtin_amdgcn_readfirstlane(P);
         const GLOBAL_AS u32x4 *rp = (const GLOBAL_AS u32x4 *)T.grec + T.tpos;
         auto fetch = [&](uint32_t c) -> u32x4 {
             const uint32_t cc = c < last ? c : last;
             if constexpr (CW == 8)
-                return __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (int)(cc * stride), 0);
+                return rec_fetch(R, cc * Pu);
             else
                 return rp[cc * P];
         };
@@ -427,6 +439,31 @@ __device__ __forceinline__ void sweep(const Tile &T, uint32_t rb, uint32_t (&acc
     const LDS_AS uint16_t *so = (const LDS_AS uint16_t *)(uintptr_t)(T.lds0 + T.stp);
     const uint32_t stride = NT >> T.lcol;  // positions between a thread's tasks of one step
     uint32_t cs = 0, ce = so[1];
+    if constexpr (GR && CW == 8) {
+        // The first round's record of a step is fetched through the raw buffer (rec_buf) at the
+        // end of the step before, by every thread (past the tile's records it reads zeros; such
+        // a record is unused): no vector instruction forms its address.
+        const RecBuf R = rec_buf(T);
+        u32x4 rn = rec_fetch(R, 0);
+        for (uint32_t c = 0; c < T.nsteps; ++c) {
+            const uint32_t ntask = (ce - cs) << T.lcol;
+            const u32x4 r0 = rn;
+            __syncthreads();
+            const uint32_t ce_next = so[c + 2];
+            const uint32_t ra = (T.lds0 + rb + E * (cs << T.lB)) + E * T.rbo;
+            if (T.tid < ntask)
+                update_task<CW, kAcc, MET, J0>(T, make_uint4(r0.x, r0.y, r0.z, r0.w), ra, acc);
+            const uint32_t rounds = (ntask - 1) / NT;
+            for (uint32_t k = 1; k <= rounds; ++k)
+                if (T.tid + k * NT < ntask)
+                    update_task<CW, kAcc, MET, J0>(T, rec_at<GR>(T, cs + T.tpos + k * stride),
+                                                   ra + E * ((k * stride) << T.lB), acc);
+            rn = rec_fetch(R, ce);
+            cs = ce;
+            ce = __builtin_amdgcn_readfirstlane(ce_next);
+        }
+        return;
+    }
     for (uint32_t c = 0; c < T.nsteps; ++c) {
         const uint32_t ntask = (ce - cs) << T.lcol;
         uint4 r0;  // read only by threads with a task
