@@ -54,7 +54,7 @@ typedef int32_t xs_status;
 #define XS_RESUME 0x2u        /* state already holds the start configuration (checkpoint)     */
 #define XS_PLACE_ROWS 0x4u    /* build the LDS row placement of tiles under eight blocks with
                                  its full search, even for a short run (speed only; a host
-                                 cost of about 0.4 ms per spin, once per instance and tiling,
+                                 cost of about 0.8 ms per spin, once per instance and tiling,
                                  kept for later runs). Without it, runs of fewer than 2^32
                                  clone-sweeps use a placement only if one already exists, and
                                  longer runs build one with a search sized to the run. */

@@ -494,7 +494,7 @@ uint32_t place_layout(uint32_t B, uint32_t CW) { return B < 8 ? B | CW << 8 : 0u
 // (XS_PLACE_ROWS) gets the full effort. Batches build their instances' schedules on several host
 // threads at once, which divides the cost (host_threads()).
 constexpr uint64_t kPlaceMinWork = 1ull << 32;
-constexpr int kPlaceEffort = 800;
+constexpr int kPlaceEffort = 1600;
 
 // Host threads that build the schedules of a batch.
 uint32_t host_threads() {
