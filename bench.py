@@ -48,10 +48,13 @@ ALGO_OPS_PER_UPDATE = 7 / 32 + (10 * (2 + 2) + 8) / 256
 ALGO_OPS_PER_UPDATE_W0 = 9 / 32 + (10 * (2 + 2) + 16) / 256
 
 # Headline workloads: (instances, N, clones, default sweeps per step, stop at first ground
-# state, instance-seed config number).
+# state, instance-seed config number, default sweeps per chunk). A budget run checks nothing
+# between chunks, so its chunks are long (each chunk boundary stages the tiles out and in);
+# a run to the first ground state keeps short chunks, which set how soon a hit is seen.
 HEADLINES = {
-    "steady": dict(count=16, n=1024, clones=1 << 20, budget=10000, stop=False, config=3),
-    "batched": dict(count=64, n=256, clones=65536, budget=50000, stop=True, config=2),
+    "steady": dict(count=16, n=1024, clones=1 << 20, budget=10000, stop=False, config=3,
+                   chunk=1000),
+    "batched": dict(count=64, n=256, clones=65536, budget=50000, stop=True, config=2, chunk=100),
 }
 # HBM counter records per headline workload (FETCH_SIZE / WRITE_SIZE of the sweep kernel).
 TRAFFIC_RECORDS = {"steady": "qg_queue_run_n1024x16_hbm_counters.json",
@@ -74,7 +77,8 @@ def parse():
                     help="sweep budget per instance and step (default: 10^4 for steady, uneven "
                          "and serve; 5*10^4 for batched, whose first ground states at N=256 take "
                          "far longer, so most instances end at the budget)")
-    ap.add_argument("--chunk", type=int, default=100)
+    ap.add_argument("--chunk", type=int, default=None,
+                    help="sweeps per chunk (default: 1000 for the steady workload, else 100)")
     ap.add_argument("--per-chunk", action="store_true",
                     help="launch every chunk separately (XS_PER_CHUNK) instead of the persistent "
                          "work-queue launch (speed only)")
@@ -151,7 +155,7 @@ def measured_traffic(args, wl, dims, updates_per_launch, kernel):
     path = os.path.join(ROOT, "profiles", TRAFFIC_RECORDS[wl])
     H = HEADLINES[wl]
     if (not os.path.exists(path) or dims != (H["count"], H["n"], H["clones"]) or
-            args.chunk != 100 or args.accept_thr0 or args.cap != 32):
+            (args.chunk or H["chunk"]) != H["chunk"] or args.accept_thr0 or args.cap != 32):
         return None
     rec = json.load(open(path))
     if kernel_source_sha256() != rec.get("kernel_source_sha256") or rec.get("kernel") != kernel:
@@ -214,7 +218,7 @@ def workload_uneven(args, xorsat, torch):
     def cfg(k):
         return xorsat.make_config(n_clones=sizes[k][1], seed=run_seed(4, k), instance_id=k,
                                   accept_thr=THR_PAPER, max_sweeps=budget, stop_on_first=True,
-                                  chunk_sweeps=args.chunk, per_chunk=args.per_chunk)
+                                  chunk_sweeps=args.chunk or 100, per_chunk=args.per_chunk)
 
     print(f"# uneven: {len(sizes)} instances, budget {budget}, parts {sorted(parts)}",
           file=sys.stderr, flush=True)
@@ -310,7 +314,7 @@ def workload_serve(args, xorsat, torch):
     def cfg(k):
         return xorsat.make_config(n_clones=16384, seed=run_seed(5, k), instance_id=k,
                                   accept_thr=THR_PAPER, max_sweeps=budget, stop_on_first=True,
-                                  chunk_sweeps=args.chunk)
+                                  chunk_sweeps=args.chunk or 100)
 
     srv = xorsat.Server(hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)))
     tickets = {}
@@ -636,7 +640,7 @@ def workload_single(args, xorsat, torch):
     def cfg(r):
         return xorsat.make_config(n_clones=ncl, seed=run_seed(1, 0) + r, instance_id=0,
                                   accept_thr=THR_PAPER, max_sweeps=100000, stop_on_first=True,
-                                  chunk_sweeps=args.chunk)
+                                  chunk_sweeps=args.chunk or 100)
 
     xorsat.run(h, cfg(0))  # warm
     torch.cuda.synchronize()
@@ -703,7 +707,7 @@ def tts_block(args, xorsat, torch):
     def cfg(r):
         return xorsat.make_config(n_clones=ncl, seed=run_seed(1, 0) + r, instance_id=0,
                                   accept_thr=THR_PAPER, max_sweeps=100000, stop_on_first=True,
-                                  chunk_sweeps=args.chunk)
+                                  chunk_sweeps=args.chunk or 100)
 
     xorsat.run(h, cfg(0))  # warm
     torch.cuda.synchronize()
@@ -776,7 +780,7 @@ def headline(args, xorsat, torch):
     budget = args.budget if args.budget is not None else H["budget"]
     stop = H["stop"] and args.accept_thr0 == 0
     place = args.place_rows or wl in ("steady", "batched")
-    chunk = args.chunk or 100
+    chunk = args.chunk or H["chunk"]
     insts = [planted_instance(n, gen_seed(H["config"], k)) for k in range(count)]
     handles = [xorsat.Instance(i.tri, i.J, colour_cap=args.cap) for i in insts]
 

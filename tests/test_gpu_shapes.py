@@ -172,6 +172,42 @@ def test_steady_n1024_shape_over_chunks():
         check_instance(insts[k], hs[k], cfgs[k], out, starts[k], picks[k], f"instance {k}")
 
 
+def test_steady_n1024_long_chunks():
+    """The steady-state workload as the benchmark times it: two instances of N = 1024 with 2^20
+    clones in one batch, the library's default shape with the rows placed, 2,000 sweeps in
+    chunks of 1,000 (each a cross-sweep body run over its 1,000 sweeps). The outputs equal those
+    of chunks of 100 bit for bit, and sampled clone groups equal the oracle from the same
+    starts."""
+    torch = _torch()
+    n, nc = 1024, 1 << 20
+    rng = np.random.default_rng(2024)
+    insts, hs, starts = [], [], []
+    for k in range(2):
+        inst = planted_instance(n, 3_000_000 + k)
+        insts.append(inst)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        starts.append(near_solution_state(inst, nc, rng, {})[0])
+
+    def run(chunk):
+        cfgs = [xorsat.make_config(n_clones=nc, seed=0x5C + k, instance_id=k,
+                                   accept_thr=THR_PAPER, max_sweeps=2000, resume=True,
+                                   stop_on_first=False, chunk_sweeps=chunk, place_rows=True)
+                for k in range(2)]
+        return cfgs, xorsat.run_batch(hs, cfgs,
+                                      states=[torch.from_numpy(s).cuda() for s in starts])
+
+    cfgs, long_runs = run(1000)
+    _, short_runs = run(100)
+    for k in range(2):
+        a, b = long_runs[k], short_runs[k]
+        assert (a.tile_blocks, a.wg_threads, a.col_bytes, a.rec_global) == STEADY_SHAPE
+        assert a.end_sweep == b.end_sweep == 2000
+        assert torch.equal(a.state, b.state), f"instance {k}"
+        assert torch.equal(a.first_hit, b.first_hit) and torch.equal(a.energy, b.energy)
+        check_instance(insts[k], hs[k], cfgs[k], a, starts[k], [3, 16001, nc // 32 - 1],
+                       f"instance {k}")
+
+
 def test_uneven_batch_against_oracle_and_alone():
     """Twenty instances of the uneven workload's family (N uniform on {32, ..., 1024}, clones
     from 4,096 to 65,536), half run to the first ground state and half to a budget, in one
