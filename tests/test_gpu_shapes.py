@@ -141,6 +141,51 @@ def test_batched_n256_timed_shape_resumed_near_solution(shape):
         check_instance(insts[k], hs[k], cfgs[k], out, starts[k], picks[k], f"instance {k}")
 
 
+def test_batched_n256_long_chunks_stop_on_first():
+    """The batched N = 256 workload as the benchmark times it: its launch shape (four-block
+    tiles of 256 threads, 16-byte columns, records in global memory, rows placed), runs to the
+    first ground state in chunks of 500 sweeps, from near-solution starts. Each run ends at the
+    end of the chunk that holds its first hit, with the same TTS and winner as in chunks of 50
+    (the first hits up to that sweep agree clone for clone), and sampled clone groups equal the
+    oracle."""
+    torch = _torch()
+    n, nc = 256, 65536
+    rng = np.random.default_rng(2561)
+    insts, hs, starts, picks = [], [], [], []
+    for k in range(2):
+        inst = planted_instance(n, 2_000_000 + k)
+        insts.append(inst)
+        hs.append(xorsat.Instance(inst.tri, inst.J))
+        gf = {64 * (3 + 4 * t) + 5 * t + 1: f for t, f in enumerate((4, 16, 32, 48))}
+        st, _ = near_solution_state(inst, nc, rng, gf)
+        starts.append(st)
+        picks.append(sorted(gf) + [64 * 30 + 63])
+
+    def run(chunk):
+        cfgs = [xorsat.make_config(n_clones=nc, seed=0xB5 + k, instance_id=k,
+                                   accept_thr=THR_PAPER, max_sweeps=1000, resume=True,
+                                   stop_on_first=True, chunk_sweeps=chunk, tile_blocks=4,
+                                   wg_threads=256, col_bytes=16, rec_global=1, place_rows=True)
+                for k in range(2)]
+        return cfgs, xorsat.run_batch(hs, cfgs,
+                                      states=[torch.from_numpy(s.copy()).cuda() for s in starts])
+
+    cfgs, long_runs = run(500)
+    _, short_runs = run(50)
+    for k in range(2):
+        a, b = long_runs[k], short_runs[k]
+        assert (a.tile_blocks, a.wg_threads, a.col_bytes, a.rec_global) == (4, 256, 16, 1)
+        assert 0 <= a.tts_sweeps < 500, "no hit in the first long chunk"
+        assert a.end_sweep == 500 and b.end_sweep == 50 * (b.tts_sweeps // 50 + 1)
+        assert (a.tts_sweeps, a.winner_clone) == (b.tts_sweeps, b.winner_clone)
+        fa, fb = a.first_hit.cpu().numpy(), b.first_hit.cpu().numpy()
+        upto = (fb >= 0) & (fb < b.end_sweep)
+        assert np.array_equal(fa[upto], fb[upto]), f"instance {k}"
+        early = (fa >= 0) & (fa < b.end_sweep)
+        assert np.array_equal(fa[early], fb[early]), f"instance {k}"
+        check_instance(insts[k], hs[k], cfgs[k], a, starts[k], picks[k], f"instance {k}")
+
+
 def test_steady_n1024_shape_over_chunks():
     """The steady-state workload's kernel at its real size: two instances of N = 1024 with 2^20
     clones in one batch, the library's default shape with the LDS rows placed, 30 sweeps in
